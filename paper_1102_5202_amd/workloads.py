@@ -1,0 +1,297 @@
+"""Seeded synthetic initial data (primitive variables) for the standard workloads.
+
+This module holds no arithmetic of the numerical scheme: it only draws seeded
+random numbers and writes primitive fields
+P = (rho, p, u~x, u~y, u~z, Bx, By, Bz, Phi) as float64 arrays ``[9, nz, ny, nx]``
+(structure of arrays, x fastest).  Both the GPU path and the CPU oracle consume
+exactly these arrays.  Where a recipe is stated in terms of the spacetime (the
+velocity of a rigidly rotating blob, a densitised magnetic field) the given
+metric functions of that spacetime are evaluated here, as part of the recipe.
+
+The paper's own workloads (rotating neutron stars imported from the rns code,
+Thor reference runs) are not available; these synthetic inputs stand in for
+them with the shapes, sizes and value ranges of the paper's tests.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 11025202
+
+FLAT, ISO_SCHW = 0, 1
+SOFT_SQRT, SOFT_MAX = 0, 1
+PERIODIC, OUTFLOW = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    P: np.ndarray                  # [9, nz, ny, nx] float64 primitives
+    n: tuple
+    lo: tuple
+    hi: tuple
+    bc: tuple
+    gamma: float
+    rk_order: int
+    dt: float
+    nsteps: int
+    metric: int = FLAT
+    M: float = 0.0
+    soft: int = SOFT_SQRT
+    r_min: float = 1.0
+    rho_atm: float = 1e-12
+    p_atm: float = 1e-12
+    c_h: float = 1.0
+    kappa: float = 1.0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ncell(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    def problem_kwargs(self) -> dict:
+        """Keyword arguments shared by the solver and the oracle descriptions."""
+        return dict(n=tuple(self.n), lo=tuple(self.lo), hi=tuple(self.hi), bc=tuple(self.bc),
+                    metric=self.metric, M=self.M, soft=self.soft, r_min=self.r_min,
+                    gamma=self.gamma, rk_order=self.rk_order, c_h=self.c_h, kappa=self.kappa,
+                    rho_atm=self.rho_atm, p_atm=self.p_atm)
+
+
+def rng_for(config: int, k: int = 0) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + 1000 * config + k)
+
+
+def centres(n, lo, hi):
+    """Cell-centre coordinate arrays (z, y, x order broadcastable to [nz, ny, nx])."""
+    xs = [lo[d] + (np.arange(n[d]) + 0.5) * (hi[d] - lo[d]) / n[d] for d in range(3)]
+    return (xs[0][None, None, :], xs[1][None, :, None], xs[2][:, None, None])
+
+
+def _curl_central(A, dx):
+    """Central-difference curl of a vector potential sampled on an extended grid.
+
+    ``A`` has shape [3, nz+2, ny+2, nx+2] (one extra layer on each side); the
+    result has shape [3, nz, ny, nx] and its central-difference divergence
+    vanishes identically (up to rounding).
+    """
+    def d(comp, axis):
+        a = A[comp]
+        h = dx[axis]
+        if axis == 0:
+            return (a[1:-1, 1:-1, 2:] - a[1:-1, 1:-1, :-2]) / (2 * h)
+        if axis == 1:
+            return (a[1:-1, 2:, 1:-1] - a[1:-1, :-2, 1:-1]) / (2 * h)
+        return (a[2:, 1:-1, 1:-1] - a[:-2, 1:-1, 1:-1]) / (2 * h)
+    return np.stack([d(2, 1) - d(1, 2), d(0, 2) - d(2, 0), d(1, 0) - d(0, 1)])
+
+
+def _extended_centres(n, lo, hi):
+    dx = [(hi[d] - lo[d]) / n[d] for d in range(3)]
+    xs = [lo[d] + (np.arange(-1, n[d] + 1) + 0.5) * dx[d] for d in range(3)]
+    return (xs[0][None, None, :], xs[1][None, :, None], xs[2][:, None, None]), dx
+
+
+def _modes(rng, count, kmax):
+    """Draw `count` integer wave vectors with 0 < |k|_2 <= kmax."""
+    ks = []
+    while len(ks) < count:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        nk = float(np.sqrt((k * k).sum()))
+        if 0.0 < nk <= kmax:
+            ks.append(k)
+    return np.array(ks)
+
+
+# -----------------------------------------------------------------------------
+# 1D magnetised Riemann problems (seeded states)
+
+def riemann_states(rng):
+    """Left/right states: rho U[0.1,1], p U[0.01,1], v = 0, Bx U[0.3,1] shared,
+    By, Bz U[-1,1]; Phi = 0.  Draw order: rhoL, rhoR, pL, pR, Bx, ByL, BzL, ByR, BzR."""
+    rhoL, rhoR = rng.uniform(0.1, 1.0, 2)
+    pL, pR = rng.uniform(0.01, 1.0, 2)
+    bx = rng.uniform(0.3, 1.0)
+    byL, bzL, byR, bzR = rng.uniform(-1.0, 1.0, 4)
+    L = np.array([rhoL, pL, 0.0, 0.0, 0.0, bx, byL, bzL, 0.0])
+    R = np.array([rhoR, pR, 0.0, 0.0, 0.0, bx, byR, bzR, 0.0])
+    return L, R
+
+
+def riemann_1d(L, R, n=400, axis=0, x0=0.5):
+    """A 1D Riemann problem on [0,1] along `axis` (other axes have one cell)."""
+    shape = [1, 1, 1]
+    shape[axis] = n
+    P = np.empty((9, shape[2], shape[1], shape[0]))
+    x = (np.arange(n) + 0.5) / n
+    left = x < x0
+    for v in range(9):
+        P[v] = np.where(left, L[v], R[v]).reshape((shape[2], shape[1], shape[0]))
+    # rotate vector components so that the problem's "x" is along `axis`
+    if axis != 0:
+        perm = [0, 1, 2]
+        perm[0], perm[axis] = perm[axis], perm[0]
+        P[2:5] = P[[2 + perm[0], 2 + perm[1], 2 + perm[2]]]
+        P[5:8] = P[[5 + perm[0], 5 + perm[1], 5 + perm[2]]]
+    return P
+
+
+def config1(k: int = 0, n: int = 400, axis: int = 0) -> Workload:
+    """1D special-relativistic MHD Riemann problem, flat metric, n cells on [0,1],
+    Gamma = 5/3, outflow, CFL 0.4 to t = 0.4 (dt = 0.4/n), SSP-RK3."""
+    L, R = riemann_states(rng_for(1, k))
+    P = riemann_1d(L, R, n=n, axis=axis)
+    nn = [1, 1, 1]
+    nn[axis] = n
+    return Workload(name="riemann1d_%d" % n, P=P, n=tuple(nn), lo=(0.0, 0.0, 0.0),
+                    hi=(1.0, 1.0, 1.0), bc=(OUTFLOW,) * 3, gamma=5.0 / 3.0, rk_order=3,
+                    dt=0.4 / n, nsteps=n, extra={"L": L, "R": R})
+
+
+def sod(n=400, axis=0, magnetised=False) -> Workload:
+    """Sod test of section 5.1 (Gamma = 5/3; rho_L = 1, p_L = 1, rho_R = 0.125,
+    p_R = 0.1, velocities 0); with ``magnetised`` the first Balsara test of the
+    same section (Bx = 0.5, By = +1 / -1)."""
+    L = np.array([1.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    R = np.array([0.125, 0.1, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    if magnetised:
+        L[5], L[6] = 0.5, 1.0
+        R[5], R[6] = 0.5, -1.0
+    P = riemann_1d(L, R, n=n, axis=axis)
+    nn = [1, 1, 1]
+    nn[axis] = n
+    return Workload(name="balsara1" if magnetised else "sod", P=P, n=tuple(nn),
+                    lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(OUTFLOW,) * 3,
+                    gamma=5.0 / 3.0, rk_order=3, dt=0.4 / n, nsteps=n, extra={"L": L, "R": R})
+
+
+# -----------------------------------------------------------------------------
+# 3D periodic flat box
+
+def config2(n: int = 128, k: int = 0, nsteps: int = 100, config_id: int = 2) -> Workload:
+    """Periodic flat box [0,1]^3, Gamma = 4/3:
+    rho = 1 + 0.1 sum_m a_m cos(2 pi k_m.x + phi_m) over 16 modes (|k| <= 4,
+    sum |a_m| = 1); p = 0.1; v = 0.3 V / max|V| with V from 16 modes per
+    component, u~ = W v; B = (0.1, 0.05, 0) + central curl of a 16-mode vector
+    potential scaled to max|dB| = 0.01; Phi = 0.  SSP-RK2, dt = 0.4/n."""
+    rng = rng_for(config_id, k)
+    nn = (n, n, n)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    X = centres(nn, lo, hi)
+    P = np.zeros((9, n, n, n))
+
+    def field(count=16, kmax=4):
+        ks = _modes(rng, count, kmax)
+        ph = rng.uniform(0.0, 2 * np.pi, count)
+        am = rng.uniform(-1.0, 1.0, count)
+        return ks, ph, am
+
+    def evaluate(ks, ph, am, Xs):
+        f = 0.0
+        for m in range(len(am)):
+            f = f + am[m] * np.cos(2 * np.pi * (ks[m, 0] * Xs[0] + ks[m, 1] * Xs[1]
+                                                + ks[m, 2] * Xs[2]) + ph[m])
+        return f
+
+    ks, ph, am = field()
+    am = am / np.abs(am).sum()
+    P[0] = 1.0 + 0.1 * evaluate(ks, ph, am, X)
+    P[1] = 0.1
+    V = np.stack([np.broadcast_to(evaluate(*field(), X), (n, n, n)) for _ in range(3)])
+    vmag = np.sqrt((V * V).sum(axis=0))
+    v = 0.3 * V / vmag.max()
+    W = 1.0 / np.sqrt(1.0 - (v * v).sum(axis=0))
+    P[2:5] = W * v
+    Xe, dx = _extended_centres(nn, lo, hi)
+    A = np.stack([np.broadcast_to(evaluate(*field(), Xe), (n + 2, n + 2, n + 2))
+                  for _ in range(3)])
+    dB = _curl_central(A, dx)
+    dB *= 0.01 / np.abs(dB).max()
+    P[5] = 0.1 + dB[0]
+    P[6] = 0.05 + dB[1]
+    P[7] = dB[2]
+    P[8] = 0.0
+    return Workload(name="periodic_flat_%d" % n, P=P, n=nn, lo=lo, hi=hi, bc=(PERIODIC,) * 3,
+                    gamma=4.0 / 3.0, rk_order=2, dt=0.4 / n, nsteps=nsteps)
+
+
+# -----------------------------------------------------------------------------
+# 3D curved static spacetime: rotating Gaussian blob
+
+def _iso_schw(X, M=1.0, r_min=1.0, soft=SOFT_SQRT):
+    """Lapse and conformal factor^4 of the isotropic Schwarzschild metric with
+    the radius softened near the origin (the given spacetime of the workload)."""
+    r = np.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2)
+    rs = np.sqrt(r * r + r_min * r_min) if soft == SOFT_SQRT else np.maximum(r, r_min)
+    h = M / (2.0 * rs)
+    return (1.0 - h) / (1.0 + h), (1.0 + h) ** 4
+
+
+def config3(n=192, k: int = 0, nsteps: int = 200, half: float = 20.0, noise: bool = True,
+            rho_c: float = 1e-3, width: float = 4.0, omega: float = 0.02, K: float = 100.0,
+            beta_plasma: float = 1000.0, rho_atm: float = 1e-10, M: float = 1.0) -> Workload:
+    """Static curved spacetime on [-half, half]^3 (G = c = M = 1), isotropic
+    Schwarzschild with r_s = sqrt(r^2 + 1); Gamma = 2 polytropic data p = K rho^2
+    (K = 100); rho = max(rho_c exp(-r^2/w^2)(1 + 0.01 xi), rho_atm) with xi
+    U[-1,1] per cell; rigid rotation with coordinate angular velocity Omega
+    about z; poloidal field from A = A_b rho_c exp(-r^2/w^2)(-y, x, 0) through a
+    central curl of the densitised field, scaled so that max(B^2/2) =
+    max(p)/beta_plasma; outflow; SSP-RK3, dt = 0.4 dx.  ``n`` may be a 3-tuple."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+    rng = rng_for(3, k)
+    lo, hi = (-half,) * 3, (half,) * 3
+    X = centres(nn, lo, hi)
+    shape = (nn[2], nn[1], nn[0])
+    P = np.zeros((9,) + shape)
+    r2 = X[0] ** 2 + X[1] ** 2 + X[2] ** 2
+    xi = rng.uniform(-1.0, 1.0, shape) if noise else np.zeros(shape)
+    rho = np.maximum(rho_c * np.exp(-r2 / width ** 2) * (1.0 + 0.01 * xi), rho_atm)
+    P[0] = rho
+    P[1] = K * rho ** 2
+    alpha, psi4 = _iso_schw(X, M=M)
+    # coordinate velocity u^i/u^t = Omega (-y, x, 0); Eulerian V = v/alpha
+    vx = np.broadcast_to(-omega * X[1] / alpha, shape)
+    vy = np.broadcast_to(omega * X[0] / alpha, shape)
+    W = 1.0 / np.sqrt(1.0 - psi4 * (vx ** 2 + vy ** 2))
+    P[2] = W * vx
+    P[3] = W * vy
+    P[4] = 0.0
+    # densitised poloidal field Bd = curl A;  B = Bd / sqrt(-g), sqrt(-g) = alpha psi^6
+    Xe, dx = _extended_centres(nn, lo, hi)
+    env = rho_c * np.exp(-(Xe[0] ** 2 + Xe[1] ** 2 + Xe[2] ** 2) / width ** 2)
+    eshape = (nn[2] + 2, nn[1] + 2, nn[0] + 2)
+    A = np.stack([np.broadcast_to(-Xe[1] * env, eshape), np.broadcast_to(Xe[0] * env, eshape),
+                  np.zeros(eshape)])
+    Bd = _curl_central(A, dx)
+    sqrtmg = alpha * psi4 ** 1.5
+    B = Bd / sqrtmg
+    bmag2 = psi4 * (B * B).sum(axis=0)
+    scale = np.sqrt((P[1].max() / beta_plasma) / (0.5 * bmag2.max()))
+    P[5:8] = B * scale
+    P[8] = 0.0
+    dxmin = min(dx)
+    return Workload(name="curved_blob_%dx%dx%d" % nn, P=P, n=nn, lo=lo, hi=hi,
+                    bc=(OUTFLOW,) * 3, gamma=2.0, rk_order=3, dt=0.4 * dxmin, nsteps=nsteps,
+                    metric=ISO_SCHW, M=M, soft=SOFT_SQRT, r_min=1.0, rho_atm=rho_atm,
+                    p_atm=K * rho_atm ** 2, extra={"K": K})
+
+
+# -----------------------------------------------------------------------------
+# smooth advected pulse (convergence test input)
+
+def pulse_1d(n: int, v: float = 0.5, amp: float = 0.5, axis: int = 0, p: float = 1.0,
+             bx: float = 0.3, gamma: float = 5.0 / 3.0) -> Workload:
+    """rho = 1 + amp sin^2(pi x) on periodic [0,1], uniform p and velocity v along
+    the axis, uniform field along the axis.  The exact solution is rho(x - v t)."""
+    nn = [1, 1, 1]
+    nn[axis] = n
+    x = (np.arange(n) + 0.5) / n
+    P = np.zeros((9, nn[2], nn[1], nn[0]))
+    W = 1.0 / np.sqrt(1.0 - v * v)
+    P[0] = (1.0 + amp * np.sin(np.pi * x) ** 2).reshape(nn[2], nn[1], nn[0])
+    P[1] = p
+    P[2 + axis] = W * v
+    P[5 + axis] = bx
+    return Workload(name="pulse_%d" % n, P=P, n=tuple(nn), lo=(0.0,) * 3, hi=(1.0,) * 3,
+                    bc=(PERIODIC,) * 3, gamma=gamma, rk_order=3, dt=0.4 / n, nsteps=0)
