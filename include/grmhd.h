@@ -1,0 +1,196 @@
+/*
+ * grmhd.h -- C ABI of the MI355X (gfx950) GRMHD substep library, libgrmhd.so.
+ *
+ * The library advances the equations of general-relativistic ideal MHD in a
+ * fixed, given static spacetime (the Cowling setting of section 2.1 of
+ * Zink, "HORIZON: Accelerated General Relativistic Magnetohydrodynamics",
+ * arXiv:1102.5202) with the finite-volume method of section 2.2 and the scheme
+ * choices of section 3.2: TVD reconstruction with the MC limiter, HLLE face
+ * fluxes, the metric source terms of eq. 2, Newton-Raphson recovery of the
+ * primitive variables, Runge-Kutta time integration, and hyperbolic
+ * divergence cleaning of the constraint d_i(sqrt(-g) B^i) = 0.  Every step of
+ * that update runs in hand-written HIP kernels on the device; the host only
+ * enqueues launches.
+ *
+ * Variables (9 per cell, structure of arrays):
+ *   primitives  P = (rho, p, u~x, u~y, u~z, Bx, By, Bz, Phi)
+ *     u~^i = u^i + W beta^i / alpha  (the primitive velocity of the footnote
+ *     in section 5.2), B^i = *F^{it} (eq. 2), Phi the cleaning scalar;
+ *   conserved   U = (D, tau, Sx, Sy, Sz, Bdx, Bdy, Bdz, Phi)
+ *     D = sqrt(-g) rho u^t,  tau = -sqrt(-g)(T^t_t + rho u^t),
+ *     S_j = sqrt(-g) T^t_j,  Bd^j = sqrt(-g) B^j   (the conserved set of eq. 2,
+ *     with the energy row written relative to the rest-mass row).
+ *
+ * Array layout: every P, U or R argument is a DEVICE pointer to 9*nz*ny*nx
+ * doubles, index ((v*nz + k)*ny + j)*nx + i, interior cells only (no ghost
+ * zones), 8-byte aligned.  Cell (i,j,k) has centre
+ * lo + (i + 1/2, j + 1/2, k + 1/2) * (hi - lo)/n.  An axis with n = 1 is
+ * switched off (no fluxes along it), which gives 1D and 2D problems.
+ *
+ * Ownership: the caller owns every buffer, the workspace and the stream.  The
+ * library never allocates or frees device memory; all its scratch storage
+ * lives in the caller's workspace.  Buffers must stay valid until the work
+ * enqueued on the stream has completed.  One context serves one stream; a
+ * context is not thread-safe.
+ *
+ * Errors: every call returns 0 on success or a negative grmhd_error code
+ * (grmhd_strerror() describes it).  Enqueuing calls (cons, step, prim, rhs)
+ * are asynchronous and never synchronise; a HIP launch error is reported by
+ * the call that enqueued it.  Physical failures of the recovery (no physical
+ * root, atmosphere resets, pressure floors) are not errors: they are counted
+ * on the device and read with grmhd_status(), which synchronises.
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRMHD_NVAR 9
+
+typedef enum {
+    GRMHD_OK = 0,
+    GRMHD_ERR_ARG = -1,        /* invalid argument (null pointer, bad size or option) */
+    GRMHD_ERR_WORKSPACE = -2,  /* workspace missing or smaller than grmhd_workspace_bytes() */
+    GRMHD_ERR_HIP = -3,        /* a HIP runtime call or kernel launch failed */
+    GRMHD_ERR_STATE = -4       /* call out of order (e.g. step before cons/prim) */
+} grmhd_error;
+
+typedef enum { GRMHD_METRIC_FLAT = 0, GRMHD_METRIC_ISO_SCHW = 1 } grmhd_metric_kind;
+typedef enum { GRMHD_SOFT_SQRT = 0, GRMHD_SOFT_MAX = 1 } grmhd_soft_kind;
+typedef enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1 } grmhd_bc_kind;
+typedef enum { GRMHD_EOS_IDEAL = 0 } grmhd_eos_kind;
+typedef enum { GRMHD_FP64 = 0 } grmhd_precision;
+
+/* The fixed, given spacetime (section 2.1).  FLAT is Minkowski space.
+ * ISO_SCHW is the Schwarzschild metric in isotropic coordinates, static and
+ * without shift: alpha = (1 - M/(2 r_s))/(1 + M/(2 r_s)), gamma_ij = psi^4
+ * delta_ij, psi = 1 + M/(2 r_s), with the radius softened near the origin:
+ * r_s = sqrt(r^2 + r_min^2) (SQRT) or max(r, r_min) (MAX).  Requires
+ * r_min > M/2 so that alpha > 0 everywhere. */
+typedef struct {
+    int kind;       /* grmhd_metric_kind */
+    int soft;       /* grmhd_soft_kind   */
+    double M;
+    double r_min;
+} grmhd_metric;
+
+/* Cartesian uniform mesh (section 3.2).  n[d] >= 1 cells on [lo[d], hi[d]];
+ * active axes (n > 1) need n >= 2.  bc[d] applies on both ends of axis d:
+ * PERIODIC, or OUTFLOW (two zero-gradient ghost cells of the primitives). */
+typedef struct {
+    int n[3];
+    double lo[3];
+    double hi[3];
+    int bc[3];
+} grmhd_grid;
+
+/* Ideal-gas equation of state p = (gamma - 1) rho eps (section 5.1). */
+typedef struct {
+    int kind;       /* grmhd_eos_kind (IDEAL only) */
+    double gamma;   /* adiabatic index, 1 < gamma <= 2 */
+    double K;       /* polytropic constant; used only to derive p_atm = K rho_atm^gamma
+                       when opts.p_atm < 0 */
+} grmhd_eos;
+
+/* Scheme options and the caller's workspace. */
+typedef struct {
+    int rk_order;          /* 2 (SSP-RK2) or 3 (SSP-RK3, the order of section 3.2) */
+    int precision;         /* grmhd_precision (FP64 only) */
+    double c_h;            /* cleaning speed, > 0 (1 if 0 is given) */
+    double kappa;          /* cleaning damping rate, >= 0 */
+    double rho_atm;        /* atmosphere density (absolute), > 0 */
+    double p_atm;          /* atmosphere and floor pressure; < 0: K rho_atm^gamma */
+    double newton_tol;     /* relative step tolerance of the recovery (1e-12 if 0) */
+    int newton_maxit;      /* iteration cap of the recovery (50 if 0) */
+    int timing;            /* nonzero: time every kernel launch with HIP events */
+    void *workspace;       /* device memory, >= grmhd_workspace_bytes(), 256-byte aligned */
+    size_t workspace_bytes;
+} grmhd_opts;
+
+/* Device-side counters accumulated since the last reset. */
+typedef struct {
+    long long c2p_fail;     /* cells where the recovery found no physical root */
+    long long atm_hits;     /* cells reset to the atmosphere */
+    long long p_floor_hits; /* cells whose pressure was raised to p_atm */
+    long long fallback_1d;  /* cells the 2D Newton iteration handed to the bracketed 1D solve */
+    int max_newton_it;      /* most 2D Newton iterations any cell needed */
+} grmhd_stats;
+
+/* Kernel classes reported by grmhd_timing(). */
+typedef enum {
+    GRMHD_K_BC = 0,       /* ghost-zone fill of the primitive cache          */
+    GRMHD_K_FLUX_X = 1,   /* reconstruction + face physics + HLLE, x faces   */
+    GRMHD_K_FLUX_Y = 2,
+    GRMHD_K_FLUX_Z = 3,
+    GRMHD_K_UPDATE = 4,   /* flux divergence + sources + RK + recovery       */
+    GRMHD_K_CONS = 5,     /* primitive -> conserved                          */
+    GRMHD_K_PRIM = 6,     /* conserved -> primitive                          */
+    GRMHD_K_RHS = 7,      /* flux divergence + sources only                  */
+    GRMHD_K_COUNT = 8
+} grmhd_kernel;
+
+typedef struct grmhd_ctx grmhd_ctx;
+
+/* Bytes of device workspace a context needs for this grid and these options.
+ * Returns 0 for an invalid grid. */
+size_t grmhd_workspace_bytes(const grmhd_grid *grid, const grmhd_opts *opts);
+
+/* Create a context (host-only; no device work, no allocation of device
+ * memory).  The workspace in opts is carved into the ghosted primitive cache,
+ * the stage buffer, the face-flux buffers and the counters.  *ctx is set on
+ * success and must be released with grmhd_free().  The stream is the null
+ * stream until grmhd_set_stream() is called. */
+int grmhd_init(grmhd_ctx **ctx, const grmhd_metric *metric, const grmhd_grid *grid,
+               const grmhd_eos *eos, const grmhd_opts *opts);
+
+/* Set the HIP stream (a hipStream_t passed as void*) all later work is
+ * enqueued on. */
+int grmhd_set_stream(grmhd_ctx *ctx, void *stream);
+
+/* Conserved variables from primitives, an algebraic map (section 2.2: the
+ * evolution starts by converting the initial primitives).  P is read, U is
+ * written (both device, layout above).  Also loads P into the context's
+ * primitive cache, which seeds the next grmhd_step(). */
+int grmhd_cons(grmhd_ctx *ctx, const double *P, double *U);
+
+/* One full Runge-Kutta step of size dt (section 2.2: reconstruction, HLLE
+ * fluxes, flux differences plus sources, Newton recovery, once per substep;
+ * SSP-RK3 or SSP-RK2 per opts.rk_order), in place on the device array U.  The
+ * primitives of U must be in the context's cache (set by grmhd_cons,
+ * grmhd_prim or the previous grmhd_step).  Asynchronous; graph-capturable. */
+int grmhd_step(grmhd_ctx *ctx, double *U, double dt);
+
+/* Primitives from conserved variables by Newton-Raphson (section 2.2: the
+ * inversion is not algebraic), followed by the atmosphere and floor policy.
+ * U is read (never modified), P written; the context's cache, which provides
+ * the Newton initial guess, is refreshed with P. */
+int grmhd_prim(grmhd_ctx *ctx, const double *U, double *P);
+
+/* Right-hand side L(P) = -sum_d (F_d(i+1/2) - F_d(i-1/2))/dx_d + s(P) of one
+ * substep (compact form eq. 3) for the primitives P, written to R (device).
+ * Loads P into the context's primitive cache, as grmhd_cons does. */
+int grmhd_rhs(grmhd_ctx *ctx, const double *P, double *R);
+
+/* Copy the device counters to *st (synchronises the stream); reset them to 0
+ * afterwards when reset != 0. */
+int grmhd_status(grmhd_ctx *ctx, grmhd_stats *st, int reset);
+
+/* With opts.timing set: synchronise, then report the summed duration (ms) and
+ * the number of launches of each kernel class since the last reset, in arrays
+ * of GRMHD_K_COUNT entries (either may be NULL). */
+int grmhd_timing(grmhd_ctx *ctx, double *ms, long long *launches, int reset);
+
+/* Release the context (host memory and HIP events only). */
+int grmhd_free(grmhd_ctx *ctx);
+
+/* Static description of an error code. */
+const char *grmhd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -259,3 +259,27 @@ def point_face_flux(qL, qR, gamma, dir, c_h=1.0, x=0.0, y=0.0, z=0.0, **mk):
 
 def mc_slope(qm, q0, qp) -> float:
     return float(lib().orc_mc_slope(qm, q0, qp))
+
+
+# ---- parity metric (test infrastructure) ----------------------------------------
+
+GROUPS = ((0,), (1,), (2, 3, 4), (5, 6, 7), (8,))
+
+
+def parity_error(U, U_ref):
+    """Relative L1 distance per conserved variable, sum|U - U_ref| / sum|U_ref|
+    over all cells.  Components of a vector (momentum S, densitised field Bd)
+    are normalised by the L1 norm of the largest component of that vector, so
+    that a component which vanishes analytically (rounding noise on both
+    sides) is judged against the vector's size.  A variable whose whole group
+    is zero in the reference reports the absolute L1 distance."""
+    U = np.asarray(U).reshape(9, -1)
+    R = np.asarray(U_ref).reshape(9, -1)
+    num = np.abs(U - R).sum(axis=1)
+    l1 = np.abs(R).sum(axis=1)
+    out = np.empty(9)
+    for grp in GROUPS:
+        den = max(l1[v] for v in grp)
+        for v in grp:
+            out[v] = num[v] / den if den > 0 else num[v]
+    return out

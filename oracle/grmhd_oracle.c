@@ -360,9 +360,11 @@ static double c2p_f(const c2p_in *c, double Wc, double *df)
     return -0.5 * c->Bc2 * (1.0 + v2) + c->QB2 / (2.0 * Wc * Wc) - Wc + p - c->Qn;
 }
 
+#define ORC_ATM_MARGIN 1e-10
+
 static int isfin(double x)
 {
-    return x == x && x - x == 0.0;
+    return isfinite(x);
 }
 
 /* returns 1 and fills P on success, 0 if no physical root was found */
@@ -406,7 +408,9 @@ static int c2p_solve(const geom *G, double gamma, const double *U, double *P)
     c.QB2 = c.QB * c.QB;
     c.gamma = gamma;
 
-    /* lower end: Wc >= D (h W >= 1) and v^2(Wc) < 1 (v^2 decreases with Wc) */
+    /* lower end of the bracket: the smallest Wc with v^2(Wc) < 1 (v^2 falls
+     * as Wc grows).  Roots below D (h W < 1) carry p < 0; they are accepted
+     * and the pressure floor then applies. */
     lo = c.D;
     c2p_v2(&c, lo, &v2, &dv2);
     if (!(v2 < 1.0)) {
@@ -429,6 +433,32 @@ static int c2p_solve(const geom *G, double gamma, const double *U, double *P)
                 b = mid;
             else
                 a = mid;
+        }
+        lo = b;
+    } else if (!(c2p_f(&c, lo, NULL) > 0.0)) {
+        /* f decreases with Wc: a root exists only below D */
+        double a = 0.5 * lo, b = lo;
+        int found = 0;
+        for (it = 0; it < 700; it++) {
+            c2p_v2(&c, a, &v2, &dv2);
+            if (!(v2 < 1.0)) {
+                found = 1;
+                break;
+            }
+            b = a;
+            a *= 0.5;
+        }
+        if (found) {
+            for (it = 0; it < 200; it++) {
+                double mid = 0.5 * (a + b);
+                if (mid <= a || mid >= b)
+                    break;
+                c2p_v2(&c, mid, &v2, &dv2);
+                if (v2 < 1.0)
+                    b = mid;
+                else
+                    a = mid;
+            }
         }
         lo = b;
     }
@@ -497,8 +527,10 @@ static int c2p_solve(const geom *G, double gamma, const double *U, double *P)
 
 /* Recovery followed by the atmosphere / floor policy (not in the paper):
  *  failure             -> keep the guess (rho, p, u~);
- *  rho < rho_atm, or a failure where the guess has rho < 10 rho_atm
- *                      -> rho = rho_atm, p = p_atm, u~ = 0;
+ *  rho < (1 - 1e-10) rho_atm, or a failure where the guess has
+ *  rho < 10 rho_atm    -> rho = rho_atm, p = p_atm, u~ = 0;
+ *                         (the margin keeps cells that sit at the atmosphere
+ *                          density from being reset back and forth by rounding)
  *  p < p_atm           -> p = p_atm;
  * B and Phi always come from U.  Wherever any of these fired, the matter part
  * of U (D, tau, S) is recomputed from the adjusted primitives.              */
@@ -514,7 +546,8 @@ static int c2p_cell(const geom *G, const orc_problem *pb, double *U, const doubl
             P[5 + i] = U[5 + i] / G->sqrtmg;
         P[8] = U[8];
     }
-    if (!(P[0] >= pb->rho_atm) || ((flags & ORC_FLAG_FAIL) && Pg[0] < 10.0 * pb->rho_atm)) {
+    if (!(P[0] >= (1.0 - ORC_ATM_MARGIN) * pb->rho_atm)
+        || ((flags & ORC_FLAG_FAIL) && Pg[0] < 10.0 * pb->rho_atm)) {
         flags |= ORC_FLAG_ATM;
         P[0] = pb->rho_atm;
         P[1] = pb->p_atm;

@@ -1,0 +1,442 @@
+// grmhd_api.hip -- the C ABI declared in include/grmhd.h.
+//
+// Host side only: validation, carving the caller's workspace, and enqueuing
+// the kernels of grmhd_kernels.hip on the caller's stream.  No device memory
+// is allocated or freed here and no call except grmhd_status/grmhd_timing
+// synchronises.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "grmhd.h"
+#include "grmhd_internal.h"
+
+using grmhd::Dev;
+
+namespace {
+
+struct TimedLaunch {
+    int kind;
+    hipEvent_t start, stop;
+};
+
+struct Layout {
+    int g[3], px, py, pz;
+    long long sv, N, nf[3];
+    size_t off_cnt, off_pc, off_us, off_f[3], total;
+};
+
+size_t round_up(size_t x, size_t a)
+{
+    return (x + a - 1) / a * a;
+}
+
+bool grid_ok(const grmhd_grid* g)
+{
+    if (!g)
+        return false;
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 1 || g->n[d] > (1 << 20))
+            return false;
+        if (!(g->hi[d] > g->lo[d]) || !std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]))
+            return false;
+        if (g->bc[d] != GRMHD_BC_PERIODIC && g->bc[d] != GRMHD_BC_OUTFLOW)
+            return false;
+    }
+    return true;
+}
+
+Layout make_layout(const grmhd_grid* g)
+{
+    Layout L{};
+    for (int d = 0; d < 3; ++d)
+        L.g[d] = g->n[d] > 1 ? 2 : 0;
+    // x pitch rounded to 8 doubles (64 bytes) so rows start aligned
+    L.px = (int)round_up((size_t)(g->n[0] + 2 * L.g[0]), 8);
+    L.py = g->n[1] + 2 * L.g[1];
+    L.pz = g->n[2] + 2 * L.g[2];
+    L.sv = (long long)L.px * L.py * L.pz;
+    L.N = (long long)g->n[0] * g->n[1] * g->n[2];
+    for (int d = 0; d < 3; ++d) {
+        long long nf = 1;
+        for (int e = 0; e < 3; ++e)
+            nf *= g->n[e] + (e == d ? 1 : 0);
+        L.nf[d] = g->n[d] > 1 ? nf : 0;
+    }
+    size_t off = 0;
+    L.off_cnt = off;
+    off += 256;
+    L.off_pc = off;
+    off = round_up(off + sizeof(double) * 9 * (size_t)L.sv, 256);
+    L.off_us = off;
+    off = round_up(off + sizeof(double) * 9 * (size_t)L.N, 256);
+    for (int d = 0; d < 3; ++d) {
+        L.off_f[d] = off;
+        off = round_up(off + sizeof(double) * 9 * (size_t)L.nf[d], 256);
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct grmhd_ctx {
+    Dev d;
+    int kind;
+    int rk_order;
+    hipStream_t stream = nullptr;
+    Layout L;
+    unsigned char* ws = nullptr;
+    double* Pc = nullptr;
+    double* Us = nullptr;
+    double* F[3] = {nullptr, nullptr, nullptr};
+    unsigned long long* cnt = nullptr;
+    bool prepared = false;
+    bool cache_valid = false;
+    int timing = 0;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> spare;
+    double ms[GRMHD_K_COUNT] = {};
+    long long launches[GRMHD_K_COUNT] = {};
+};
+
+namespace {
+
+hipEvent_t take_event(grmhd_ctx* c)
+{
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Run `f` (which enqueues one kernel) bracketed by events when timing is on.
+template <class Fn>
+int timed(grmhd_ctx* c, int kind, Fn&& f)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->timing) {
+        a = take_event(c);
+        b = take_event(c);
+        if (!a || !b)
+            return GRMHD_ERR_HIP;
+        if (hipEventRecord(a, c->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
+    }
+    if (f() != hipSuccess)
+        return GRMHD_ERR_HIP;
+    if (c->timing) {
+        if (hipEventRecord(b, c->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
+        c->pending.push_back({kind, a, b});
+    }
+    return GRMHD_OK;
+}
+
+// First enqueuing call: clear the counters and poison the cache with NaN so
+// that a read outside the stencil (edges, corners, pitch padding) shows up.
+int prepare(grmhd_ctx* c)
+{
+    if (c->prepared)
+        return GRMHD_OK;
+    if (grmhd::launch_zero_counters(c->cnt, c->stream) != hipSuccess)
+        return GRMHD_ERR_HIP;
+    if (grmhd::launch_fill(c->Pc, 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
+        return GRMHD_ERR_HIP;
+    c->prepared = true;
+    return GRMHD_OK;
+}
+
+// Ghost fill and the face fluxes of every active axis.
+int fluxes(grmhd_ctx* c)
+{
+    int rc = timed(c, GRMHD_K_BC, [&] { return grmhd::launch_ghosts(c->Pc, c->d, c->stream); });
+    if (rc)
+        return rc;
+    for (int dir = 0; dir < 3; ++dir) {
+        if (!c->d.act[dir])
+            continue;
+        rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
+            return grmhd::launch_flux(c->kind, dir, c->Pc, c->F[dir], c->d, c->stream);
+        });
+        if (rc)
+            return rc;
+    }
+    return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_opts* opts)
+{
+    (void)opts;
+    if (!grid_ok(grid))
+        return 0;
+    return make_layout(grid).total;
+}
+
+int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
+               const grmhd_eos* eos, const grmhd_opts* opts)
+{
+    if (!out || !metric || !grid || !eos || !opts)
+        return GRMHD_ERR_ARG;
+    *out = nullptr;
+    if (!grid_ok(grid))
+        return GRMHD_ERR_ARG;
+    if (metric->kind != GRMHD_METRIC_FLAT && metric->kind != GRMHD_METRIC_ISO_SCHW)
+        return GRMHD_ERR_ARG;
+    if (metric->kind == GRMHD_METRIC_ISO_SCHW) {
+        if (metric->soft != GRMHD_SOFT_SQRT && metric->soft != GRMHD_SOFT_MAX)
+            return GRMHD_ERR_ARG;
+        if (!(metric->M >= 0.0) || !(metric->r_min > 0.5 * metric->M))
+            return GRMHD_ERR_ARG;
+    }
+    if (eos->kind != GRMHD_EOS_IDEAL || !(eos->gamma > 1.0) || !(eos->gamma <= 2.0))
+        return GRMHD_ERR_ARG;
+    if (opts->rk_order != 2 && opts->rk_order != 3)
+        return GRMHD_ERR_ARG;
+    if (opts->precision != GRMHD_FP64)
+        return GRMHD_ERR_ARG;
+    if (opts->c_h < 0.0 || opts->kappa < 0.0 || !(opts->rho_atm > 0.0))
+        return GRMHD_ERR_ARG;
+    if (opts->newton_tol < 0.0 || opts->newton_maxit < 0)
+        return GRMHD_ERR_ARG;
+    Layout L = make_layout(grid);
+    if (!opts->workspace || opts->workspace_bytes < L.total)
+        return GRMHD_ERR_WORKSPACE;
+    if (((uintptr_t)opts->workspace) % 256 != 0)
+        return GRMHD_ERR_WORKSPACE;
+
+    grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
+    if (!c)
+        return GRMHD_ERR_ARG;
+    c->L = L;
+    c->kind = metric->kind == GRMHD_METRIC_FLAT ? grmhd::FLAT : grmhd::ISO;
+    c->rk_order = opts->rk_order;
+    c->timing = opts->timing;
+    Dev& d = c->d;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = grid->n[a];
+        d.g[a] = L.g[a];
+        d.act[a] = grid->n[a] > 1;
+        d.bc[a] = grid->bc[a] == GRMHD_BC_PERIODIC ? 0 : 1;
+        d.lo[a] = grid->lo[a];
+        d.dx[a] = (grid->hi[a] - grid->lo[a]) / grid->n[a];
+        d.idx[a] = 1.0 / d.dx[a];
+        d.nf[a] = L.nf[a];
+    }
+    d.px = L.px;
+    d.py = L.py;
+    d.pz = L.pz;
+    d.sv = L.sv;
+    d.N = L.N;
+    d.M = metric->M;
+    d.rmin = metric->r_min;
+    d.rmin2 = metric->r_min * metric->r_min;
+    d.soft = metric->soft == GRMHD_SOFT_SQRT ? 0 : 1;
+    d.gamma = eos->gamma;
+    d.gk = (eos->gamma - 1.0) / eos->gamma;
+    d.gfac = eos->gamma / (eos->gamma - 1.0);
+    d.c_h = opts->c_h > 0.0 ? opts->c_h : 1.0;
+    d.ic_h = 1.0 / d.c_h;
+    d.c_h2 = d.c_h * d.c_h;
+    d.kappa = opts->kappa;
+    d.rho_atm = opts->rho_atm;
+    d.p_atm = opts->p_atm >= 0.0 ? opts->p_atm : eos->K * std::pow(opts->rho_atm, eos->gamma);
+    d.tol = opts->newton_tol > 0.0 ? opts->newton_tol : 1e-12;
+    d.maxit = opts->newton_maxit > 0 ? opts->newton_maxit : 50;
+
+    c->ws = (unsigned char*)opts->workspace;
+    c->cnt = (unsigned long long*)(c->ws + L.off_cnt);
+    c->Pc = (double*)(c->ws + L.off_pc);
+    c->Us = (double*)(c->ws + L.off_us);
+    for (int a = 0; a < 3; ++a)
+        c->F[a] = L.nf[a] ? (double*)(c->ws + L.off_f[a]) : nullptr;
+    *out = c;
+    return GRMHD_OK;
+}
+
+int grmhd_set_stream(grmhd_ctx* c, void* stream)
+{
+    if (!c)
+        return GRMHD_ERR_ARG;
+    c->stream = (hipStream_t)stream;
+    return GRMHD_OK;
+}
+
+int grmhd_cons(grmhd_ctx* c, const double* P, double* U)
+{
+    if (!c || !P || !U)
+        return GRMHD_ERR_ARG;
+    int rc = prepare(c);
+    if (rc)
+        return rc;
+    rc = timed(c, GRMHD_K_CONS, [&] { return grmhd::launch_cons(c->kind, P, U, c->Pc, c->d, c->stream); });
+    if (rc)
+        return rc;
+    c->cache_valid = true;
+    return GRMHD_OK;
+}
+
+int grmhd_prim(grmhd_ctx* c, const double* U, double* P)
+{
+    if (!c || !U || !P)
+        return GRMHD_ERR_ARG;
+    int rc = prepare(c);
+    if (rc)
+        return rc;
+    rc = timed(c, GRMHD_K_PRIM, [&] {
+        return grmhd::launch_prim(c->kind, U, P, c->Pc, c->d, c->cnt, c->stream);
+    });
+    if (rc)
+        return rc;
+    c->cache_valid = true;
+    return GRMHD_OK;
+}
+
+int grmhd_rhs(grmhd_ctx* c, const double* P, double* R)
+{
+    if (!c || !P || !R)
+        return GRMHD_ERR_ARG;
+    int rc = prepare(c);
+    if (rc)
+        return rc;
+    rc = timed(c, GRMHD_K_CONS, [&] {
+        return grmhd::launch_cons(c->kind, P, nullptr, c->Pc, c->d, c->stream);
+    });
+    if (rc)
+        return rc;
+    c->cache_valid = true;
+    rc = fluxes(c);
+    if (rc)
+        return rc;
+    return timed(c, GRMHD_K_RHS, [&] {
+        return grmhd::launch_rhs(c->kind, c->F[0], c->F[1], c->F[2], c->Pc, R, c->d, c->stream);
+    });
+}
+
+int grmhd_step(grmhd_ctx* c, double* U, double dt)
+{
+    static const double rk3a[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double rk3b[3] = {1.0, 0.25, 2.0 / 3.0};
+    static const double rk2a[2] = {0.0, 0.5};
+    static const double rk2b[2] = {1.0, 0.5};
+    if (!c || !U || !std::isfinite(dt))
+        return GRMHD_ERR_ARG;
+    if (!c->cache_valid)
+        return GRMHD_ERR_STATE;
+    const int ns = c->rk_order;
+    const double* A = ns == 3 ? rk3a : rk2a;
+    const double* B = ns == 3 ? rk3b : rk2b;
+    for (int s = 0; s < ns; ++s) {
+        int rc = fluxes(c);
+        if (rc)
+            return rc;
+        const double* Us = s == 0 ? U : c->Us;
+        double* Uout = s == ns - 1 ? U : c->Us;
+        rc = timed(c, GRMHD_K_UPDATE, [&] {
+            return grmhd::launch_update(c->kind, c->F[0], c->F[1], c->F[2], c->Pc, U, Us, Uout, c->d, dt,
+                                        A[s], B[s], c->cnt, c->stream);
+        });
+        if (rc)
+            return rc;
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_status(grmhd_ctx* c, grmhd_stats* st, int reset)
+{
+    if (!c || !st)
+        return GRMHD_ERR_ARG;
+    unsigned long long h[grmhd::CNT_WORDS] = {};
+    if (c->prepared) {
+        if (hipMemcpyAsync(h, c->cnt, sizeof h, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
+        if (hipStreamSynchronize(c->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
+    }
+    st->c2p_fail = (long long)h[grmhd::CNT_FAIL];
+    st->atm_hits = (long long)h[grmhd::CNT_ATM];
+    st->p_floor_hits = (long long)h[grmhd::CNT_PFLOOR];
+    st->fallback_1d = (long long)h[grmhd::CNT_FALLBACK];
+    st->max_newton_it = (int)h[grmhd::CNT_MAXIT];
+    if (reset && c->prepared) {
+        if (grmhd::launch_zero_counters(c->cnt, c->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_timing(grmhd_ctx* c, double* ms, long long* launches, int reset)
+{
+    if (!c)
+        return GRMHD_ERR_ARG;
+    if (!c->pending.empty()) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
+        for (auto& t : c->pending) {
+            float e = 0.0f;
+            if (hipEventElapsedTime(&e, t.start, t.stop) != hipSuccess)
+                return GRMHD_ERR_HIP;
+            c->ms[t.kind] += e;
+            c->launches[t.kind] += 1;
+            c->spare.push_back(t.start);
+            c->spare.push_back(t.stop);
+        }
+        c->pending.clear();
+    }
+    for (int k = 0; k < GRMHD_K_COUNT; ++k) {
+        if (ms)
+            ms[k] = c->ms[k];
+        if (launches)
+            launches[k] = c->launches[k];
+        if (reset) {
+            c->ms[k] = 0.0;
+            c->launches[k] = 0;
+        }
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_free(grmhd_ctx* c)
+{
+    if (!c)
+        return GRMHD_ERR_ARG;
+    for (auto& t : c->pending) {
+        hipEventDestroy(t.start);
+        hipEventDestroy(t.stop);
+    }
+    for (auto e : c->spare)
+        hipEventDestroy(e);
+    delete c;
+    return GRMHD_OK;
+}
+
+const char* grmhd_strerror(int code)
+{
+    switch (code) {
+    case GRMHD_OK:
+        return "success";
+    case GRMHD_ERR_ARG:
+        return "invalid argument";
+    case GRMHD_ERR_WORKSPACE:
+        return "workspace missing, misaligned or smaller than grmhd_workspace_bytes()";
+    case GRMHD_ERR_HIP:
+        return "HIP runtime or kernel launch error";
+    case GRMHD_ERR_STATE:
+        return "primitive cache not initialised: call grmhd_cons or grmhd_prim first";
+    default:
+        return "unknown error";
+    }
+}
+
+}  // extern "C"

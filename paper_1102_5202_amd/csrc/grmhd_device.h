@@ -1,0 +1,491 @@
+// grmhd_device.h -- device-side physics of the GRMHD substep for gfx950.
+//
+// Static metric without shift, gamma_ij = psi^4 delta_ij (FLAT: alpha = psi = 1),
+// so every 4-tensor contraction collapses to a few scalar products.  Formulas
+// follow eq. 2 of the paper (conserved variables, fluxes, Christoffel source)
+// and the 3+1 primitive recovery of Noble et al. (2006) named in section 3.2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace grmhd {
+
+enum { FLAT = 0, ISO = 1 };
+
+// Per-launch constants (passed by value as a kernel argument).
+struct Dev {
+    int n[3];        // interior cells
+    int g[3];        // ghost width per axis (2 on active axes, 0 otherwise)
+    int act[3];      // axis active (n > 1)
+    int bc[3];       // 0 periodic, 1 outflow
+    int px, py, pz;  // dimensions of the ghosted primitive cache (px is the pitch)
+    long long sv;    // per-variable stride of the cache
+    long long N;     // interior cell count
+    long long nf[3]; // face count per direction
+    double lo[3], dx[3], idx[3];
+    // metric
+    double M, rmin, rmin2;
+    int soft;        // 0 sqrt(r^2 + r_min^2), 1 max(r, r_min)
+    // equation of state and scheme
+    double gamma, gk, gfac;   // gamma, (gamma-1)/gamma, gamma/(gamma-1)
+    double c_h, ic_h, c_h2, kappa;
+    double rho_atm, p_atm, tol;
+    int maxit;
+};
+
+// Geometry at one point.
+struct Geo {
+    double alpha, psi4, ipsi4, sqrtg, sqrtmg, isqrtmg;
+};
+
+// h = M/(2 r_s) and r_s at a point; returns false where the softened radius is
+// constant (MAX softening inside r_min: derivatives vanish).
+__device__ __forceinline__ double soft_radius(const Dev& d, double r2, bool& varying)
+{
+    if (d.soft == 0) {
+        varying = true;
+        return sqrt(r2 + d.rmin2);
+    }
+    double r = sqrt(r2);
+    varying = r > d.rmin;
+    return varying ? r : d.rmin;
+}
+
+template <int KIND>
+__device__ __forceinline__ Geo geo_at(const Dev& d, double x, double y, double z)
+{
+    Geo g;
+    if (KIND == FLAT) {
+        g.alpha = g.psi4 = g.ipsi4 = g.sqrtg = g.sqrtmg = g.isqrtmg = 1.0;
+    } else {
+        bool vary;
+        double rs = soft_radius(d, x * x + y * y + z * z, vary);
+        double h = 0.5 * d.M / rs;
+        double i1h = 1.0 / (1.0 + h);
+        double psi = 1.0 + h;
+        double psi2 = psi * psi;
+        double i2 = i1h * i1h;
+        g.alpha = (1.0 - h) * i1h;
+        g.psi4 = psi2 * psi2;
+        g.ipsi4 = i2 * i2;
+        g.sqrtg = g.psi4 * psi2;
+        g.sqrtmg = g.alpha * g.sqrtg;
+        g.isqrtmg = 1.0 / g.sqrtmg;
+    }
+    return g;
+}
+
+// Geometry plus the radial derivative factors at a cell centre:
+// d_j alpha = ka * x_j and d_j psi^4 = kp * x_j.
+template <int KIND>
+__device__ __forceinline__ Geo geo_deriv(const Dev& d, double x, double y, double z, double& ka,
+                                         double& kp)
+{
+    Geo g;
+    if (KIND == FLAT) {
+        g.alpha = g.psi4 = g.ipsi4 = g.sqrtg = g.sqrtmg = g.isqrtmg = 1.0;
+        ka = kp = 0.0;
+    } else {
+        bool vary;
+        double rs = soft_radius(d, x * x + y * y + z * z, vary);
+        double irs = 1.0 / rs;
+        double h = 0.5 * d.M * irs;
+        double i1h = 1.0 / (1.0 + h);
+        double psi = 1.0 + h;
+        double psi2 = psi * psi;
+        double i2 = i1h * i1h;
+        g.alpha = (1.0 - h) * i1h;
+        g.psi4 = psi2 * psi2;
+        g.ipsi4 = i2 * i2;
+        g.sqrtg = g.psi4 * psi2;
+        g.sqrtmg = g.alpha * g.sqrtg;
+        g.isqrtmg = 1.0 / g.sqrtmg;
+        double hr2 = vary ? h * irs * irs : 0.0;
+        // d alpha/d r_s = 2 h / (r_s (1+h)^2), d psi^4/d r_s = -4 psi^3 h / r_s, d r_s/d x_j = x_j / r_s
+        ka = 2.0 * hr2 * i2;
+        kp = -4.0 * psi2 * psi * hr2;
+    }
+    return g;
+}
+
+// Fluid-frame quantities of one state (W, b^mu, enthalpies).
+struct Kin {
+    double W, bt, b[3], b2, w, wtot, ptot;
+};
+
+__device__ __forceinline__ Kin kinematics(const double* q, const Geo& g, double gfac)
+{
+    Kin k;
+    double u0 = q[2], u1 = q[3], u2 = q[4];
+    double B0 = q[5], B1 = q[6], B2 = q[7];
+    k.W = sqrt(1.0 + g.psi4 * (u0 * u0 + u1 * u1 + u2 * u2));
+    double f = g.alpha / k.W;                      // 1/u^t
+    k.bt = g.psi4 * (B0 * u0 + B1 * u1 + B2 * u2); // b^t = B^i u_i
+    k.b[0] = (B0 + k.bt * u0) * f;                 // b^i = (B^i + b^t u^i)/u^t
+    k.b[1] = (B1 + k.bt * u1) * f;
+    k.b[2] = (B2 + k.bt * u2) * f;
+    k.b2 = (g.psi4 * (B0 * B0 + B1 * B1 + B2 * B2) + k.bt * k.bt) * f * f;
+    k.w = q[0] + gfac * q[1];
+    k.wtot = k.w + k.b2;
+    k.ptot = q[1] + 0.5 * k.b2;
+    return k;
+}
+
+// Extreme signal speeds along axis D: the dispersion relation with the
+// isotropic fast speed c^2 = (gamma p + b^2)/(w + b^2), solved in closed form.
+template <int D>
+__device__ __forceinline__ void speeds(const double* q, const Kin& k, const Geo& g, double gamma,
+                                       double& lm, double& lp)
+{
+    double inv = 1.0 / k.wtot;
+    double c2 = (k.b2 + gamma * q[1]) * inv;
+    double a = (k.w - gamma * q[1]) * inv;         // 1 - c^2
+    double qi = q[2 + D];
+    double den = k.W * k.W * a + c2;
+    double disc = c2 * (den * g.ipsi4 - qi * qi * a);
+    double s = sqrt(fmax(disc, 0.0));
+    double t = g.alpha / den;
+    double m = k.W * qi * a;
+    lp = (m + s) * t;
+    lm = (m - s) * t;
+}
+
+// Component v (0..7, not the normal field) of the physical flux along D.
+template <int D>
+__device__ __forceinline__ double flux_comp(int v, const double* q, const Kin& k, const Geo& g)
+{
+    double uD = q[2 + D];
+    switch (v) {
+    case 0:
+        return g.sqrtmg * q[0] * uD;
+    case 1:
+        return g.sqrtmg * ((k.wtot * g.alpha * k.W - q[0]) * uD - g.alpha * g.alpha * k.bt * k.b[D]);
+    case 2:
+    case 3:
+    case 4: {
+        int j = v - 2;
+        double t = g.psi4 * (k.wtot * uD * q[2 + j] - k.b[D] * k.b[j]);
+        if (j == D)
+            t += k.ptot;
+        return g.sqrtmg * t;
+    }
+    default: {
+        int j = v - 5;
+        return g.sqrtmg * (k.b[j] * uD - k.b[D] * q[2 + j]);
+    }
+    }
+}
+
+// Component v (0..7) of the conserved variables.
+__device__ __forceinline__ double cons_comp(int v, const double* q, const Kin& k, const Geo& g)
+{
+    switch (v) {
+    case 0:
+        return g.sqrtg * q[0] * k.W;
+    case 1:
+        return g.sqrtmg * (k.wtot * k.W * k.W - k.ptot - g.alpha * g.alpha * k.bt * k.bt)
+               - g.sqrtg * q[0] * k.W;
+    case 2:
+    case 3:
+    case 4: {
+        int j = v - 2;
+        return g.psi4 * (g.sqrtg * k.wtot * k.W * q[2 + j] - g.sqrtmg * k.bt * k.b[j]);
+    }
+    default:
+        return g.sqrtmg * q[v];
+    }
+}
+
+// MC-limited slope: minmod(2 dq-, (dq- + dq+)/2, 2 dq+).
+__device__ __forceinline__ double mc_slope(double qm, double q0, double qp)
+{
+    double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
+    double s = fmin(fmin(2.0 * fabs(dl), 2.0 * fabs(dr)), fabs(dc));
+    return (dl * dr > 0.0) ? copysign(s, dc) : 0.0;
+}
+
+// A class test, not arithmetic: with FMA contraction "x - x" may be evaluated
+// as fma(a, b, -x) for x = a*b, which is the rounding error of the product.
+__device__ __forceinline__ bool finite(double x)
+{
+    return __builtin_isfinite(x);
+}
+
+// ---------------------------------------------------------------------------
+// Primitive recovery (section 2.2; the 2D_W equations of Noble et al. 2006 in
+// the unknowns Wc = rho h W^2 and v^2).
+
+struct C2P {
+    double D, Qn, Qt2, Bc2, QB2;
+};
+
+__device__ __forceinline__ double c2p_press(const C2P& c, double gk, double Wc, double v2)
+{
+    double s = sqrt(1.0 - v2);
+    return gk * (Wc * (1.0 - v2) - c.D * s);
+}
+
+// Newton-Raphson on the two residuals, warm-started.  Converged when the
+// relative step in Wc falls below tol, after one more step; the final point
+// must then satisfy both equations to 1e-10 of their scales with v^2 inside
+// (0, 1) unclamped.  Returns true on acceptance; iters counts the iterations.
+__device__ __forceinline__ bool c2p_newton2d(const C2P& c, double gk, double tol, int maxit,
+                                             double& Wc, double& v2, int& iters)
+{
+    const double vmax = 1.0 - 1e-16;
+    int extra = -1;
+    bool clamped = false;
+    for (int it = 0; it < maxit; ++it) {
+        iters = it + 1;
+        double bw = c.Bc2 + Wc;
+        double iW = 1.0 / Wc;
+        double iW2 = iW * iW;
+        double s = sqrt(1.0 - v2);
+        // residuals
+        double r1 = v2 * bw * bw - c.QB2 * (c.Bc2 + 2.0 * Wc) * iW2 - c.Qt2;
+        double p = gk * (Wc * (1.0 - v2) - c.D * s);
+        double r2 = -0.5 * c.Bc2 * (1.0 + v2) + 0.5 * c.QB2 * iW2 - Wc + p - c.Qn;
+        // Jacobian
+        double a11 = 2.0 * v2 * bw + 2.0 * c.QB2 * bw * iW2 * iW;
+        double a12 = bw * bw;
+        double a21 = -c.QB2 * iW2 * iW - 1.0 + gk * (1.0 - v2);
+        double a22 = -0.5 * c.Bc2 + gk * (-Wc + 0.5 * c.D / s);
+        double det = a11 * a22 - a12 * a21;
+        double dW = (r1 * a22 - a12 * r2) / det;
+        double dv = (a11 * r2 - a21 * r1) / det;
+        double Wn = Wc - dW;
+        double vn = v2 - dv;
+        if (!(Wn > 0.0))
+            Wn = 0.5 * Wc;
+        clamped = !(vn < vmax);
+        vn = fmin(fmax(vn, 0.0), vmax);
+        double step = fabs(Wn - Wc);
+        Wc = Wn;
+        v2 = vn;
+        if (!finite(Wc) || !finite(v2))
+            return false;
+        if (extra == 0)
+            break;
+        if (step <= tol * Wc)
+            extra = 0;   // converged: one more step puts the error at round-off
+    }
+    if (extra != 0 || clamped || !(Wc > 0.0))
+        return false;
+    double bw = c.Bc2 + Wc;
+    double iW2 = 1.0 / (Wc * Wc);
+    double s = sqrt(1.0 - v2);
+    double t1 = v2 * bw * bw, t2 = c.QB2 * (c.Bc2 + 2.0 * Wc) * iW2;
+    double r1 = t1 - t2 - c.Qt2;
+    double p = gk * (Wc * (1.0 - v2) - c.D * s);
+    double r2 = -0.5 * c.Bc2 * (1.0 + v2) + 0.5 * c.QB2 * iW2 - Wc + p - c.Qn;
+    double sc1 = t1 + t2 + c.Qt2;
+    double sc2 = c.Bc2 + Wc + fabs(p) + fabs(c.Qn) + 0.5 * c.QB2 * iW2;
+    return fabs(r1) <= 1e-10 * sc1 && fabs(r2) <= 1e-10 * sc2;
+}
+
+__device__ __forceinline__ void c2p_v2(const C2P& c, double Wc, double& v2, double& dv2)
+{
+    double bw = c.Bc2 + Wc;
+    double ibw = 1.0 / bw;
+    double iW = 1.0 / Wc;
+    double gq = (c.Bc2 + 2.0 * Wc) * ibw * ibw * iW * iW;
+    v2 = c.Qt2 * ibw * ibw + c.QB2 * gq;
+    dv2 = -2.0 * c.Qt2 * ibw * ibw * ibw + c.QB2 * gq * (2.0 / (c.Bc2 + 2.0 * Wc) - 2.0 * ibw - 2.0 * iW);
+}
+
+__device__ __forceinline__ double c2p_f1d(const C2P& c, double gk, double Wc, double& df)
+{
+    double v2, dv2;
+    c2p_v2(c, Wc, v2, dv2);
+    double s = sqrt(1.0 - v2);
+    double p = gk * (Wc * (1.0 - v2) - c.D * s);
+    double dp = gk * ((1.0 - v2) + (-Wc + 0.5 * c.D / s) * dv2);
+    double iW = 1.0 / Wc;
+    df = -0.5 * c.Bc2 * dv2 - c.QB2 * iW * iW * iW - 1.0 + dp;
+    return -0.5 * c.Bc2 * (1.0 + v2) + 0.5 * c.QB2 * iW * iW - Wc + p - c.Qn;
+}
+
+// Bracketed solve in Wc alone (v^2 eliminated): used when the 2D iteration
+// is not accepted.  The bracket starts at the smallest Wc with v^2 < 1 (v^2
+// falls with Wc; f falls with Wc), searched above D when v^2(D) >= 1 and
+// below D only when f(D) <= 0; Newton steps are kept inside the bracket.
+__device__ __noinline__ bool c2p_bracketed(const C2P& c, double gk, double& Wc_out, double& v2_out)
+{
+    double lo = c.D, v2, dv2, df;
+    c2p_v2(c, lo, v2, dv2);
+    if (!(v2 < 1.0)) {
+        double a = lo, b = 2.0 * lo;
+        int it = 0;
+        for (; it < 1100; ++it) {
+            c2p_v2(c, b, v2, dv2);
+            if (v2 < 1.0)
+                break;
+            a = b;
+            b *= 2.0;
+        }
+        if (!(v2 < 1.0))
+            return false;
+        for (it = 0; it < 120; ++it) {
+            double m = 0.5 * (a + b);
+            if (!(m > a && m < b))
+                break;
+            c2p_v2(c, m, v2, dv2);
+            if (v2 < 1.0)
+                b = m;
+            else
+                a = m;
+        }
+        lo = b;
+    } else if (!(c2p_f1d(c, gk, lo, df) > 0.0)) {
+        double a = 0.5 * lo, b = lo;
+        bool found = false;
+        for (int it = 0; it < 700; ++it) {
+            c2p_v2(c, a, v2, dv2);
+            if (!(v2 < 1.0)) {
+                found = true;
+                break;
+            }
+            b = a;
+            a *= 0.5;
+        }
+        for (int it = 0; found && it < 120; ++it) {
+            double m = 0.5 * (a + b);
+            if (!(m > a && m < b))
+                break;
+            c2p_v2(c, m, v2, dv2);
+            if (v2 < 1.0)
+                b = m;
+            else
+                a = m;
+        }
+        lo = b;
+    }
+    if (!(c2p_f1d(c, gk, lo, df) > 0.0))
+        return false;
+    double hi = 2.0 * lo;
+    for (int it = 0; it < 1100 && c2p_f1d(c, gk, hi, df) >= 0.0; ++it) {
+        lo = hi;
+        hi *= 2.0;
+    }
+    if (!(c2p_f1d(c, gk, hi, df) < 0.0))
+        return false;
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 300; ++it) {
+        double f = c2p_f1d(c, gk, x, df);
+        if (f == 0.0)
+            break;
+        if (f > 0.0)
+            lo = x;
+        else
+            hi = x;
+        double xn = x - f / df;
+        if (!(xn > lo && xn < hi))
+            xn = 0.5 * (lo + hi);
+        bool done = fabs(xn - x) <= 1e-14 * x || hi - lo <= 4e-16 * hi;
+        x = xn;
+        if (done) {
+            f = c2p_f1d(c, gk, x, df);
+            xn = x - f / df;
+            if (f != 0.0 && xn > lo && xn < hi)
+                x = xn;
+            break;
+        }
+    }
+    c2p_v2(c, x, v2, dv2);
+    if (!(v2 >= 0.0 && v2 < 1.0) || !finite(x))
+        return false;
+    Wc_out = x;
+    v2_out = v2;
+    return true;
+}
+
+enum { FLAG_FAIL = 1, FLAG_ATM = 2, FLAG_PFLOOR = 4, FLAG_FALLBACK = 8 };
+
+// Recovery plus the atmosphere/floor policy for one cell.  u is the conserved
+// state (its matter part is rewritten where a floor fired), qg the guess (the
+// previous primitives of the cell), p the output primitives.  Returns flags.
+__device__ __forceinline__ int recover_cell(const Dev& d, const Geo& g, double* u, const double* qg,
+                                            double* p, int& iters)
+{
+    int flags = 0;
+    iters = 0;
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        ok = ok && finite(u[v]);
+    ok = ok && u[0] > 0.0;
+    double Bc[3], Q[3];
+    C2P c;
+    double isg = 1.0 / g.sqrtg;
+    c.D = u[0] * isg;
+    c.Qn = -(u[1] + u[0]) * g.isqrtmg;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        Q[i] = u[2 + i] * isg;
+        Bc[i] = g.alpha * (u[5 + i] * g.isqrtmg);
+    }
+    c.Qt2 = g.ipsi4 * (Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+    c.Bc2 = g.psi4 * (Bc[0] * Bc[0] + Bc[1] * Bc[1] + Bc[2] * Bc[2]);
+    double QB = Q[0] * Bc[0] + Q[1] * Bc[1] + Q[2] * Bc[2];
+    c.QB2 = QB * QB;
+
+    double Wc = 0.0, v2 = 0.0;
+    if (ok) {
+        // warm start from the guess primitives
+        double uu = g.psi4 * (qg[2] * qg[2] + qg[3] * qg[3] + qg[4] * qg[4]);
+        double Wg2 = 1.0 + uu;
+        Wc = (qg[0] + d.gfac * qg[1]) * Wg2;
+        v2 = uu / Wg2;
+        bool guess_ok = finite(Wc) && Wc > 0.0 && finite(v2);
+        bool conv = guess_ok && c2p_newton2d(c, d.gk, d.tol, d.maxit, Wc, v2, iters);
+        if (!conv) {
+            flags |= FLAG_FALLBACK;
+            ok = c2p_bracketed(c, d.gk, Wc, v2);
+        }
+    }
+    if (ok) {
+        double s = sqrt(1.0 - v2);
+        double W = 1.0 / s;
+        p[0] = c.D * s;
+        p[1] = d.gk * (Wc * (1.0 - v2) - c.D * s);
+        double f = W / (Wc + c.Bc2);
+        double fq = QB / Wc;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            p[2 + i] = f * (g.ipsi4 * Q[i] + fq * Bc[i]);
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+            ok = ok && finite(p[v]);
+    }
+    if (!ok) {
+        flags |= FLAG_FAIL;
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+            p[v] = qg[v];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        p[5 + i] = u[5 + i] * g.isqrtmg;
+    p[8] = u[8];
+    // atmosphere: rho below rho_atm by more than a relative 1e-10 (a margin
+    // above rounding, so cells sitting at rho_atm are not reset back and forth)
+    if (!(p[0] >= (1.0 - 1e-10) * d.rho_atm) || ((flags & FLAG_FAIL) && qg[0] < 10.0 * d.rho_atm)) {
+        flags |= FLAG_ATM;
+        p[0] = d.rho_atm;
+        p[1] = d.p_atm;
+        p[2] = p[3] = p[4] = 0.0;
+    }
+    if (!(p[1] >= d.p_atm)) {
+        flags |= FLAG_PFLOOR;
+        p[1] = d.p_atm;
+    }
+    if (flags & (FLAG_FAIL | FLAG_ATM | FLAG_PFLOOR)) {
+        Kin k = kinematics(p, g, d.gfac);
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+            u[v] = cons_comp(v, p, k, g);
+    }
+    return flags;
+}
+
+}  // namespace grmhd

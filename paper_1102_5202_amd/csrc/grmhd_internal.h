@@ -1,0 +1,26 @@
+// grmhd_internal.h -- launchers shared by the C ABI and the kernel unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "grmhd_device.h"
+
+namespace grmhd {
+
+// device counter words (unsigned 64-bit)
+enum { CNT_FAIL = 0, CNT_ATM = 1, CNT_PFLOOR = 2, CNT_FALLBACK = 3, CNT_MAXIT = 4, CNT_WORDS = 8 };
+
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
+hipError_t launch_zero_counters(unsigned long long* cnt, hipStream_t s);
+hipError_t launch_ghosts(double* Pc, const Dev& d, hipStream_t s);
+hipError_t launch_flux(int kind, int dir, const double* Pc, double* F, const Dev& d, hipStream_t s);
+hipError_t launch_update(int kind, const double* Fx, const double* Fy, const double* Fz, double* Pc,
+                         const double* Un, const double* Us, double* Uout, const Dev& d, double dt,
+                         double a, double b, unsigned long long* cnt, hipStream_t s);
+hipError_t launch_rhs(int kind, const double* Fx, const double* Fy, const double* Fz, const double* Pc,
+                      double* R, const Dev& d, hipStream_t s);
+hipError_t launch_cons(int kind, const double* P, double* U, double* Pc, const Dev& d, hipStream_t s);
+hipError_t launch_prim(int kind, const double* U, double* P, double* Pc, const Dev& d,
+                       unsigned long long* cnt, hipStream_t s);
+
+}  // namespace grmhd

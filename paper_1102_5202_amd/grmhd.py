@@ -1,0 +1,215 @@
+"""ctypes binding of ``libgrmhd.so`` (the C ABI of ``include/grmhd.h``).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  PyTorch provides the device memory (tensors) and the stream.  The
+binding fails loudly when the library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgrmhd.so")
+
+FLAT, ISO_SCHW = 0, 1
+SOFT_SQRT, SOFT_MAX = 0, 1
+PERIODIC, OUTFLOW = 0, 1
+FP64 = 0
+KERNELS = ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs")
+NVAR = 9
+
+# exported symbols of include/grmhd.h
+SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_cons", "grmhd_step",
+           "grmhd_prim", "grmhd_rhs", "grmhd_status", "grmhd_timing", "grmhd_free",
+           "grmhd_strerror")
+
+
+class Metric(C.Structure):
+    _fields_ = [("kind", C.c_int), ("soft", C.c_int), ("M", C.c_double), ("r_min", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("bc", C.c_int * 3)]
+
+
+class Eos(C.Structure):
+    _fields_ = [("kind", C.c_int), ("gamma", C.c_double), ("K", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("rk_order", C.c_int), ("precision", C.c_int), ("c_h", C.c_double),
+                ("kappa", C.c_double), ("rho_atm", C.c_double), ("p_atm", C.c_double),
+                ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("timing", C.c_int),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("c2p_fail", C.c_longlong), ("atm_hits", C.c_longlong),
+                ("p_floor_hits", C.c_longlong), ("fallback_1d", C.c_longlong),
+                ("max_newton_it", C.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgrmhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libgrmhd.so is not built (%s); run `python -m paper_1102_5202_amd.build`"
+                           " or __graft_entry__.build()" % path)
+    L = C.CDLL(path)
+    vp = C.c_void_p
+    L.grmhd_workspace_bytes.argtypes = [C.POINTER(Grid), C.POINTER(Opts)]
+    L.grmhd_workspace_bytes.restype = C.c_size_t
+    L.grmhd_init.argtypes = [C.POINTER(vp), C.POINTER(Metric), C.POINTER(Grid), C.POINTER(Eos),
+                             C.POINTER(Opts)]
+    L.grmhd_set_stream.argtypes = [vp, vp]
+    L.grmhd_cons.argtypes = [vp, vp, vp]
+    L.grmhd_step.argtypes = [vp, vp, C.c_double]
+    L.grmhd_prim.argtypes = [vp, vp, vp]
+    L.grmhd_rhs.argtypes = [vp, vp, vp]
+    L.grmhd_status.argtypes = [vp, C.POINTER(Stats), C.c_int]
+    L.grmhd_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
+    L.grmhd_free.argtypes = [vp]
+    L.grmhd_strerror.argtypes = [C.c_int]
+    L.grmhd_strerror.restype = C.c_char_p
+    for name in SYMBOLS:
+        if name not in ("grmhd_workspace_bytes", "grmhd_strerror"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        msg = load().grmhd_strerror(rc).decode()
+        raise RuntimeError("%s failed: %s (%d)" % (what, msg, rc))
+
+
+def make_grid(n, lo, hi, bc) -> Grid:
+    g = Grid()
+    for d in range(3):
+        g.n[d] = int(n[d])
+        g.lo[d] = float(lo[d])
+        g.hi[d] = float(hi[d])
+        g.bc[d] = int(bc[d])
+    return g
+
+
+def workspace_bytes(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0, 0, 0)) -> int:
+    return int(load().grmhd_workspace_bytes(C.byref(make_grid(n, lo, hi, bc)), None))
+
+
+class Solver:
+    """One simulation context: grid, metric, EOS and options, with the
+    workspace and stream owned by PyTorch.
+
+    Tensors are float64, contiguous, shape (9, nz, ny, nx), on the solver's
+    device: P = (rho, p, u~x, u~y, u~z, Bx, By, Bz, Phi),
+    U = (D, tau, Sx, Sy, Sz, Bdx, Bdy, Bdz, Phi)."""
+
+    def __init__(self, n, lo, hi, bc, metric=FLAT, M=0.0, soft=SOFT_SQRT, r_min=1.0,
+                 gamma=5.0 / 3.0, K=0.0, rk_order=3, c_h=1.0, kappa=1.0, rho_atm=1e-12,
+                 p_atm=1e-12, newton_tol=1e-12, newton_maxit=50, timing=False, device="cuda",
+                 stream=None):
+        L = load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise RuntimeError("Solver needs a GPU device; got %s" % self.device)
+        self.n = tuple(int(v) for v in n)
+        self.shape = (NVAR, self.n[2], self.n[1], self.n[0])
+        self._grid = make_grid(n, lo, hi, bc)
+        self._metric = Metric(int(metric), int(soft), float(M), float(r_min))
+        self._eos = Eos(0, float(gamma), float(K))
+        nbytes = int(L.grmhd_workspace_bytes(C.byref(self._grid), None))
+        if nbytes == 0:
+            raise ValueError("invalid grid")
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._opts = Opts(int(rk_order), FP64, float(c_h), float(kappa), float(rho_atm),
+                          float(p_atm), float(newton_tol), int(newton_maxit), int(bool(timing)),
+                          C.c_void_p(self.workspace.data_ptr()), nbytes)
+        ctx = C.c_void_p()
+        _check(L.grmhd_init(C.byref(ctx), C.byref(self._metric), C.byref(self._grid),
+                            C.byref(self._eos), C.byref(self._opts)), "grmhd_init")
+        self._ctx = ctx
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream(self.device))
+
+    # -- plumbing ------------------------------------------------------------
+    def set_stream(self, stream) -> None:
+        self.stream = stream
+        _check(load().grmhd_set_stream(self._ctx, C.c_void_p(stream.cuda_stream)),
+               "grmhd_set_stream")
+
+    def _t(self, x: torch.Tensor, name: str) -> int:
+        if (not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_contiguous()
+                or x.device != self.device or tuple(x.shape) != self.shape):
+            raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s"
+                             % (name, self.shape, self.device))
+        return x.data_ptr()
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    # -- the C ABI -----------------------------------------------------------
+    def cons(self, P: torch.Tensor, U: torch.Tensor = None) -> torch.Tensor:
+        U = self.empty() if U is None else U
+        _check(load().grmhd_cons(self._ctx, C.c_void_p(self._t(P, "P")), C.c_void_p(self._t(U, "U"))),
+               "grmhd_cons")
+        return U
+
+    def step(self, U: torch.Tensor, dt: float) -> torch.Tensor:
+        _check(load().grmhd_step(self._ctx, C.c_void_p(self._t(U, "U")), float(dt)), "grmhd_step")
+        return U
+
+    def prim(self, U: torch.Tensor, P: torch.Tensor = None) -> torch.Tensor:
+        P = self.empty() if P is None else P
+        _check(load().grmhd_prim(self._ctx, C.c_void_p(self._t(U, "U")), C.c_void_p(self._t(P, "P"))),
+               "grmhd_prim")
+        return P
+
+    def rhs(self, P: torch.Tensor, R: torch.Tensor = None) -> torch.Tensor:
+        R = self.empty() if R is None else R
+        _check(load().grmhd_rhs(self._ctx, C.c_void_p(self._t(P, "P")), C.c_void_p(self._t(R, "R"))),
+               "grmhd_rhs")
+        return R
+
+    def status(self, reset: bool = False) -> dict:
+        st = Stats()
+        _check(load().grmhd_status(self._ctx, C.byref(st), int(bool(reset))), "grmhd_status")
+        return {"fail": st.c2p_fail, "atm": st.atm_hits, "pfloor": st.p_floor_hits,
+                "fallback_1d": st.fallback_1d, "max_newton_it": st.max_newton_it}
+
+    def timing(self, reset: bool = False) -> dict:
+        ms = (C.c_double * len(KERNELS))()
+        cnt = (C.c_longlong * len(KERNELS))()
+        _check(load().grmhd_timing(self._ctx, ms, cnt, int(bool(reset))), "grmhd_timing")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None):
+            load().grmhd_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(workload, **over) -> Solver:
+    """A Solver configured for a :class:`workloads.Workload`."""
+    kw = dict(n=workload.n, lo=workload.lo, hi=workload.hi, bc=workload.bc, metric=workload.metric,
+              M=workload.M, soft=workload.soft, r_min=workload.r_min, gamma=workload.gamma,
+              rk_order=workload.rk_order, c_h=workload.c_h, kappa=workload.kappa,
+              rho_atm=workload.rho_atm, p_atm=workload.p_atm)
+    kw.update(over)
+    return Solver(**kw)

@@ -59,6 +59,13 @@ class Workload:
                     rho_atm=self.rho_atm, p_atm=self.p_atm)
 
 
+def cfl_dt(n, lo, hi, cfl: float = 0.4) -> float:
+    """Time step for Courant number `cfl` of an unsplit update: the signal speed
+    is bounded by 1 and the Courant numbers of the active axes add up."""
+    s = sum(n[d] / (hi[d] - lo[d]) for d in range(3) if n[d] > 1)
+    return cfl / s
+
+
 def rng_for(config: int, k: int = 0) -> np.random.Generator:
     return np.random.default_rng(SEED_BASE + 1000 * config + k)
 
@@ -174,12 +181,16 @@ def config2(n: int = 128, k: int = 0, nsteps: int = 100, config_id: int = 2) -> 
     rho = 1 + 0.1 sum_m a_m cos(2 pi k_m.x + phi_m) over 16 modes (|k| <= 4,
     sum |a_m| = 1); p = 0.1; v = 0.3 V / max|V| with V from 16 modes per
     component, u~ = W v; B = (0.1, 0.05, 0) + central curl of a 16-mode vector
-    potential scaled to max|dB| = 0.01; Phi = 0.  SSP-RK2, dt = 0.4/n."""
+    potential scaled to max|dB| = 0.01; Phi = 0.  SSP-RK2 with CFL 0.4 against
+    the light-speed bound summed over the axes: dt = 0.4 / sum_d(1/dx_d).
+    ``n`` may be a 3-tuple (the modes stay periodic on the unit box)."""
     rng = rng_for(config_id, k)
-    nn = (n, n, n)
+    nn = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
     lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
     X = centres(nn, lo, hi)
-    P = np.zeros((9, n, n, n))
+    shape = (nn[2], nn[1], nn[0])
+    eshape = (nn[2] + 2, nn[1] + 2, nn[0] + 2)
+    P = np.zeros((9,) + shape)
 
     def field(count=16, kmax=4):
         ks = _modes(rng, count, kmax)
@@ -198,22 +209,22 @@ def config2(n: int = 128, k: int = 0, nsteps: int = 100, config_id: int = 2) -> 
     am = am / np.abs(am).sum()
     P[0] = 1.0 + 0.1 * evaluate(ks, ph, am, X)
     P[1] = 0.1
-    V = np.stack([np.broadcast_to(evaluate(*field(), X), (n, n, n)) for _ in range(3)])
+    V = np.stack([np.broadcast_to(evaluate(*field(), X), shape) for _ in range(3)])
     vmag = np.sqrt((V * V).sum(axis=0))
     v = 0.3 * V / vmag.max()
     W = 1.0 / np.sqrt(1.0 - (v * v).sum(axis=0))
     P[2:5] = W * v
     Xe, dx = _extended_centres(nn, lo, hi)
-    A = np.stack([np.broadcast_to(evaluate(*field(), Xe), (n + 2, n + 2, n + 2))
-                  for _ in range(3)])
+    A = np.stack([np.broadcast_to(evaluate(*field(), Xe), eshape) for _ in range(3)])
     dB = _curl_central(A, dx)
     dB *= 0.01 / np.abs(dB).max()
     P[5] = 0.1 + dB[0]
     P[6] = 0.05 + dB[1]
     P[7] = dB[2]
     P[8] = 0.0
-    return Workload(name="periodic_flat_%d" % n, P=P, n=nn, lo=lo, hi=hi, bc=(PERIODIC,) * 3,
-                    gamma=4.0 / 3.0, rk_order=2, dt=0.4 / n, nsteps=nsteps)
+    return Workload(name="periodic_flat_%dx%dx%d" % nn, P=P, n=nn, lo=lo, hi=hi,
+                    bc=(PERIODIC,) * 3, gamma=4.0 / 3.0, rk_order=2, dt=cfl_dt(nn, lo, hi),
+                    nsteps=nsteps)
 
 
 # -----------------------------------------------------------------------------
@@ -237,7 +248,8 @@ def config3(n=192, k: int = 0, nsteps: int = 200, half: float = 20.0, noise: boo
     U[-1,1] per cell; rigid rotation with coordinate angular velocity Omega
     about z; poloidal field from A = A_b rho_c exp(-r^2/w^2)(-y, x, 0) through a
     central curl of the densitised field, scaled so that max(B^2/2) =
-    max(p)/beta_plasma; outflow; SSP-RK3, dt = 0.4 dx.  ``n`` may be a 3-tuple."""
+    max(p)/beta_plasma; outflow; SSP-RK3 with dt = 0.4 / sum_d(1/dx_d) (coordinate
+    signal speeds are bounded by alpha/psi^2 <= 1).  ``n`` may be a 3-tuple."""
     nn = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
     rng = rng_for(3, k)
     lo, hi = (-half,) * 3, (half,) * 3
@@ -270,9 +282,8 @@ def config3(n=192, k: int = 0, nsteps: int = 200, half: float = 20.0, noise: boo
     scale = np.sqrt((P[1].max() / beta_plasma) / (0.5 * bmag2.max()))
     P[5:8] = B * scale
     P[8] = 0.0
-    dxmin = min(dx)
     return Workload(name="curved_blob_%dx%dx%d" % nn, P=P, n=nn, lo=lo, hi=hi,
-                    bc=(OUTFLOW,) * 3, gamma=2.0, rk_order=3, dt=0.4 * dxmin, nsteps=nsteps,
+                    bc=(OUTFLOW,) * 3, gamma=2.0, rk_order=3, dt=cfl_dt(nn, lo, hi), nsteps=nsteps,
                     metric=ISO_SCHW, M=M, soft=SOFT_SQRT, r_min=1.0, rho_atm=rho_atm,
                     p_atm=K * rho_atm ** 2, extra={"K": K})
 

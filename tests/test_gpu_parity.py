@@ -1,0 +1,259 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on the same
+seeded inputs.  Bar: relative L1 <= 1e-10 per conserved variable after the
+stated step counts (FP64), tighter for single kernels; bitwise where the
+scheme fixes the result exactly."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1102_5202_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1102_5202_amd import grmhd
+    grmhd.load()
+    return grmhd
+
+
+def rel_l1(a, b):
+    import oracle
+    return oracle.parity_error(a, b)
+
+
+def gpu_run(G, w, nsteps, P0=None, **over):
+    s = G.solver_for(w, device=DEV, **over)
+    P = torch.from_numpy(np.ascontiguousarray(w.P if P0 is None else P0)).to(DEV)
+    U = s.cons(P)
+    for _ in range(nsteps):
+        s.step(U, w.dt)
+    Pn = s.prim(U)
+    st = s.status()
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), Pn.cpu().numpy(), st, s
+
+
+def oracle_run(orc, w, nsteps, P0=None, **over):
+    kw = w.problem_kwargs()
+    kw.update(over)
+    pb = orc.Problem(**kw)
+    P = w.P if P0 is None else P0
+    U0 = orc.prim2con(pb, P)
+    U, Pn, st = orc.step(pb, U0, P, w.dt, nsteps)
+    return U, Pn, st, pb
+
+
+# ---------------------------------------------------------------------------
+# single kernels
+
+def test_cons_matches_oracle(G, orc):
+    w = WL.config3(n=(37, 29, 23), nsteps=0)
+    s = G.solver_for(w, device=DEV)
+    U = s.cons(torch.from_numpy(w.P).to(DEV)).cpu().numpy()
+    pb = orc.Problem(**w.problem_kwargs())
+    Ur = orc.prim2con(pb, w.P)
+    err = rel_l1(U, Ur)
+    say("cons rel-L1", err)
+    assert np.all(err <= 1e-14)
+
+
+def test_prim_matches_oracle_from_perturbed_guess(G, orc):
+    """Newton from a guess 5% away, flat and curved, magnetised states."""
+    for w in (WL.config2(n=24, k=3), WL.config3(n=(26, 22, 20))):
+        pb = orc.Problem(**w.problem_kwargs())
+        rng = np.random.default_rng(0)
+        Pg = w.P * (1.0 + 0.05 * rng.uniform(-1, 1, w.P.shape))
+        Ut = orc.prim2con(pb, w.P)
+        s = G.solver_for(w, device=DEV)
+        s.cons(torch.from_numpy(Pg).to(DEV))          # loads the guess into the cache
+        P = s.prim(torch.from_numpy(Ut).to(DEV)).cpu().numpy()
+        st = s.status()
+        Pr, Ur2, flags, sto = orc.con2prim(pb, Ut, Pg)
+        err = rel_l1(P, Pr)
+        say(w.name, "prim rel-L1", err, st, sto)
+        assert np.all(err[:8] <= 1e-12)
+        assert st["fail"] == sto["fail"] and st["atm"] == sto["atm"]
+
+
+def test_rhs_matches_oracle(G, orc):
+    """One evaluation of L(P): flux differences + sources."""
+    cases = [WL.config1(2, n=400), WL.config2(n=20, k=2), WL.config3(n=(41, 35, 30)),
+             WL.config3(n=(33, 1, 27), k=4)]
+    for w in cases:
+        s = G.solver_for(w, device=DEV)
+        R = s.rhs(torch.from_numpy(np.ascontiguousarray(w.P)).to(DEV)).cpu().numpy()
+        pb = orc.Problem(**w.problem_kwargs())
+        Rr = orc.rhs(pb, w.P)
+        scale = np.abs(Rr).reshape(9, -1).max(axis=1, keepdims=True)
+        err = (np.abs(R - Rr).reshape(9, -1) / np.maximum(scale, 1e-300)).max(axis=1)
+        say(w.name, "rhs max rel err", err)
+        assert np.all(err <= 1e-11), err
+
+
+# ---------------------------------------------------------------------------
+# the configurations
+
+@pytest.mark.parametrize("k", range(8))
+def test_riemann_1d_full_run(G, orc, k):
+    """400 cells, 400 SSP-RK3 steps to t = 0.4 (seeded left/right states)."""
+    w = WL.config1(k)
+    U, P, st, _ = gpu_run(G, w, w.nsteps)
+    Ur, Pr, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say("riemann k=%d" % k, "rel-L1", err[:8].max(), st, sto)
+    assert np.all(err[:8] <= 1e-10)
+    assert np.array_equal(U[5], Ur[5]) and np.all(U[8] == 0.0)     # Bx, Phi exact in 1D
+    assert st["fail"] == sto["fail"]
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_riemann_1d_along_other_axes(G, orc, axis):
+    w = WL.config1(1, n=300, axis=axis)
+    U, P, st, _ = gpu_run(G, w, 150)
+    Ur, Pr, sto, _ = oracle_run(orc, w, 150)
+    assert np.all(rel_l1(U, Ur)[:8] <= 1e-10)
+
+
+def test_periodic_flat_box(G, orc):
+    """Config 2 recipe on a ragged 33 x 30 x 28 periodic grid, 100 SSP-RK2 steps."""
+    w = WL.config2(n=(33, 30, 28), nsteps=100)
+    U, P, st, _ = gpu_run(G, w, w.nsteps)
+    Ur, Pr, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say("periodic box rel-L1", err, st, sto)
+    assert np.all(err <= 1e-10)
+    assert st["fail"] == 0 and sto["fail"] == 0
+
+
+def test_curved_blob(G, orc):
+    """Config 3 recipe at 40 x 36 x 34 cells on [-20,20]^3, 20 SSP-RK3 steps."""
+    w = WL.config3(n=(40, 36, 34), nsteps=20)
+    U, P, st, _ = gpu_run(G, w, w.nsteps)
+    Ur, Pr, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say("curved blob rel-L1", err, st, sto)
+    assert np.all(err <= 1e-10)
+
+
+def test_curved_blob_full_size_sampled(G, orc):
+    """Config 3 at its full 192^3 size, one SSP-RK3 step on the GPU (the launch
+    configuration of the benchmark).  The oracle recomputes sampled cells one
+    by one on the 13^3 box around each: one RK3 step depends on cells at most
+    6 away (2 per substep), so the box centre is exact."""
+    w = WL.config3(n=192, nsteps=1)
+    say("generated 192^3 initial data")
+    s = G.solver_for(w, device=DEV)
+    U = s.cons(torch.from_numpy(w.P).to(DEV))
+    s.step(U, w.dt)
+    torch.cuda.synchronize()
+    U = U.cpu().numpy()
+    say("GPU step done", s.status())
+    n = 192
+    dx = 40.0 / n
+    rng = np.random.default_rng(7)
+    picks = [tuple(rng.integers(0, n, 3)) for _ in range(120)]
+    picks += [(0, 0, 0), (n - 1, n - 1, n - 1), (95, 96, 96), (96, 95, 0), (3, 100, 191),
+              (60, 96, 96), (130, 70, 110)]
+    scale = np.abs(U).reshape(9, -1).max(axis=1)
+    worst = np.zeros(9)
+    for (i, j, k) in picks:
+        lo_i = [max(c - 6, 0) for c in (i, j, k)]
+        hi_i = [min(c + 6, n - 1) for c in (i, j, k)]
+        sub = np.ascontiguousarray(w.P[:, lo_i[2]:hi_i[2] + 1, lo_i[1]:hi_i[1] + 1,
+                                       lo_i[0]:hi_i[0] + 1])
+        kw = w.problem_kwargs()
+        kw["n"] = tuple(hi_i[d] - lo_i[d] + 1 for d in range(3))
+        kw["lo"] = tuple(-20.0 + lo_i[d] * dx for d in range(3))
+        kw["hi"] = tuple(-20.0 + (hi_i[d] + 1) * dx for d in range(3))
+        pb = orc.Problem(**kw)
+        Ur, _, _ = orc.step(pb, orc.prim2con(pb, sub), sub, w.dt, 1)
+        ref = Ur[:, k - lo_i[2], j - lo_i[1], i - lo_i[0]]
+        got = U[:, k, j, i]
+        worst = np.maximum(worst, np.abs(got - ref) / np.maximum(scale, 1e-300))
+    say("192^3 sampled max err / scale", worst)
+    assert np.all(worst <= 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# exactness, determinism, failure policy, graph replay
+
+def test_uniform_state_held_bitwise(G):
+    P0 = np.array([0.7, 0.3, 0.4, -0.2, 0.5, 0.3, -0.6, 0.2, 0.0])
+    for metric, M in ((WL.FLAT, 0.0), (WL.ISO_SCHW, 0.0)):
+        for bc in (WL.PERIODIC, WL.OUTFLOW):
+            P = np.empty((9, 9, 11, 13))
+            for v in range(9):
+                P[v] = P0[v]
+            w = WL.Workload(name="u", P=P, n=(13, 11, 9), lo=(0.0,) * 3, hi=(1.0,) * 3,
+                            bc=(bc,) * 3, gamma=5.0 / 3.0, rk_order=3, dt=0.03, nsteps=4,
+                            metric=metric, M=M)
+            s = G.solver_for(w, device=DEV)
+            U = s.cons(torch.from_numpy(P).to(DEV))
+            U0 = U.clone()
+            for _ in range(4):
+                s.step(U, w.dt)
+            torch.cuda.synchronize()
+            assert torch.equal(U, U0)
+
+
+def test_bitwise_deterministic(G):
+    w = WL.config3(n=(30, 28, 26), nsteps=5)
+    a = gpu_run(G, w, 5)[0]
+    b = gpu_run(G, w, 5)[0]
+    assert np.array_equal(a, b)
+
+
+def test_failure_policy_matches_oracle(G, orc):
+    w = WL.config2(n=8)
+    pb = orc.Problem(**{**w.problem_kwargs(), "rho_atm": 1e-6, "p_atm": 1e-8})
+    U = orc.prim2con(pb, w.P)
+    U[1, 0, 0, 0] = -10.0
+    U[2, 1, 0, 0] = 100.0
+    U[0, 2, 0, 0] = np.nan
+    U[:, 3, 0, 0] = 0.0
+    Pg = w.P.copy()
+    Pg[0, 2, 0, 0] = 5e-6
+    s = G.solver_for(w, device=DEV, rho_atm=1e-6, p_atm=1e-8)
+    s.cons(torch.from_numpy(Pg).to(DEV))
+    P = s.prim(torch.from_numpy(U).to(DEV)).cpu().numpy()
+    st = s.status(reset=True)
+    Pr, _, flags, sto = orc.con2prim(pb, U, Pg)
+    say(st, sto)
+    assert st["fail"] == sto["fail"] == 4
+    assert st["atm"] == sto["atm"]
+    np.testing.assert_allclose(P, Pr, rtol=1e-12, atol=1e-14)
+    assert s.status()["fail"] == 0
+
+
+def test_graph_replay_matches_eager(G):
+    """A captured step replayed several times (with eager work and
+    synchronisation between replays) equals eager steps, bitwise."""
+    w = WL.config3(n=(24, 22, 20), nsteps=3)
+    P = torch.from_numpy(w.P).to(DEV)
+    se = G.solver_for(w, device=DEV)
+    Ue = se.cons(P)
+    sg = G.solver_for(w, device=DEV)
+    Ug = sg.cons(P)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sg.set_stream(torch.cuda.current_stream())
+        sg.step(Ug, w.dt)
+    sg.set_stream(torch.cuda.current_stream())
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        se.step(Ue, w.dt)
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, Ue), r
