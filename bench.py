@@ -1,0 +1,187 @@
+"""Benchmark of the GRMHD substep on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 192] [--no-cpu]
+
+Workload: the static curved-spacetime blob on [-20,20]^3 at 192^3 cells
+(isotropic Schwarzschild metric with softened radius, Gamma = 2, SSP-RK3,
+FP64), synthetic seeded initial data already resident in HBM.  A step is one
+full Runge-Kutta step (three substeps, every kernel of the path).  The metric
+is zone-updates per second per Runge-Kutta substep.  Prints one JSON line.
+
+Per-kernel durations come from HIP events the library records around each
+launch on its stream during the timed region.  The roofline entry is for the
+kernel with the largest total time; its algorithmic bytes per launch follow
+from the sizes below (flux kernels: read the primitives once, write 9 face
+values per face; update kernel: read 3x9 face values, the primitives, U^n and
+U^(s), write U^(s+1) and the primitives).  The CPU baseline times the plain
+oracle on one full RK step of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/s per RK substep (FP64 vs mixed) at stated L1 error; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1102_5202_amd/csrc/grmhd_kernels.hip",
+                  "paper_1102_5202_amd/csrc/grmhd_device.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel: str, n, nsub: int) -> float:
+    """Algorithmic HBM bytes of ONE launch of a kernel class on an n[0] x n[1] x n[2] grid."""
+    N = n[0] * n[1] * n[2]
+    w = 8.0 * 9                      # bytes of one 9-variable FP64 record
+    if kernel.startswith("flux_"):
+        d = "xyz".index(kernel[-1])
+        nf = N // n[d] * (n[d] + 1)
+        return w * N + w * nf        # primitives once + one flux record per face
+    if kernel == "update":
+        # faces (one unique record per cell and axis) + primitives r/w + U^n + U^(s) + U^(s+1);
+        # averaged over the substeps (the first substep reads U^n only once)
+        reads_us = (nsub - 1) / nsub
+        return w * N * (3 + 1 + 1 + reads_us + 1 + 1)
+    if kernel == "bc":
+        g = 2
+        return w * 2 * g * (n[1] * n[2] + n[0] * n[2] + n[0] * n[1]) * 2
+    return float("nan")
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (scaled by a copy-kernel calibration), if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload, {}).get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, pb_kwargs):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    pb = oracle.Problem(**pb_kwargs)
+    U0 = oracle.prim2con(pb, w.P)
+    t0 = time.perf_counter()
+    oracle.step(pb, U0, w.P, w.dt, 1)
+    dt = time.perf_counter() - t0
+    subs = w.rk_order * w.ncell
+    return {"value": subs / dt, "unit": "zone-updates/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": "one full SSP-RK%d step (%d substeps) of the %s workload, %d cells, %.1f s wall"
+                      % (w.rk_order, w.rk_order, w.name, w.ncell, dt)}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=192)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the multi-GPU halo exchange is a design note, not an implemented path)" % args.gpus,
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1102_5202_amd import grmhd, workloads
+
+    dev = "cuda:0"
+    w = workloads.config3(n=args.n, nsteps=args.steps)
+    wl_name = "curved_blob_%d^3" % args.n
+    s = grmhd.solver_for(w, device=dev, timing=not args.no_timing)
+    P = torch.from_numpy(w.P).to(dev)
+    U = s.cons(P)
+    for _ in range(args.warmup):
+        s.step(U, w.dt)
+    torch.cuda.synchronize()
+    s.timing(reset=True)
+    s.status(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step(U, w.dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    nsub = w.rk_order
+    value = w.ncell * nsub * args.steps / elapsed
+    st = s.status()
+    finite = bool(torch.isfinite(U).all().item())
+
+    kernels = {}
+    roof = None
+    if not args.no_timing:
+        tm = s.timing()
+        for k, (ms, cnt) in tm.items():
+            if cnt:
+                avg = ms / cnt
+                b = algorithmic_bytes(k, w.n, nsub)
+                kernels[k] = {"launches": cnt, "total_ms": round(ms, 4), "avg_ms": round(avg, 5),
+                              "alg_GBps": round(b / (avg * 1e-3) / 1e9, 1) if b == b else None}
+        dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+        avg_s = kernels[dom]["avg_ms"] * 1e-3
+        b = algorithmic_bytes(dom, w.n, nsub)
+        achieved = b / avg_s / 1e9
+        traffic = load_traffic(dom, wl_name)
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "alg_bytes_per_launch": b}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded initial data)",
+        "config": {"workload": wl_name + " static curved spacetime (isotropic Schwarzschild, "
+                   "r_s = sqrt(r^2+1)), [-20,20]^3, Gamma=2, SSP-RK3, FP64",
+                   "cells": w.ncell, "substeps_per_step": nsub, "dt": w.dt},
+        "roofline": roof,
+        "kernels": kernels,
+        "recovery": st,
+        "finite": finite,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, w.problem_kwargs())
+    print(json.dumps(out), flush=True)
+    return 0 if finite else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -67,7 +67,7 @@ Layout make_layout(const grmhd_grid* g)
     }
     size_t off = 0;
     L.off_cnt = off;
-    off += 256;
+    off = round_up(off + grmhd::CNT_BYTES, 256);
     L.off_pc = off;
     off = round_up(off + sizeof(double) * 9 * (size_t)L.sv, 256);
     L.off_us = off;
@@ -357,12 +357,19 @@ int grmhd_status(grmhd_ctx* c, grmhd_stats* st, int reset)
 {
     if (!c || !st)
         return GRMHD_ERR_ARG;
-    unsigned long long h[grmhd::CNT_WORDS] = {};
+    std::vector<unsigned long long> slots(grmhd::CNT_WORDS * grmhd::CNT_SLOTS, 0ull);
     if (c->prepared) {
-        if (hipMemcpyAsync(h, c->cnt, sizeof h, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        if (hipMemcpyAsync(slots.data(), c->cnt, grmhd::CNT_BYTES, hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
         if (hipStreamSynchronize(c->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
+    }
+    unsigned long long h[grmhd::CNT_WORDS] = {};
+    for (int s = 0; s < grmhd::CNT_SLOTS; ++s) {
+        const unsigned long long* w = &slots[(size_t)s * grmhd::CNT_WORDS];
+        for (int i = 0; i < grmhd::CNT_WORDS; ++i)
+            h[i] = i == grmhd::CNT_MAXIT ? (w[i] > h[i] ? w[i] : h[i]) : h[i] + w[i];
     }
     st->c2p_fail = (long long)h[grmhd::CNT_FAIL];
     st->atm_hits = (long long)h[grmhd::CNT_ATM];

@@ -309,8 +309,22 @@ __device__ __forceinline__ double c2p_f1d(const C2P& c, double gk, double Wc, do
 // is not accepted.  The bracket starts at the smallest Wc with v^2 < 1 (v^2
 // falls with Wc; f falls with Wc), searched above D when v^2(D) >= 1 and
 // below D only when f(D) <= 0; Newton steps are kept inside the bracket.
-__device__ __noinline__ bool c2p_bracketed(const C2P& c, double gk, double& Wc_out, double& v2_out)
+struct WV {
+    double Wc, v2;   // Wc < 0 flags a failure
+};
+
+// All inputs by value and the result returned by value, so that nothing of
+// the caller's state has its address taken (it stays in registers).
+__device__ __noinline__ WV c2p_bracketed(double D, double Qn, double Qt2, double Bc2, double QB2,
+                                         double gk)
 {
+    C2P c;
+    c.D = D;
+    c.Qn = Qn;
+    c.Qt2 = Qt2;
+    c.Bc2 = Bc2;
+    c.QB2 = QB2;
+    const WV fail = {-1.0, 0.0};
     double lo = c.D, v2, dv2, df;
     c2p_v2(c, lo, v2, dv2);
     if (!(v2 < 1.0)) {
@@ -324,7 +338,7 @@ __device__ __noinline__ bool c2p_bracketed(const C2P& c, double gk, double& Wc_o
             b *= 2.0;
         }
         if (!(v2 < 1.0))
-            return false;
+            return fail;
         for (it = 0; it < 120; ++it) {
             double m = 0.5 * (a + b);
             if (!(m > a && m < b))
@@ -361,14 +375,14 @@ __device__ __noinline__ bool c2p_bracketed(const C2P& c, double gk, double& Wc_o
         lo = b;
     }
     if (!(c2p_f1d(c, gk, lo, df) > 0.0))
-        return false;
+        return fail;
     double hi = 2.0 * lo;
     for (int it = 0; it < 1100 && c2p_f1d(c, gk, hi, df) >= 0.0; ++it) {
         lo = hi;
         hi *= 2.0;
     }
     if (!(c2p_f1d(c, gk, hi, df) < 0.0))
-        return false;
+        return fail;
     double x = 0.5 * (lo + hi);
     for (int it = 0; it < 300; ++it) {
         double f = c2p_f1d(c, gk, x, df);
@@ -393,10 +407,9 @@ __device__ __noinline__ bool c2p_bracketed(const C2P& c, double gk, double& Wc_o
     }
     c2p_v2(c, x, v2, dv2);
     if (!(v2 >= 0.0 && v2 < 1.0) || !finite(x))
-        return false;
-    Wc_out = x;
-    v2_out = v2;
-    return true;
+        return fail;
+    WV r = {x, v2};
+    return r;
 }
 
 enum { FLAG_FAIL = 1, FLAG_ATM = 2, FLAG_PFLOOR = 4, FLAG_FALLBACK = 8 };
@@ -440,7 +453,10 @@ __device__ __forceinline__ int recover_cell(const Dev& d, const Geo& g, double* 
         bool conv = guess_ok && c2p_newton2d(c, d.gk, d.tol, d.maxit, Wc, v2, iters);
         if (!conv) {
             flags |= FLAG_FALLBACK;
-            ok = c2p_bracketed(c, d.gk, Wc, v2);
+            WV r = c2p_bracketed(c.D, c.Qn, c.Qt2, c.Bc2, c.QB2, d.gk);
+            ok = r.Wc > 0.0;
+            Wc = r.Wc;
+            v2 = r.v2;
         }
     }
     if (ok) {

@@ -7,8 +7,14 @@
 
 namespace grmhd {
 
-// device counter words (unsigned 64-bit)
-enum { CNT_FAIL = 0, CNT_ATM = 1, CNT_PFLOOR = 2, CNT_FALLBACK = 3, CNT_MAXIT = 4, CNT_WORDS = 8 };
+// Device counters: CNT_SLOTS copies of CNT_WORDS unsigned 64-bit words, one
+// 128-byte line per slot.  A wave adds into slot (block index mod CNT_SLOTS),
+// so that atomics from different waves rarely meet on one address (atomics on
+// a single address serialise in the L2); the host sums (max for MAXIT) the
+// slots when it reads them.
+enum { CNT_FAIL = 0, CNT_ATM = 1, CNT_PFLOOR = 2, CNT_FALLBACK = 3, CNT_MAXIT = 4, CNT_WORDS = 16 };
+enum { CNT_SLOTS = 256 };
+static constexpr size_t CNT_BYTES = sizeof(unsigned long long) * CNT_WORDS * CNT_SLOTS;
 
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
 hipError_t launch_zero_counters(unsigned long long* cnt, hipStream_t s);

@@ -25,10 +25,10 @@ __global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ p, long lon
         p[t] = v;
 }
 
-__global__ __launch_bounds__(64) void k_zero_counters(unsigned long long* cnt)
+__global__ __launch_bounds__(BLOCK) void k_zero_counters(unsigned long long* cnt)
 {
-    if (threadIdx.x < CNT_WORDS)
-        cnt[threadIdx.x] = 0ull;
+    for (int t = threadIdx.x; t < CNT_WORDS * CNT_SLOTS; t += BLOCK)
+        cnt[t] = 0ull;
 }
 
 // Ghost fill: one thread per ghost cell of the three face slabs (no edges or
@@ -205,8 +205,9 @@ __device__ __forceinline__ long long cache_index(const Dev& d, int i, int j, int
     return ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + (i + d.g[0]);
 }
 
-__device__ __forceinline__ void count_flags(unsigned long long* cnt, int flags, int iters)
+__device__ __forceinline__ void count_flags(unsigned long long* cnt_base, int flags, int iters)
 {
+    unsigned long long* cnt = cnt_base + (size_t)(blockIdx.x % CNT_SLOTS) * CNT_WORDS;
     // one atomic per wave and counter
     unsigned long long mf = __ballot((flags & FLAG_FAIL) != 0);
     unsigned long long ma = __ballot((flags & FLAG_ATM) != 0);
@@ -227,6 +228,8 @@ __device__ __forceinline__ void count_flags(unsigned long long* cnt, int flags, 
             atomicAdd(&cnt[CNT_PFLOOR], (unsigned long long)__popcll(mp));
         if (mb)
             atomicAdd(&cnt[CNT_FALLBACK], (unsigned long long)__popcll(mb));
+        // no returning atomic here: waiting on one would also wait for the
+        // wave's outstanding result stores before it can retire
         atomicMax(&cnt[CNT_MAXIT], (unsigned long long)itmax);
     }
 }
@@ -378,7 +381,7 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t s)
 
 hipError_t launch_zero_counters(unsigned long long* cnt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, cnt);
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(BLOCK), 0, s, cnt);
     return hipGetLastError();
 }
 
