@@ -76,6 +76,53 @@ def load_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    """Kernel class of a demangled kernel name."""
+    for key, short in (("k_flux<0", "flux_x"), ("k_flux<1", "flux_y"), ("k_flux<2", "flux_z"),
+                       ("k_update", "update"), ("k_ghosts", "bc"), ("k_cons", "cons"),
+                       ("k_prim", "prim"), ("k_rhs", "rhs"), ("copyBuffer", "copy_probe")):
+        if key in name:
+            return short
+    return name[:40]
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: str, out_json: str):
+    """Per-launch HBM bytes of each kernel class from two rocprofv3 --pmc runs
+    (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled by what the same
+    counter reads for the copy probe of known size (probe_bytes read and written)."""
+    per = {}
+    for path, ctr in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        for r in _read_csv(path):
+            if r.get("Counter_Name") != ctr:
+                continue
+            k = _short(r["Kernel_Name"])
+            per.setdefault(k, {}).setdefault(ctr, []).append(float(r["Counter_Value"]))
+    probe = per.get("copy_probe")
+    if not probe:
+        raise SystemExit("no copy-probe dispatch found in the counter files")
+    ff = (probe_bytes / 1024.0) / (sum(probe["FETCH_SIZE"]) / len(probe["FETCH_SIZE"]))
+    fw = (probe_bytes / 1024.0) / (sum(probe["WRITE_SIZE"]) / len(probe["WRITE_SIZE"]))
+    res = {"calibration": {"probe_bytes": probe_bytes, "fetch_factor": ff, "write_factor": fw},
+           workload: {}}
+    for k, c in per.items():
+        if k == "copy_probe" or "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        fk = sum(c["FETCH_SIZE"]) / len(c["FETCH_SIZE"])
+        wk = sum(c["WRITE_SIZE"]) / len(c["WRITE_SIZE"])
+        res[workload][k] = {"fetch_KiB": fk, "write_KiB": wk,
+                            "bytes_per_launch": 1024.0 * (fk * ff + wk * fw),
+                            "dispatches": len(c["FETCH_SIZE"]), "source_hash": kernel_source_hash()}
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1, sort_keys=True)
+    return res
+
+
 def cpu_baseline(w, pb_kwargs):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -100,7 +147,19 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
+                    help="first run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files "
+                         "(taken with --copy-probe) and exit")
+    ap.add_argument("--probe-mib", type=float, default=1024.0)
     args = ap.parse_args(argv)
+
+    if args.pmc_summary:
+        res = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.probe_mib * 2 ** 20,
+                          "curved_blob_%d^3" % args.n, os.path.join(ROOT, "profiles", "traffic.json"))
+        print(json.dumps(res, indent=1))
+        return 0
 
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -114,6 +173,13 @@ def main(argv=None) -> int:
     from paper_1102_5202_amd import grmhd, workloads
 
     dev = "cuda:0"
+    if args.copy_probe > 0:
+        nel = int(args.copy_probe * 2 ** 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = workloads.config3(n=args.n, nsteps=args.steps)
     wl_name = "curved_blob_%d^3" % args.n
     s = grmhd.solver_for(w, device=dev, timing=not args.no_timing)
