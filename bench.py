@@ -106,12 +106,15 @@ def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: st
     probe = per.get("copy_probe")
     if not probe:
         raise SystemExit("no copy-probe dispatch found in the counter files")
-    ff = (probe_bytes / 1024.0) / (sum(probe["FETCH_SIZE"]) / len(probe["FETCH_SIZE"]))
-    fw = (probe_bytes / 1024.0) / (sum(probe["WRITE_SIZE"]) / len(probe["WRITE_SIZE"]))
+    # the probe is the largest copy dispatch (other copies are small host transfers)
+    ff = (probe_bytes / 1024.0) / max(probe["FETCH_SIZE"])
+    fw = (probe_bytes / 1024.0) / max(probe["WRITE_SIZE"])
     res = {"calibration": {"probe_bytes": probe_bytes, "fetch_factor": ff, "write_factor": fw},
            workload: {}}
     for k, c in per.items():
-        if k == "copy_probe" or "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+        if k not in ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs"):
+            continue
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
             continue
         fk = sum(c["FETCH_SIZE"]) / len(c["FETCH_SIZE"])
         wk = sum(c["WRITE_SIZE"]) / len(c["WRITE_SIZE"])

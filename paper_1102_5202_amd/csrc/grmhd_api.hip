@@ -25,7 +25,7 @@ struct TimedLaunch {
 struct Layout {
     int g[3], px, py, pz;
     long long sv, N, nf[3];
-    size_t off_cnt, off_pc, off_us, off_f[3], total;
+    size_t off_cnt, off_pc[3], off_us, off_f[3], total;
 };
 
 size_t round_up(size_t x, size_t a)
@@ -68,8 +68,11 @@ Layout make_layout(const grmhd_grid* g)
     size_t off = 0;
     L.off_cnt = off;
     off = round_up(off + grmhd::CNT_BYTES, 256);
-    L.off_pc = off;
-    off = round_up(off + sizeof(double) * 9 * (size_t)L.sv, 256);
+    for (int b = 0; b < 3; ++b) {
+        L.off_pc[b] = off;
+        if (b == 0 || g->n[2] > 1)   // the extra caches serve the fused 3D update only
+            off = round_up(off + sizeof(double) * 9 * (size_t)L.sv, 256);
+    }
     L.off_us = off;
     off = round_up(off + sizeof(double) * 9 * (size_t)L.N, 256);
     for (int d = 0; d < 3; ++d) {
@@ -89,7 +92,11 @@ struct grmhd_ctx {
     hipStream_t stream = nullptr;
     Layout L;
     unsigned char* ws = nullptr;
-    double* Pc = nullptr;
+    // Primitive caches.  Pbuf[0] holds the current primitives between calls.
+    // A 3D step rotates through all three (RK3: 0 -> 1 -> 2 -> 0, RK2: 0 -> 1
+    // -> 0) so that every substep writes a cache it does not read and the step
+    // ends in Pbuf[0] (a captured step can be replayed).
+    double* Pbuf[3] = {nullptr, nullptr, nullptr};
     double* Us = nullptr;
     double* F[3] = {nullptr, nullptr, nullptr};
     unsigned long long* cnt = nullptr;
@@ -148,23 +155,30 @@ int prepare(grmhd_ctx* c)
         return GRMHD_OK;
     if (grmhd::launch_zero_counters(c->cnt, c->stream) != hipSuccess)
         return GRMHD_ERR_HIP;
-    if (grmhd::launch_fill(c->Pc, 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
-        return GRMHD_ERR_HIP;
+    for (int b = 0; b < 3; ++b)
+        if (c->d.act[2] || b == 0)
+            if (grmhd::launch_fill(c->Pbuf[b], 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
+                return GRMHD_ERR_HIP;
     c->prepared = true;
     return GRMHD_OK;
 }
 
-// Ghost fill and the face fluxes of every active axis.
-int fluxes(grmhd_ctx* c)
+double* cache(grmhd_ctx* c)
 {
-    int rc = timed(c, GRMHD_K_BC, [&] { return grmhd::launch_ghosts(c->Pc, c->d, c->stream); });
+    return c->Pbuf[0];
+}
+
+// Ghost fill of the cache P and the face fluxes of the active axes up to ndir.
+int fluxes(grmhd_ctx* c, double* P, int ndir)
+{
+    int rc = timed(c, GRMHD_K_BC, [&] { return grmhd::launch_ghosts(P, c->d, c->stream); });
     if (rc)
         return rc;
-    for (int dir = 0; dir < 3; ++dir) {
+    for (int dir = 0; dir < ndir; ++dir) {
         if (!c->d.act[dir])
             continue;
         rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
-            return grmhd::launch_flux(c->kind, dir, c->Pc, c->F[dir], c->d, c->stream);
+            return grmhd::launch_flux(c->kind, dir, P, c->F[dir], c->d, c->stream);
         });
         if (rc)
             return rc;
@@ -257,7 +271,8 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
 
     c->ws = (unsigned char*)opts->workspace;
     c->cnt = (unsigned long long*)(c->ws + L.off_cnt);
-    c->Pc = (double*)(c->ws + L.off_pc);
+    for (int b = 0; b < 3; ++b)
+        c->Pbuf[b] = (double*)(c->ws + L.off_pc[b]);
     c->Us = (double*)(c->ws + L.off_us);
     for (int a = 0; a < 3; ++a)
         c->F[a] = L.nf[a] ? (double*)(c->ws + L.off_f[a]) : nullptr;
@@ -280,7 +295,7 @@ int grmhd_cons(grmhd_ctx* c, const double* P, double* U)
     int rc = prepare(c);
     if (rc)
         return rc;
-    rc = timed(c, GRMHD_K_CONS, [&] { return grmhd::launch_cons(c->kind, P, U, c->Pc, c->d, c->stream); });
+    rc = timed(c, GRMHD_K_CONS, [&] { return grmhd::launch_cons(c->kind, P, U, cache(c), c->d, c->stream); });
     if (rc)
         return rc;
     c->cache_valid = true;
@@ -295,7 +310,7 @@ int grmhd_prim(grmhd_ctx* c, const double* U, double* P)
     if (rc)
         return rc;
     rc = timed(c, GRMHD_K_PRIM, [&] {
-        return grmhd::launch_prim(c->kind, U, P, c->Pc, c->d, c->cnt, c->stream);
+        return grmhd::launch_prim(c->kind, U, P, cache(c), c->d, c->cnt, c->stream);
     });
     if (rc)
         return rc;
@@ -311,16 +326,16 @@ int grmhd_rhs(grmhd_ctx* c, const double* P, double* R)
     if (rc)
         return rc;
     rc = timed(c, GRMHD_K_CONS, [&] {
-        return grmhd::launch_cons(c->kind, P, nullptr, c->Pc, c->d, c->stream);
+        return grmhd::launch_cons(c->kind, P, nullptr, cache(c), c->d, c->stream);
     });
     if (rc)
         return rc;
     c->cache_valid = true;
-    rc = fluxes(c);
+    rc = fluxes(c, cache(c), 3);
     if (rc)
         return rc;
     return timed(c, GRMHD_K_RHS, [&] {
-        return grmhd::launch_rhs(c->kind, c->F[0], c->F[1], c->F[2], c->Pc, R, c->d, c->stream);
+        return grmhd::launch_rhs(c->kind, c->F[0], c->F[1], c->F[2], cache(c), R, c->d, c->stream);
     });
 }
 
@@ -337,15 +352,24 @@ int grmhd_step(grmhd_ctx* c, double* U, double dt)
     const int ns = c->rk_order;
     const double* A = ns == 3 ? rk3a : rk2a;
     const double* B = ns == 3 ? rk3b : rk2b;
+    // 3D grids: the z faces are computed inside the fused update kernel, which
+    // writes the new primitives to the other cache; otherwise the update works
+    // in place on the cache with all face fluxes precomputed.
+    const bool zmarch = c->d.act[2] != 0;
     for (int s = 0; s < ns; ++s) {
-        int rc = fluxes(c);
+        double* src = zmarch ? c->Pbuf[s] : cache(c);
+        double* dst = zmarch ? c->Pbuf[s == ns - 1 ? 0 : s + 1] : cache(c);
+        int rc = fluxes(c, src, zmarch ? 2 : 3);
         if (rc)
             return rc;
         const double* Us = s == 0 ? U : c->Us;
         double* Uout = s == ns - 1 ? U : c->Us;
         rc = timed(c, GRMHD_K_UPDATE, [&] {
-            return grmhd::launch_update(c->kind, c->F[0], c->F[1], c->F[2], c->Pc, U, Us, Uout, c->d, dt,
-                                        A[s], B[s], c->cnt, c->stream);
+            if (zmarch)
+                return grmhd::launch_update_zmarch(c->kind, c->F[0], c->F[1], src, dst, U, Us, Uout,
+                                                   c->d, dt, A[s], B[s], c->cnt, c->stream);
+            return grmhd::launch_update(c->kind, c->F[0], c->F[1], c->F[2], src, U, Us, Uout, c->d,
+                                        dt, A[s], B[s], c->cnt, c->stream);
         });
         if (rc)
             return rc;

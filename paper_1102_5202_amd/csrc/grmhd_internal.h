@@ -23,6 +23,10 @@ hipError_t launch_flux(int kind, int dir, const double* Pc, double* F, const Dev
 hipError_t launch_update(int kind, const double* Fx, const double* Fy, const double* Fz, double* Pc,
                          const double* Un, const double* Us, double* Uout, const Dev& d, double dt,
                          double a, double b, unsigned long long* cnt, hipStream_t s);
+hipError_t launch_update_zmarch(int kind, const double* Fx, const double* Fy, const double* Pc,
+                                double* Pn, const double* Un, const double* Us, double* Uout,
+                                const Dev& d, double dt, double a, double b, unsigned long long* cnt,
+                                hipStream_t s);
 hipError_t launch_rhs(int kind, const double* Fx, const double* Fy, const double* Fz, const double* Pc,
                       double* R, const Dev& d, hipStream_t s);
 hipError_t launch_cons(int kind, const double* P, double* U, double* Pc, const Dev& d, hipStream_t s);

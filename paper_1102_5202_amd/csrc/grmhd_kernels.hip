@@ -2,7 +2,8 @@
 //
 // One substep (section 2.2 of the paper) is
 //   k_ghosts  : ghost zones of the primitive cache (periodic / zero-gradient)
-//   k_flux<D> : per face along axis D: MC reconstruction of the 9 primitives,
+//   k_flux_x, k_flux_march<D>: per face along axis D: MC reconstruction of the
+//               9 primitives,
 //               exact (normal field, Phi) cleaning pair, face physics of both
 //               states, HLLE flux (section 3.2)
 //   k_update  : per cell: flux differences + metric sources (eq. 2), SSP
@@ -16,6 +17,18 @@
 namespace grmhd {
 
 static constexpr int BLOCK = 256;
+static constexpr int NXCD = 8;   // accelerator complexes (each with its own L2)
+
+// Workgroups are dispatched round-robin over the XCDs: physical block b runs on
+// XCD b mod 8.  Give each XCD a contiguous range of logical blocks instead, so
+// that neighbouring rows (the y stencil, the second y face of a cell) are read
+// through the same L2.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ long long xcd_block()
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q = nb / NXCD, r = nb % NXCD, x = b % NXCD;
+    return (long long)(x * q + (x < r ? x : r) + b / NXCD);
+}
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_fill(double* __restrict__ p, long long n, double v)
@@ -77,33 +90,13 @@ __global__ __launch_bounds__(BLOCK) void k_ghosts(double* __restrict__ Pc, Dev d
 }
 
 // ---------------------------------------------------------------------------
+// Face solver: from the reconstructed left/right primitives at a face along D
+// (positions x, y, z), the 9 components Fo of the numerical flux: exact
+// (Bd^n, Phi) cleaning pair, then HLLE on the rest.
 template <int D, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_flux(const double* __restrict__ Pc, double* __restrict__ F,
-                                               Dev d)
+__device__ __forceinline__ void face_flux(double* qL, double* qR, double x, double y, double z,
+                                          const Dev& d, double* Fo)
 {
-    long long f = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (f >= d.nf[D])
-        return;
-    const int nfx = d.n[0] + (D == 0), nfy = d.n[1] + (D == 1);
-    int i = (int)(f % nfx);
-    long long t = f / nfx;
-    int j = (int)(t % nfy);
-    int k = (int)(t / nfy);
-    const long long st = D == 0 ? 1 : (D == 1 ? (long long)d.px : (long long)d.px * d.py);
-    // cell f-2 along D, in ghosted coordinates
-    long long base = ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + (i + d.g[0]) - 2 * st;
-
-    double qL[9], qR[9];
-#pragma unroll
-    for (int v = 0; v < 9; ++v) {
-        const double* p = Pc + v * d.sv + base;
-        double q0 = p[0], q1 = p[st], q2 = p[2 * st], q3 = p[3 * st];
-        qL[v] = q1 + 0.5 * mc_slope(q0, q1, q2);
-        qR[v] = q2 - 0.5 * mc_slope(q1, q2, q3);
-    }
-    double x = d.lo[0] + (D == 0 ? (double)i : i + 0.5) * d.dx[0];
-    double y = d.lo[1] + (D == 1 ? (double)j : j + 0.5) * d.dx[1];
-    double z = d.lo[2] + (D == 2 ? (double)k : k + 0.5) * d.dx[2];
     Geo g = geo_at<KIND>(d, x, y, z);
 
     // cleaning pair: exact solution of the linear (Bd^n, Phi) Riemann problem
@@ -134,7 +127,6 @@ __global__ __launch_bounds__(BLOCK) void k_flux(const double* __restrict__ Pc, d
         cR = -sl * inv;
         cU = sl * sr * inv;
     }
-    const long long NF = d.nf[D];
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         if (v == 5 + D)
@@ -144,13 +136,146 @@ __global__ __launch_bounds__(BLOCK) void k_flux(const double* __restrict__ Pc, d
         double o = cL * fl + cR * fr;
         if (cU != 0.0)
             o += cU * (cons_comp(v, qR, kR, g) - cons_comp(v, qL, kL, g));
-        F[v * NF + f] = o;
+        Fo[v] = o;
     }
-    F[(5 + D) * NF + f] = phs;
-    F[8 * NF + f] = d.c_h2 * Bs;
+    Fo[5 + D] = phs;
+    Fo[8] = d.c_h2 * Bs;
+}
+
+template <int D, int KIND>
+__device__ __forceinline__ void face_store(double* qL, double* qR, double x, double y, double z,
+                                           const Dev& d, double* __restrict__ F, long long NF,
+                                           long long f)
+{
+    double Fo[9];
+    face_flux<D, KIND>(qL, qR, x, y, z, d, Fo);
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        F[v * NF + f] = Fo[v];
+}
+
+// x faces: one thread per face (the x stencil of a wave shares cache lines).
+template <int KIND>
+__global__ __launch_bounds__(BLOCK) void k_flux_x(const double* __restrict__ Pc, double* __restrict__ F,
+                                                 Dev d)
+{
+    long long f = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (f >= d.nf[0])
+        return;
+    const int nfx = d.n[0] + 1;
+    int i = (int)(f % nfx);
+    long long t = f / nfx;
+    int j = (int)(t % d.n[1]);
+    int k = (int)(t / d.n[1]);
+    // cell i-2 in ghosted coordinates
+    long long base = ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + i + d.g[0] - 2;
+    double qL[9], qR[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        const double* p = Pc + v * d.sv + base;
+        double q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+        qL[v] = q1 + 0.5 * mc_slope(q0, q1, q2);
+        qR[v] = q2 - 0.5 * mc_slope(q1, q2, q3);
+    }
+    face_store<0, KIND>(qL, qR, d.lo[0] + i * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
+                        d.lo[2] + (k + 0.5) * d.dx[2], d, F, d.nf[0], f);
+}
+
+// y or z faces: a thread marches along D over a segment of up to SEG faces at
+// fixed (i, other transverse index).  Moving from face f-1/2 to f+1/2 it keeps
+// q_f, q_{f+1} and the MC slope of cell f, so each face loads one new cell
+// (9 values instead of 36) and computes one slope instead of two.
+template <int D, int KIND, int SEG>
+__global__ __launch_bounds__(BLOCK) void k_flux_march(const double* __restrict__ Pc,
+                                                     double* __restrict__ F, Dev d)
+{
+    constexpr int O = D == 1 ? 2 : 1;          // the other transverse axis
+    const int nfD = d.n[D] + 1;
+    const int nseg = (nfD + SEG - 1) / SEG;
+    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= (long long)d.n[0] * d.n[O] * nseg)
+        return;
+    int i = (int)(t % d.n[0]);
+    long long r = t / d.n[0];
+    int a = (int)(r % d.n[O]);
+    int seg = (int)(r / d.n[O]);
+    int f0 = seg * SEG;
+    int f1 = min(f0 + SEG, nfD);
+    const long long st = D == 1 ? (long long)d.px : (long long)d.px * d.py;
+    // ghosted address of cell (f0 - 2) along D
+    const int gi = i + d.g[0];
+    const int gj = D == 1 ? f0 - 2 + d.g[1] : a + d.g[1];
+    const int gk = D == 2 ? f0 - 2 + d.g[2] : a + d.g[2];
+    long long base = ((long long)gk * d.py + gj) * d.px + gi;
+    const long long NF = d.nf[D];
+    // face f index stride along D in the face array
+    const long long fstr = D == 1 ? (long long)d.n[0] : (long long)d.n[0] * d.n[1];
+    long long fidx = D == 1 ? i + (long long)d.n[0] * ((long long)f0 + (long long)(d.n[1] + 1) * a)
+                            : i + (long long)d.n[0] * (a + (long long)d.n[1] * f0);
+    double qb[9], qc[9], sc[9];      // cells f-1 and f, slope of cell f... set up below
+    {
+        double qa[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            const double* p = Pc + v * d.sv + base;
+            qa[v] = p[0];
+            qb[v] = p[st];
+            qc[v] = p[2 * st];
+        }
+        // carried state for face f0: (q_{f-1}, q_f) and the slope of cell f-1
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            sc[v] = mc_slope(qa[v], qb[v], qc[v]);
+    }
+    double xyz[3];
+    xyz[0] = d.lo[0] + (i + 0.5) * d.dx[0];
+    xyz[O] = d.lo[O] + (a + 0.5) * d.dx[O];
+    for (int f = f0; f < f1; ++f) {
+        // cell f+1 is 3 cells above cell f-2
+        const long long pf = base + (long long)(f - f0 + 3) * st;
+        double qL[9], qR[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            double qd = Pc[v * d.sv + pf];
+            double sn = mc_slope(qb[v], qc[v], qd);   // slope of cell f
+            qL[v] = qb[v] + 0.5 * sc[v];               // cell f-1, right face
+            qR[v] = qc[v] - 0.5 * sn;                  // cell f, left face
+            sc[v] = sn;
+            qb[v] = qc[v];
+            qc[v] = qd;
+        }
+        xyz[D] = d.lo[D] + f * d.dx[D];
+        face_store<D, KIND>(qL, qR, xyz[0], xyz[1], xyz[2], d, F, NF, fidx);
+        fidx += fstr;
+    }
 }
 
 // ---------------------------------------------------------------------------
+// Metric sources at a cell centre (x, y, z) with primitives q, added to R:
+// 1/2 sqrt(-g) [T^tt d_j g_tt + sum_k T^kk d_j g_kk] on the momenta (d_j g_tt =
+// -2 alpha d_j alpha), zero on mass and energy (static metric), -kappa Phi on
+// the cleaning scalar.  Returns the centre geometry in g.
+template <int KIND>
+__device__ __forceinline__ void add_sources(const Dev& d, double x, double y, double z,
+                                            const double* q, Geo& g, double* R)
+{
+    double ka, kp;
+    g = geo_deriv<KIND>(d, x, y, z, ka, kp);
+    if (KIND != FLAT) {
+        Kin kk = kinematics(q, g, d.gfac);
+        double ia2 = 1.0 / (g.alpha * g.alpha);
+        double Ttt = (kk.wtot * kk.W * kk.W - kk.ptot) * ia2 - kk.bt * kk.bt;
+        double uu = q[2] * q[2] + q[3] * q[3] + q[4] * q[4];
+        double bb = kk.b[0] * kk.b[0] + kk.b[1] * kk.b[1] + kk.b[2] * kk.b[2];
+        double Tkk = kk.wtot * uu + 3.0 * kk.ptot * g.ipsi4 - bb;
+        double K = 0.5 * g.sqrtmg * (-2.0 * g.alpha * Ttt * ka + Tkk * kp);
+        R[2] += K * x;
+        R[3] += K * y;
+        R[4] += K * z;
+    }
+    R[8] -= d.kappa * q[8];
+}
+
 // Flux differences + sources for cell c (i,j,k); q are its primitives.
 template <int KIND>
 __device__ __forceinline__ void rhs_cell(const Dev& d, const double* __restrict__ Fx,
@@ -179,25 +304,8 @@ __device__ __forceinline__ void rhs_cell(const Dev& d, const double* __restrict_
         for (int v = 0; v < 9; ++v)
             R[v] -= (Fz[v * d.nf[2] + c + nxy] - Fz[v * d.nf[2] + c]) * d.idx[2];
     }
-    double x = d.lo[0] + (i + 0.5) * d.dx[0];
-    double y = d.lo[1] + (j + 0.5) * d.dx[1];
-    double z = d.lo[2] + (k + 0.5) * d.dx[2];
-    double ka, kp;
-    g = geo_deriv<KIND>(d, x, y, z, ka, kp);
-    if (KIND != FLAT) {
-        // 1/2 sqrt(-g) [T^tt d_j g_tt + sum_k T^kk d_j g_kk], d_j g_tt = -2 alpha d_j alpha
-        Kin kk = kinematics(q, g, d.gfac);
-        double ia2 = 1.0 / (g.alpha * g.alpha);
-        double Ttt = (kk.wtot * kk.W * kk.W - kk.ptot) * ia2 - kk.bt * kk.bt;
-        double uu = q[2] * q[2] + q[3] * q[3] + q[4] * q[4];
-        double bb = kk.b[0] * kk.b[0] + kk.b[1] * kk.b[1] + kk.b[2] * kk.b[2];
-        double Tkk = kk.wtot * uu + 3.0 * kk.ptot * g.ipsi4 - bb;
-        double K = 0.5 * g.sqrtmg * (-2.0 * g.alpha * Ttt * ka + Tkk * kp);
-        R[2] += K * x;
-        R[3] += K * y;
-        R[4] += K * z;
-    }
-    R[8] -= d.kappa * q[8];
+    add_sources<KIND>(d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
+                      d.lo[2] + (k + 0.5) * d.dx[2], q, g, R);
 }
 
 __device__ __forceinline__ long long cache_index(const Dev& d, int i, int j, int k)
@@ -274,6 +382,147 @@ __global__ __launch_bounds__(BLOCK) void k_update(const double* __restrict__ Fx,
         }
     }
     count_flags(cnt, flags, iters);
+}
+
+// Per-thread counts (summed over the cells a thread updated) reduced over the
+// wave, one atomic per wave and counter into the block's slot.
+__device__ __forceinline__ void count_sums(unsigned long long* cnt_base, int nf, int na, int np,
+                                           int nb, int itmax)
+{
+    unsigned long long* cnt = cnt_base + (size_t)(blockIdx.x % CNT_SLOTS) * CNT_WORDS;
+    for (int o = 32; o > 0; o >>= 1) {
+        nf += __shfl_xor(nf, o);
+        na += __shfl_xor(na, o);
+        np += __shfl_xor(np, o);
+        nb += __shfl_xor(nb, o);
+        itmax = max(itmax, __shfl_xor(itmax, o));
+    }
+    unsigned long long act = __ballot(1);
+    if (__lane_id() == __ffsll((long long)act) - 1) {
+        if (nf)
+            atomicAdd(&cnt[CNT_FAIL], (unsigned long long)nf);
+        if (na)
+            atomicAdd(&cnt[CNT_ATM], (unsigned long long)na);
+        if (np)
+            atomicAdd(&cnt[CNT_PFLOOR], (unsigned long long)np);
+        if (nb)
+            atomicAdd(&cnt[CNT_FALLBACK], (unsigned long long)nb);
+        atomicMax(&cnt[CNT_MAXIT], (unsigned long long)itmax);
+    }
+}
+
+// z faces and the cell update fused (3D grids).  A thread owns cells
+// k0..k1-1 of the column (i, j), computes the z faces k0-1/2 .. k1-1/2 in
+// order (one face per cell plus one) keeping the previous face flux in
+// registers, and for each cell forms R from that z flux difference and the
+// x/y face fluxes, adds the sources, combines the RK stage and recovers the
+// primitives, written to the other primitive cache Pn (segments of one column
+// overlap by two cells, so the cache read here cannot be updated in place).
+template <int KIND, int SEG>
+__global__ __launch_bounds__(BLOCK) void k_update_zmarch(
+    const double* __restrict__ Fx, const double* __restrict__ Fy, const double* __restrict__ Pc,
+    double* __restrict__ Pn, const double* Un, const double* Us, double* Uout, Dev d, double dt,
+    double a, double b, unsigned long long* __restrict__ cnt)
+{
+    const int nz = d.n[2];
+    const int nseg = (nz + SEG - 1) / SEG;
+    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
+    if (t < (long long)d.n[0] * d.n[1] * nseg) {
+        const int i = (int)(t % d.n[0]);
+        const long long r = t / d.n[0];
+        const int j = (int)(r % d.n[1]);
+        const int seg = (int)(r / d.n[1]);
+        const int k0 = seg * SEG;
+        const int k1 = min(k0 + SEG, nz);
+        const long long st = (long long)d.px * d.py;
+        const long long col = (long long)(j + d.g[1]) * d.px + i + d.g[0];
+        // ghosted address of cell k0 - 2
+        const long long base = col + (long long)(k0 - 2 + d.g[2]) * st;
+        const double x = d.lo[0] + (i + 0.5) * d.dx[0];
+        const double y = d.lo[1] + (j + 0.5) * d.dx[1];
+        double qb[9], qc[9], sc[9], Fp[9];
+        {
+            double qa[9], qL[9], qR[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                const double* p = Pc + v * d.sv + base;
+                qa[v] = p[0];
+                qb[v] = p[st];
+                qc[v] = p[2 * st];
+            }
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                double qd = Pc[v * d.sv + base + 3 * st];
+                double s0 = mc_slope(qa[v], qb[v], qc[v]);   // cell k0-1
+                double s1 = mc_slope(qb[v], qc[v], qd);      // cell k0
+                qL[v] = qb[v] + 0.5 * s0;
+                qR[v] = qc[v] - 0.5 * s1;
+                sc[v] = s1;
+                qb[v] = qc[v];
+                qc[v] = qd;
+            }
+            face_flux<2, KIND>(qL, qR, x, y, d.lo[2] + k0 * d.dx[2], d, Fp);
+        }
+        // window now: qb = q_k0, qc = q_{k0+1}, sc = slope of cell k0
+        for (int k = k0; k < k1; ++k) {
+            double q[9], qL[9], qR[9], Fc[9];
+            const long long pnext = base + (long long)(k - k0 + 4) * st;   // cell k+2
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                double qd = Pc[v * d.sv + pnext];
+                double sn = mc_slope(qb[v], qc[v], qd);      // cell k+1
+                q[v] = qb[v];
+                qL[v] = qb[v] + 0.5 * sc[v];
+                qR[v] = qc[v] - 0.5 * sn;
+                sc[v] = sn;
+                qb[v] = qc[v];
+                qc[v] = qd;
+            }
+            const double z = d.lo[2] + (k + 0.5) * d.dx[2];
+            face_flux<2, KIND>(qL, qR, x, y, z + 0.5 * d.dx[2], d, Fc);
+            const long long c = i + (long long)d.n[0] * (j + (long long)d.n[1] * k);
+            double R[9], u[9], p[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                R[v] = -(Fc[v] - Fp[v]) * d.idx[2];
+                Fp[v] = Fc[v];
+            }
+            if (d.act[0]) {
+                long long f = i + (long long)(d.n[0] + 1) * (j + (long long)d.n[1] * k);
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    R[v] -= (Fx[v * d.nf[0] + f + 1] - Fx[v * d.nf[0] + f]) * d.idx[0];
+            }
+            if (d.act[1]) {
+                long long f = i + (long long)d.n[0] * (j + (long long)(d.n[1] + 1) * k);
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    R[v] -= (Fy[v * d.nf[1] + f + d.n[0]] - Fy[v * d.nf[1] + f]) * d.idx[1];
+            }
+            Geo g;
+            add_sources<KIND>(d, x, y, z, q, g, R);
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                double un = Un[v * d.N + c], us = Us[v * d.N + c];
+                u[v] = us + a * (un - us) + b * (dt * R[v]);
+            }
+            int iters = 0;
+            int flags = recover_cell(d, g, u, q, p, iters);
+            nfail += (flags & FLAG_FAIL) != 0;
+            natm += (flags & FLAG_ATM) != 0;
+            npf += (flags & FLAG_PFLOOR) != 0;
+            nfb += (flags & FLAG_FALLBACK) != 0;
+            itmax = max(itmax, iters);
+            const long long pc = col + (long long)(k + d.g[2]) * st;
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                Uout[v * d.N + c] = u[v];
+                Pn[v * d.sv + pc] = p[v];
+            }
+        }
+    }
+    count_sums(cnt, nfail, natm, npf, nfb, itmax);
 }
 
 template <int KIND>
@@ -399,16 +648,22 @@ hipError_t launch_ghosts(double* Pc, const Dev& d, hipStream_t s)
     return hipGetLastError();
 }
 
+static constexpr int MARCH_SEG = 8;
+
 template <int KIND>
 static hipError_t launch_flux_k(int dir, const double* Pc, double* F, const Dev& d, hipStream_t s)
 {
-    unsigned nb = blocks_for(d.nf[dir]);
-    if (dir == 0)
-        hipLaunchKernelGGL((k_flux<0, KIND>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
-    else if (dir == 1)
-        hipLaunchKernelGGL((k_flux<1, KIND>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
-    else
-        hipLaunchKernelGGL((k_flux<2, KIND>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+    if (dir == 0) {
+        hipLaunchKernelGGL(k_flux_x<KIND>, dim3(blocks_for(d.nf[0])), dim3(BLOCK), 0, s, Pc, F, d);
+    } else {
+        const int o = dir == 1 ? 2 : 1;
+        long long nseg = (d.n[dir] + 1 + MARCH_SEG - 1) / MARCH_SEG;
+        unsigned nb = blocks_for((long long)d.n[0] * d.n[o] * nseg);
+        if (dir == 1)
+            hipLaunchKernelGGL((k_flux_march<1, KIND, MARCH_SEG>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+        else
+            hipLaunchKernelGGL((k_flux_march<2, KIND, MARCH_SEG>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+    }
     return hipGetLastError();
 }
 
@@ -428,6 +683,24 @@ hipError_t launch_update(int kind, const double* Fx, const double* Fy, const dou
     else
         hipLaunchKernelGGL(k_update<ISO>, dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Un, Us, Uout, d,
                            dt, a, b, cnt);
+    return hipGetLastError();
+}
+
+static constexpr int ZSEG = 8;
+
+hipError_t launch_update_zmarch(int kind, const double* Fx, const double* Fy, const double* Pc,
+                                double* Pn, const double* Un, const double* Us, double* Uout,
+                                const Dev& d, double dt, double a, double b, unsigned long long* cnt,
+                                hipStream_t s)
+{
+    long long nseg = (d.n[2] + ZSEG - 1) / ZSEG;
+    unsigned nb = blocks_for((long long)d.n[0] * d.n[1] * nseg);
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_update_zmarch<FLAT, ZSEG>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn, Un,
+                           Us, Uout, d, dt, a, b, cnt);
+    else
+        hipLaunchKernelGGL((k_update_zmarch<ISO, ZSEG>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn, Un,
+                           Us, Uout, d, dt, a, b, cnt);
     return hipGetLastError();
 }
 
