@@ -10,11 +10,11 @@ is zone-updates per second per Runge-Kutta substep.  Prints one JSON line.
 
 Per-kernel durations come from HIP events the library records around each
 launch on its stream during the timed region.  The roofline entry is for the
-kernel with the largest total time; its algorithmic bytes per launch follow
-from the sizes below (flux kernels: read the primitives once, write 9 face
-values per face; update kernel: read 3x9 face values, the primitives, U^n and
-U^(s), write U^(s+1) and the primitives).  The CPU baseline times the plain
-oracle on one full RK step of the same workload on the host cores.
+kernel with the largest total time; its algorithmic bytes per launch are
+given by algorithmic_bytes() below, and the measured HBM traffic per launch
+(if profiles/traffic.json was taken on the current kernel sources) by two
+rocprofv3 counter runs.  The CPU baseline times the plain oracle on one full
+RK step of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -43,18 +43,26 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(kernel: str, n, nsub: int) -> float:
-    """Algorithmic HBM bytes of ONE launch of a kernel class on an n[0] x n[1] x n[2] grid."""
+    """Algorithmic HBM bytes of ONE launch of a kernel class on an n[0] x n[1] x n[2]
+    grid (3D), each value that has to cross HBM counted once:
+      flux_x / flux_y : the primitives once + one 9-value flux record per face;
+      update          : the x and y face records (one unique record per cell and
+                        axis), the primitives once (the z faces are computed in
+                        the kernel), U^n, U^(s) (not in the first substep, where it
+                        is U^n), U^(s+1) and the new primitives -- averaged over
+                        the substeps of a step;
+      bc              : read and write the 2-cell ghost slabs of the three axes."""
     N = n[0] * n[1] * n[2]
     w = 8.0 * 9                      # bytes of one 9-variable FP64 record
-    if kernel.startswith("flux_"):
+    if kernel in ("flux_x", "flux_y", "flux_z"):
         d = "xyz".index(kernel[-1])
         nf = N // n[d] * (n[d] + 1)
-        return w * N + w * nf        # primitives once + one flux record per face
+        return w * N + w * nf
     if kernel == "update":
-        # faces (one unique record per cell and axis) + primitives r/w + U^n + U^(s) + U^(s+1);
-        # averaged over the substeps (the first substep reads U^n only once)
+        fx = (n[0] + 1) / n[0]
+        fy = (n[1] + 1) / n[1]
         reads_us = (nsub - 1) / nsub
-        return w * N * (3 + 1 + 1 + reads_us + 1 + 1)
+        return w * N * (fx + fy + 1 + 1 + reads_us + 1 + 1)
     if kernel == "bc":
         g = 2
         return w * 2 * g * (n[1] * n[2] + n[0] * n[2] + n[0] * n[1]) * 2
@@ -84,8 +92,9 @@ def _read_csv(path):
 
 def _short(name: str) -> str:
     """Kernel class of a demangled kernel name."""
-    for key, short in (("k_flux<0", "flux_x"), ("k_flux<1", "flux_y"), ("k_flux<2", "flux_z"),
-                       ("k_update", "update"), ("k_ghosts", "bc"), ("k_cons", "cons"),
+    for key, short in (("k_flux_x", "flux_x"), ("k_flux_march<1", "flux_y"),
+                       ("k_flux_march<2", "flux_z"), ("k_update", "update"), ("k_ghosts", "bc"),
+                       ("k_cons", "cons"),
                        ("k_prim", "prim"), ("k_rhs", "rhs"), ("copyBuffer", "copy_probe")):
         if key in name:
             return short
