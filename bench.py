@@ -1,12 +1,16 @@
 """Benchmark of the GRMHD substep on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 192] [--no-cpu]
+                    [--precision both|fp64|mixed] [--accuracy-steps 200]
 
 Workload: the static curved-spacetime blob on [-20,20]^3 at 192^3 cells
-(isotropic Schwarzschild metric with softened radius, Gamma = 2, SSP-RK3,
-FP64), synthetic seeded initial data already resident in HBM.  A step is one
-full Runge-Kutta step (three substeps, every kernel of the path).  The metric
-is zone-updates per second per Runge-Kutta substep.  Prints one JSON line.
+(isotropic Schwarzschild metric with softened radius, Gamma = 2, SSP-RK3),
+synthetic seeded initial data already resident in HBM.  A step is one full
+Runge-Kutta step (three substeps, every kernel of the path).  The metric is
+zone-updates per second per Runge-Kutta substep.  Prints one JSON line: the
+headline value is the FP64 run; the "mixed" object holds the mixed-precision
+run of the same workload, its speedup over FP64 and its relative L1 distance
+from the FP64 state after --accuracy-steps steps.
 
 Per-kernel durations come from HIP events the library records around each
 launch on its stream during the timed region.  The roofline entry is for the
@@ -42,7 +46,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, n, nsub: int) -> float:
+def algorithmic_bytes(kernel: str, n, nsub: int, precision: str = "fp64") -> float:
     """Algorithmic HBM bytes of ONE launch of a kernel class on an n[0] x n[1] x n[2]
     grid (3D), each value that has to cross HBM counted once:
       flux_x / flux_y : the primitives once + one 9-value flux record per face;
@@ -51,9 +55,12 @@ def algorithmic_bytes(kernel: str, n, nsub: int) -> float:
                         the kernel), U^n, U^(s) (not in the first substep, where it
                         is U^n), U^(s+1) and the new primitives -- averaged over
                         the substeps of a step;
-      bc              : read and write the 2-cell ghost slabs of the three axes."""
+      bc              : read and write the 2-cell ghost slabs of the three axes.
+    In mixed precision the primitive caches and face records are FP32 and the
+    conserved arrays stay FP64."""
     N = n[0] * n[1] * n[2]
-    w = 8.0 * 9                      # bytes of one 9-variable FP64 record
+    wu = 8.0 * 9                     # bytes of one 9-variable FP64 record
+    w = wu if precision == "fp64" else 4.0 * 9
     if kernel in ("flux_x", "flux_y", "flux_z"):
         d = "xyz".index(kernel[-1])
         nf = N // n[d] * (n[d] + 1)
@@ -62,14 +69,14 @@ def algorithmic_bytes(kernel: str, n, nsub: int) -> float:
         fx = (n[0] + 1) / n[0]
         fy = (n[1] + 1) / n[1]
         reads_us = (nsub - 1) / nsub
-        return w * N * (fx + fy + 1 + 1 + reads_us + 1 + 1)
+        return N * (w * (fx + fy + 1 + 1) + wu * (1 + reads_us + 1))
     if kernel == "bc":
         g = 2
         return w * 2 * g * (n[1] * n[2] + n[0] * n[2] + n[0] * n[1]) * 2
     return float("nan")
 
 
-def load_traffic(kernel: str, workload: str):
+def load_traffic(kernel: str, workload: str, precision: str = "fp64"):
     """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
     (scaled by a copy-kernel calibration), if taken on the current sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -78,7 +85,7 @@ def load_traffic(kernel: str, workload: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    e = t.get(workload, {}).get(kernel)
+    e = t.get(workload, {}).get(precision, {}).get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
@@ -101,7 +108,8 @@ def _short(name: str) -> str:
     return name[:40]
 
 
-def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: str, out_json: str):
+def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: str, precision: str,
+                out_json: str):
     """Per-launch HBM bytes of each kernel class from two rocprofv3 --pmc runs
     (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled by what the same
     counter reads for the copy probe of known size (probe_bytes read and written)."""
@@ -118,8 +126,18 @@ def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: st
     # the probe is the largest copy dispatch (other copies are small host transfers)
     ff = (probe_bytes / 1024.0) / max(probe["FETCH_SIZE"])
     fw = (probe_bytes / 1024.0) / max(probe["WRITE_SIZE"])
-    res = {"calibration": {"probe_bytes": probe_bytes, "fetch_factor": ff, "write_factor": fw},
-           workload: {}}
+    try:
+        with open(out_json) as f:
+            res = json.load(f)
+    except (OSError, ValueError):
+        res = {}
+    res.setdefault(workload, {})
+    for k in list(res[workload]):             # entries of an older layout
+        if k not in ("fp64", "mixed"):
+            del res[workload][k]
+    res[workload][precision] = {}
+    res.setdefault("calibration", {})[workload + "/" + precision] = {
+        "probe_bytes": probe_bytes, "fetch_factor": ff, "write_factor": fw}
     for k, c in per.items():
         if k not in ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs"):
             continue
@@ -127,12 +145,42 @@ def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: st
             continue
         fk = sum(c["FETCH_SIZE"]) / len(c["FETCH_SIZE"])
         wk = sum(c["WRITE_SIZE"]) / len(c["WRITE_SIZE"])
-        res[workload][k] = {"fetch_KiB": fk, "write_KiB": wk,
+        res[workload][precision][k] = {"fetch_KiB": fk, "write_KiB": wk,
                             "bytes_per_launch": 1024.0 * (fk * ff + wk * fw),
                             "dispatches": len(c["FETCH_SIZE"]), "source_hash": kernel_source_hash()}
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)
     return res
+
+
+GROUPS = (("D", (0,)), ("tau", (1,)), ("S", (2, 3, 4)), ("B", (5, 6, 7)), ("Phi", (8,)))
+
+
+def accuracy(grmhd, w, P0, dev, nsteps):
+    """Relative L1 distance of the mixed-precision state from the FP64 state
+    after nsteps RK steps from the same initial data, per group of conserved
+    variables: sum |U_m - U_d| over the group's components divided by the
+    largest component L1 norm of the group in U_d.  "physical" is the maximum
+    over D, tau, S and the densitised field; Phi (the cleaning scalar, whose
+    size is set by the discretisation error of div B) is given apart."""
+    import torch
+    Us = {}
+    for prec in ("fp64", "mixed"):
+        s = grmhd.solver_for(w, device=dev, precision=prec)
+        U = s.cons(P0)
+        for _ in range(nsteps):
+            s.step(U, w.dt)
+        torch.cuda.synchronize()
+        Us[prec] = U
+        del s
+    a, b = Us["mixed"], Us["fp64"]
+    out = {}
+    for name, g in GROUPS:
+        num = sum(float((a[i] - b[i]).abs().sum()) for i in g)
+        den = max(float(b[i].abs().sum()) for i in g)
+        out[name] = num / den if den > 0 else num
+    out["physical"] = max(out[k] for k in ("D", "tau", "S", "B"))
+    return out
 
 
 def cpu_baseline(w, pb_kwargs):
@@ -159,6 +207,11 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--accuracy-steps", type=int, default=200,
+                    help="RK steps of the FP64-vs-mixed accuracy comparison")
+    ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both",
+                    help="which precisions to time (a counter run takes one); with --pmc-summary, "
+                         "the precision the counter files were taken on")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -168,8 +221,11 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
 
     if args.pmc_summary:
+        if args.precision == "both":
+            raise SystemExit("--pmc-summary needs --precision fp64 or mixed")
         res = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.probe_mib * 2 ** 20,
-                          "curved_blob_%d^3" % args.n, os.path.join(ROOT, "profiles", "traffic.json"))
+                          "curved_blob_%d^3" % args.n, args.precision,
+                          os.path.join(ROOT, "profiles", "traffic.json"))
         print(json.dumps(res, indent=1))
         return 0
 
@@ -194,67 +250,81 @@ def main(argv=None) -> int:
         del a, b
     w = workloads.config3(n=args.n, nsteps=args.steps)
     wl_name = "curved_blob_%d^3" % args.n
-    s = grmhd.solver_for(w, device=dev, timing=not args.no_timing)
-    P = torch.from_numpy(w.P).to(dev)
-    U = s.cons(P)
-    for _ in range(args.warmup):
-        s.step(U, w.dt)
-    torch.cuda.synchronize()
-    s.timing(reset=True)
-    s.status(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step(U, w.dt)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    ms_step = 1e3 * elapsed / args.steps
     nsub = w.rk_order
-    value = w.ncell * nsub * args.steps / elapsed
-    st = s.status()
-    finite = bool(torch.isfinite(U).all().item())
+    P0 = torch.from_numpy(w.P).to(dev)
 
-    kernels = {}
-    roof = None
-    if not args.no_timing:
-        tm = s.timing()
-        for k, (ms, cnt) in tm.items():
-            if cnt:
-                avg = ms / cnt
-                b = algorithmic_bytes(k, w.n, nsub)
-                kernels[k] = {"launches": cnt, "total_ms": round(ms, 4), "avg_ms": round(avg, 5),
-                              "alg_GBps": round(b / (avg * 1e-3) / 1e9, 1) if b == b else None}
-        dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-        avg_s = kernels[dom]["avg_ms"] * 1e-3
-        b = algorithmic_bytes(dom, w.n, nsub)
-        achieved = b / avg_s / 1e9
-        traffic = load_traffic(dom, wl_name)
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "alg_bytes_per_launch": b}
+    def timed_run(precision):
+        s = grmhd.solver_for(w, device=dev, timing=not args.no_timing, precision=precision)
+        U = s.cons(P0)
+        for _ in range(args.warmup):
+            s.step(U, w.dt)
+        torch.cuda.synchronize()
+        s.timing(reset=True)
+        s.status(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s.step(U, w.dt)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        r = {"value": w.ncell * nsub * args.steps / elapsed,
+             "ms_per_step": 1e3 * elapsed / args.steps,
+             "recovery": s.status(), "finite": bool(torch.isfinite(U).all().item()),
+             "kernels": {}, "roofline": None}
+        if not args.no_timing:
+            kernels = r["kernels"]
+            for k, (ms, cnt) in s.timing().items():
+                if cnt:
+                    avg = ms / cnt
+                    bk = algorithmic_bytes(k, w.n, nsub, precision)
+                    kernels[k] = {"launches": cnt, "total_ms": round(ms, 4), "avg_ms": round(avg, 5),
+                                  "alg_GBps": round(bk / (avg * 1e-3) / 1e9, 1) if bk == bk else None}
+            dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+            bk = algorithmic_bytes(dom, w.n, nsub, precision)
+            achieved = bk / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
+            r["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "traffic": load_traffic(dom, wl_name, precision),
+                             "alg_bytes_per_launch": bk}
+        del U, s
+        return r
+
+    fp64 = timed_run("fp64") if args.precision != "mixed" else None
+    mixed = timed_run("mixed") if args.precision != "fp64" else None
+    if fp64 and mixed:
+        mixed["speedup_vs_fp64"] = round(mixed["value"] / fp64["value"], 3)
+        if args.accuracy_steps > 0:
+            acc = accuracy(grmhd, w, P0, dev, args.accuracy_steps)
+            mixed["rel_l1_vs_fp64"] = acc["physical"]
+            mixed["rel_l1_vs_fp64_groups"] = acc
+            mixed["rel_l1_steps"] = args.accuracy_steps
+    main = fp64 or mixed
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main["value"],
         "unit": "zone-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if fp64 else "f32+f64 (mixed)",
         "data": "synthetic (seeded initial data)",
         "config": {"workload": wl_name + " static curved spacetime (isotropic Schwarzschild, "
-                   "r_s = sqrt(r^2+1)), [-20,20]^3, Gamma=2, SSP-RK3, FP64",
+                   "r_s = sqrt(r^2+1)), [-20,20]^3, Gamma=2, SSP-RK3, "
+                   + ("FP64" if fp64 else "mixed precision"),
                    "cells": w.ncell, "substeps_per_step": nsub, "dt": w.dt},
-        "roofline": roof,
-        "kernels": kernels,
-        "recovery": st,
-        "finite": finite,
+        "roofline": main["roofline"],
+        "kernels": main["kernels"],
+        "recovery": main["recovery"],
+        "finite": main["finite"],
+        "mixed": mixed if fp64 else None,
     }
+    finite = all(r["finite"] for r in (fp64, mixed) if r)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, w.problem_kwargs())
     print(json.dumps(out), flush=True)

@@ -63,7 +63,13 @@ typedef enum { GRMHD_METRIC_FLAT = 0, GRMHD_METRIC_ISO_SCHW = 1 } grmhd_metric_k
 typedef enum { GRMHD_SOFT_SQRT = 0, GRMHD_SOFT_MAX = 1 } grmhd_soft_kind;
 typedef enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1 } grmhd_bc_kind;
 typedef enum { GRMHD_EOS_IDEAL = 0 } grmhd_eos_kind;
-typedef enum { GRMHD_FP64 = 0 } grmhd_precision;
+/* FP64: every step in double.  MIXED: the primitive caches, reconstruction,
+ * face physics, HLLE fluxes and sources in float (the FP32 scheme of the paper,
+ * section 3.2), with the metric evaluated in double and rounded once, and the
+ * Runge-Kutta accumulation, the conserved variables and the primitive
+ * recovery in double (the paper runs the recovery in double precision even in
+ * single-precision runs, section 3.2).  User arrays are double in both. */
+typedef enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 } grmhd_precision;
 
 /* The fixed, given spacetime (section 2.1).  FLAT is Minkowski space.
  * ISO_SCHW is the Schwarzschild metric in isotropic coordinates, static and
@@ -99,7 +105,7 @@ typedef struct {
 /* Scheme options and the caller's workspace. */
 typedef struct {
     int rk_order;          /* 2 (SSP-RK2) or 3 (SSP-RK3, the order of section 3.2) */
-    int precision;         /* grmhd_precision (FP64 only) */
+    int precision;         /* grmhd_precision */
     double c_h;            /* cleaning speed, > 0 (1 if 0 is given) */
     double kappa;          /* cleaning damping rate, >= 0 */
     double rho_atm;        /* atmosphere density (absolute), > 0 */

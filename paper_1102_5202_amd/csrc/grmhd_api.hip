@@ -48,7 +48,7 @@ bool grid_ok(const grmhd_grid* g)
     return true;
 }
 
-Layout make_layout(const grmhd_grid* g)
+Layout make_layout(const grmhd_grid* g, size_t esize)
 {
     Layout L{};
     for (int d = 0; d < 3; ++d)
@@ -71,16 +71,22 @@ Layout make_layout(const grmhd_grid* g)
     for (int b = 0; b < 3; ++b) {
         L.off_pc[b] = off;
         if (b == 0 || g->n[2] > 1)   // the extra caches serve the fused 3D update only
-            off = round_up(off + sizeof(double) * 9 * (size_t)L.sv, 256);
+            off = round_up(off + esize * 9 * (size_t)L.sv, 256);
     }
     L.off_us = off;
     off = round_up(off + sizeof(double) * 9 * (size_t)L.N, 256);
     for (int d = 0; d < 3; ++d) {
         L.off_f[d] = off;
-        off = round_up(off + sizeof(double) * 9 * (size_t)L.nf[d], 256);
+        off = round_up(off + esize * 9 * (size_t)L.nf[d], 256);
     }
     L.total = off;
     return L;
+}
+
+// bytes of one value of the primitive caches and face buffers
+size_t elem_size(const grmhd_opts* o)
+{
+    return o && o->precision == GRMHD_MIXED ? sizeof(float) : sizeof(double);
 }
 
 }  // namespace
@@ -96,9 +102,10 @@ struct grmhd_ctx {
     // A 3D step rotates through all three (RK3: 0 -> 1 -> 2 -> 0, RK2: 0 -> 1
     // -> 0) so that every substep writes a cache it does not read and the step
     // ends in Pbuf[0] (a captured step can be replayed).
-    double* Pbuf[3] = {nullptr, nullptr, nullptr};
+    void* Pbuf[3] = {nullptr, nullptr, nullptr};
     double* Us = nullptr;
-    double* F[3] = {nullptr, nullptr, nullptr};
+    void* F[3] = {nullptr, nullptr, nullptr};
+    bool mixed = false;                     // float caches and face physics
     unsigned long long* cnt = nullptr;
     bool prepared = false;
     bool cache_valid = false;
@@ -147,9 +154,10 @@ int timed(grmhd_ctx* c, int kind, Fn&& f)
     return GRMHD_OK;
 }
 
-// First enqueuing call: clear the counters and poison the cache with NaN so
+// First enqueuing call: clear the counters and poison the caches with NaN so
 // that a read outside the stencil (edges, corners, pitch padding) shows up.
-int prepare(grmhd_ctx* c)
+template <typename T>
+int prepare_t(grmhd_ctx* c)
 {
     if (c->prepared)
         return GRMHD_OK;
@@ -157,19 +165,27 @@ int prepare(grmhd_ctx* c)
         return GRMHD_ERR_HIP;
     for (int b = 0; b < 3; ++b)
         if (c->d.act[2] || b == 0)
-            if (grmhd::launch_fill(c->Pbuf[b], 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
+            if (grmhd::launch_fill((T*)c->Pbuf[b], 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
                 return GRMHD_ERR_HIP;
     c->prepared = true;
     return GRMHD_OK;
 }
 
-double* cache(grmhd_ctx* c)
+template <typename T>
+T* cache(grmhd_ctx* c, int b = 0)
 {
-    return c->Pbuf[0];
+    return (T*)c->Pbuf[b];
+}
+
+template <typename T>
+T* faces(grmhd_ctx* c, int d)
+{
+    return (T*)c->F[d];
 }
 
 // Ghost fill of the cache P and the face fluxes of the active axes up to ndir.
-int fluxes(grmhd_ctx* c, double* P, int ndir)
+template <typename T>
+int fluxes(grmhd_ctx* c, T* P, int ndir)
 {
     int rc = timed(c, GRMHD_K_BC, [&] { return grmhd::launch_ghosts(P, c->d, c->stream); });
     if (rc)
@@ -178,7 +194,93 @@ int fluxes(grmhd_ctx* c, double* P, int ndir)
         if (!c->d.act[dir])
             continue;
         rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
-            return grmhd::launch_flux(c->kind, dir, P, c->F[dir], c->d, c->stream);
+            return grmhd::launch_flux(c->kind, dir, (const T*)P, faces<T>(c, dir), c->d, c->stream);
+        });
+        if (rc)
+            return rc;
+    }
+    return GRMHD_OK;
+}
+
+template <typename T>
+int cons_t(grmhd_ctx* c, const double* P, double* U)
+{
+    int rc = prepare_t<T>(c);
+    if (rc)
+        return rc;
+    rc = timed(c, GRMHD_K_CONS, [&] { return grmhd::launch_cons(c->kind, P, U, cache<T>(c), c->d, c->stream); });
+    if (rc)
+        return rc;
+    c->cache_valid = true;
+    return GRMHD_OK;
+}
+
+template <typename T>
+int prim_t(grmhd_ctx* c, const double* U, double* P)
+{
+    int rc = prepare_t<T>(c);
+    if (rc)
+        return rc;
+    rc = timed(c, GRMHD_K_PRIM, [&] {
+        return grmhd::launch_prim(c->kind, U, P, cache<T>(c), c->d, c->cnt, c->stream);
+    });
+    if (rc)
+        return rc;
+    c->cache_valid = true;
+    return GRMHD_OK;
+}
+
+template <typename T>
+int rhs_t(grmhd_ctx* c, const double* P, double* R)
+{
+    int rc = prepare_t<T>(c);
+    if (rc)
+        return rc;
+    rc = timed(c, GRMHD_K_CONS, [&] {
+        return grmhd::launch_cons(c->kind, P, (double*)nullptr, cache<T>(c), c->d, c->stream);
+    });
+    if (rc)
+        return rc;
+    c->cache_valid = true;
+    rc = fluxes<T>(c, cache<T>(c), 3);
+    if (rc)
+        return rc;
+    return timed(c, GRMHD_K_RHS, [&] {
+        return grmhd::launch_rhs(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
+                                 (const T*)faces<T>(c, 2), (const T*)cache<T>(c), R, c->d, c->stream);
+    });
+}
+
+template <typename T>
+int step_t(grmhd_ctx* c, double* U, double dt)
+{
+    static const double rk3a[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double rk3b[3] = {1.0, 0.25, 2.0 / 3.0};
+    static const double rk2a[2] = {0.0, 0.5};
+    static const double rk2b[2] = {1.0, 0.5};
+    const int ns = c->rk_order;
+    const double* A = ns == 3 ? rk3a : rk2a;
+    const double* B = ns == 3 ? rk3b : rk2b;
+    // 3D grids: the z faces are computed inside the fused update kernel, which
+    // writes the new primitives to another cache; otherwise the update works
+    // in place on the cache with all face fluxes precomputed.
+    const bool zmarch = c->d.act[2] != 0;
+    for (int s = 0; s < ns; ++s) {
+        T* src = zmarch ? cache<T>(c, s) : cache<T>(c);
+        T* dst = zmarch ? cache<T>(c, s == ns - 1 ? 0 : s + 1) : cache<T>(c);
+        int rc = fluxes<T>(c, src, zmarch ? 2 : 3);
+        if (rc)
+            return rc;
+        const double* Us = s == 0 ? U : c->Us;
+        double* Uout = s == ns - 1 ? U : c->Us;
+        rc = timed(c, GRMHD_K_UPDATE, [&] {
+            if (zmarch)
+                return grmhd::launch_update_zmarch(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
+                                                   (const T*)src, dst, U, Us, Uout, c->d, dt, A[s], B[s],
+                                                   c->cnt, c->stream);
+            return grmhd::launch_update(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
+                                        (const T*)faces<T>(c, 2), src, U, Us, Uout, c->d, dt, A[s], B[s],
+                                        c->cnt, c->stream);
         });
         if (rc)
             return rc;
@@ -192,10 +294,9 @@ extern "C" {
 
 size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_opts* opts)
 {
-    (void)opts;
     if (!grid_ok(grid))
         return 0;
-    return make_layout(grid).total;
+    return make_layout(grid, elem_size(opts)).total;
 }
 
 int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
@@ -218,13 +319,13 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
         return GRMHD_ERR_ARG;
     if (opts->rk_order != 2 && opts->rk_order != 3)
         return GRMHD_ERR_ARG;
-    if (opts->precision != GRMHD_FP64)
+    if (opts->precision != GRMHD_FP64 && opts->precision != GRMHD_MIXED)
         return GRMHD_ERR_ARG;
     if (opts->c_h < 0.0 || opts->kappa < 0.0 || !(opts->rho_atm > 0.0))
         return GRMHD_ERR_ARG;
     if (opts->newton_tol < 0.0 || opts->newton_maxit < 0)
         return GRMHD_ERR_ARG;
-    Layout L = make_layout(grid);
+    Layout L = make_layout(grid, elem_size(opts));
     if (!opts->workspace || opts->workspace_bytes < L.total)
         return GRMHD_ERR_WORKSPACE;
     if (((uintptr_t)opts->workspace) % 256 != 0)
@@ -237,6 +338,7 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     c->kind = metric->kind == GRMHD_METRIC_FLAT ? grmhd::FLAT : grmhd::ISO;
     c->rk_order = opts->rk_order;
     c->timing = opts->timing;
+    c->mixed = opts->precision == GRMHD_MIXED;
     Dev& d = c->d;
     for (int a = 0; a < 3; ++a) {
         d.n[a] = grid->n[a];
@@ -272,10 +374,10 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     c->ws = (unsigned char*)opts->workspace;
     c->cnt = (unsigned long long*)(c->ws + L.off_cnt);
     for (int b = 0; b < 3; ++b)
-        c->Pbuf[b] = (double*)(c->ws + L.off_pc[b]);
+        c->Pbuf[b] = (void*)(c->ws + L.off_pc[b]);
     c->Us = (double*)(c->ws + L.off_us);
     for (int a = 0; a < 3; ++a)
-        c->F[a] = L.nf[a] ? (double*)(c->ws + L.off_f[a]) : nullptr;
+        c->F[a] = L.nf[a] ? (void*)(c->ws + L.off_f[a]) : nullptr;
     *out = c;
     return GRMHD_OK;
 }
@@ -292,89 +394,30 @@ int grmhd_cons(grmhd_ctx* c, const double* P, double* U)
 {
     if (!c || !P || !U)
         return GRMHD_ERR_ARG;
-    int rc = prepare(c);
-    if (rc)
-        return rc;
-    rc = timed(c, GRMHD_K_CONS, [&] { return grmhd::launch_cons(c->kind, P, U, cache(c), c->d, c->stream); });
-    if (rc)
-        return rc;
-    c->cache_valid = true;
-    return GRMHD_OK;
+    return c->mixed ? cons_t<float>(c, P, U) : cons_t<double>(c, P, U);
 }
 
 int grmhd_prim(grmhd_ctx* c, const double* U, double* P)
 {
     if (!c || !U || !P)
         return GRMHD_ERR_ARG;
-    int rc = prepare(c);
-    if (rc)
-        return rc;
-    rc = timed(c, GRMHD_K_PRIM, [&] {
-        return grmhd::launch_prim(c->kind, U, P, cache(c), c->d, c->cnt, c->stream);
-    });
-    if (rc)
-        return rc;
-    c->cache_valid = true;
-    return GRMHD_OK;
+    return c->mixed ? prim_t<float>(c, U, P) : prim_t<double>(c, U, P);
 }
 
 int grmhd_rhs(grmhd_ctx* c, const double* P, double* R)
 {
     if (!c || !P || !R)
         return GRMHD_ERR_ARG;
-    int rc = prepare(c);
-    if (rc)
-        return rc;
-    rc = timed(c, GRMHD_K_CONS, [&] {
-        return grmhd::launch_cons(c->kind, P, nullptr, cache(c), c->d, c->stream);
-    });
-    if (rc)
-        return rc;
-    c->cache_valid = true;
-    rc = fluxes(c, cache(c), 3);
-    if (rc)
-        return rc;
-    return timed(c, GRMHD_K_RHS, [&] {
-        return grmhd::launch_rhs(c->kind, c->F[0], c->F[1], c->F[2], cache(c), R, c->d, c->stream);
-    });
+    return c->mixed ? rhs_t<float>(c, P, R) : rhs_t<double>(c, P, R);
 }
 
 int grmhd_step(grmhd_ctx* c, double* U, double dt)
 {
-    static const double rk3a[3] = {0.0, 0.75, 1.0 / 3.0};
-    static const double rk3b[3] = {1.0, 0.25, 2.0 / 3.0};
-    static const double rk2a[2] = {0.0, 0.5};
-    static const double rk2b[2] = {1.0, 0.5};
     if (!c || !U || !std::isfinite(dt))
         return GRMHD_ERR_ARG;
     if (!c->cache_valid)
         return GRMHD_ERR_STATE;
-    const int ns = c->rk_order;
-    const double* A = ns == 3 ? rk3a : rk2a;
-    const double* B = ns == 3 ? rk3b : rk2b;
-    // 3D grids: the z faces are computed inside the fused update kernel, which
-    // writes the new primitives to the other cache; otherwise the update works
-    // in place on the cache with all face fluxes precomputed.
-    const bool zmarch = c->d.act[2] != 0;
-    for (int s = 0; s < ns; ++s) {
-        double* src = zmarch ? c->Pbuf[s] : cache(c);
-        double* dst = zmarch ? c->Pbuf[s == ns - 1 ? 0 : s + 1] : cache(c);
-        int rc = fluxes(c, src, zmarch ? 2 : 3);
-        if (rc)
-            return rc;
-        const double* Us = s == 0 ? U : c->Us;
-        double* Uout = s == ns - 1 ? U : c->Us;
-        rc = timed(c, GRMHD_K_UPDATE, [&] {
-            if (zmarch)
-                return grmhd::launch_update_zmarch(c->kind, c->F[0], c->F[1], src, dst, U, Us, Uout,
-                                                   c->d, dt, A[s], B[s], c->cnt, c->stream);
-            return grmhd::launch_update(c->kind, c->F[0], c->F[1], c->F[2], src, U, Us, Uout, c->d,
-                                        dt, A[s], B[s], c->cnt, c->stream);
-        });
-        if (rc)
-            return rc;
-    }
-    return GRMHD_OK;
+    return c->mixed ? step_t<float>(c, U, dt) : step_t<double>(c, U, dt);
 }
 
 int grmhd_status(grmhd_ctx* c, grmhd_stats* st, int reset)

@@ -108,18 +108,43 @@ __device__ __forceinline__ Geo geo_deriv(const Dev& d, double x, double y, doubl
     return g;
 }
 
-// Fluid-frame quantities of one state (W, b^mu, enthalpies).
-struct Kin {
-    double W, bt, b[3], b2, w, wtot, ptot;
+// The face physics below is written for a scalar type T: double for the FP64
+// path, float for the mixed-precision path (reconstruction, face physics,
+// HLLE and sources in FP32; the metric is evaluated in FP64 and rounded once;
+// the Runge-Kutta accumulation and the recovery stay in FP64).  Every literal
+// is a T so that no expression silently promotes to double.
+template <typename T>
+struct GeoT {
+    T alpha, psi4, ipsi4, sqrtg, sqrtmg, isqrtmg;
 };
 
-__device__ __forceinline__ Kin kinematics(const double* q, const Geo& g, double gfac)
+template <typename T>
+__device__ __forceinline__ GeoT<T> geo_cast(const Geo& g)
 {
-    Kin k;
-    double u0 = q[2], u1 = q[3], u2 = q[4];
-    double B0 = q[5], B1 = q[6], B2 = q[7];
-    k.W = sqrt(1.0 + g.psi4 * (u0 * u0 + u1 * u1 + u2 * u2));
-    double f = g.alpha / k.W;                      // 1/u^t
+    GeoT<T> r;
+    r.alpha = (T)g.alpha;
+    r.psi4 = (T)g.psi4;
+    r.ipsi4 = (T)g.ipsi4;
+    r.sqrtg = (T)g.sqrtg;
+    r.sqrtmg = (T)g.sqrtmg;
+    r.isqrtmg = (T)g.isqrtmg;
+    return r;
+}
+
+// Fluid-frame quantities of one state (W, b^mu, enthalpies).
+template <typename T>
+struct Kin {
+    T W, bt, b[3], b2, w, wtot, ptot;
+};
+
+template <typename T>
+__device__ __forceinline__ Kin<T> kinematics(const T* q, const GeoT<T>& g, T gfac)
+{
+    Kin<T> k;
+    T u0 = q[2], u1 = q[3], u2 = q[4];
+    T B0 = q[5], B1 = q[6], B2 = q[7];
+    k.W = sqrt(T(1) + g.psi4 * (u0 * u0 + u1 * u1 + u2 * u2));
+    T f = g.alpha / k.W;                      // 1/u^t
     k.bt = g.psi4 * (B0 * u0 + B1 * u1 + B2 * u2); // b^t = B^i u_i
     k.b[0] = (B0 + k.bt * u0) * f;                 // b^i = (B^i + b^t u^i)/u^t
     k.b[1] = (B1 + k.bt * u1) * f;
@@ -127,34 +152,34 @@ __device__ __forceinline__ Kin kinematics(const double* q, const Geo& g, double 
     k.b2 = (g.psi4 * (B0 * B0 + B1 * B1 + B2 * B2) + k.bt * k.bt) * f * f;
     k.w = q[0] + gfac * q[1];
     k.wtot = k.w + k.b2;
-    k.ptot = q[1] + 0.5 * k.b2;
+    k.ptot = q[1] + T(0.5) * k.b2;
     return k;
 }
 
 // Extreme signal speeds along axis D: the dispersion relation with the
 // isotropic fast speed c^2 = (gamma p + b^2)/(w + b^2), solved in closed form.
-template <int D>
-__device__ __forceinline__ void speeds(const double* q, const Kin& k, const Geo& g, double gamma,
-                                       double& lm, double& lp)
+template <int D, typename T>
+__device__ __forceinline__ void speeds(const T* q, const Kin<T>& k, const GeoT<T>& g, T gamma, T& lm,
+                                       T& lp)
 {
-    double inv = 1.0 / k.wtot;
-    double c2 = (k.b2 + gamma * q[1]) * inv;
-    double a = (k.w - gamma * q[1]) * inv;         // 1 - c^2
-    double qi = q[2 + D];
-    double den = k.W * k.W * a + c2;
-    double disc = c2 * (den * g.ipsi4 - qi * qi * a);
-    double s = sqrt(fmax(disc, 0.0));
-    double t = g.alpha / den;
-    double m = k.W * qi * a;
+    T inv = T(1) / k.wtot;
+    T c2 = (k.b2 + gamma * q[1]) * inv;
+    T a = (k.w - gamma * q[1]) * inv;         // 1 - c^2
+    T qi = q[2 + D];
+    T den = k.W * k.W * a + c2;
+    T disc = c2 * (den * g.ipsi4 - qi * qi * a);
+    T s = sqrt(fmax(disc, T(0)));
+    T t = g.alpha / den;
+    T m = k.W * qi * a;
     lp = (m + s) * t;
     lm = (m - s) * t;
 }
 
 // Component v (0..7, not the normal field) of the physical flux along D.
-template <int D>
-__device__ __forceinline__ double flux_comp(int v, const double* q, const Kin& k, const Geo& g)
+template <int D, typename T>
+__device__ __forceinline__ T flux_comp(int v, const T* q, const Kin<T>& k, const GeoT<T>& g)
 {
-    double uD = q[2 + D];
+    T uD = q[2 + D];
     switch (v) {
     case 0:
         return g.sqrtmg * q[0] * uD;
@@ -164,7 +189,7 @@ __device__ __forceinline__ double flux_comp(int v, const double* q, const Kin& k
     case 3:
     case 4: {
         int j = v - 2;
-        double t = g.psi4 * (k.wtot * uD * q[2 + j] - k.b[D] * k.b[j]);
+        T t = g.psi4 * (k.wtot * uD * q[2 + j] - k.b[D] * k.b[j]);
         if (j == D)
             t += k.ptot;
         return g.sqrtmg * t;
@@ -177,7 +202,8 @@ __device__ __forceinline__ double flux_comp(int v, const double* q, const Kin& k
 }
 
 // Component v (0..7) of the conserved variables.
-__device__ __forceinline__ double cons_comp(int v, const double* q, const Kin& k, const Geo& g)
+template <typename T>
+__device__ __forceinline__ T cons_comp(int v, const T* q, const Kin<T>& k, const GeoT<T>& g)
 {
     switch (v) {
     case 0:
@@ -197,11 +223,12 @@ __device__ __forceinline__ double cons_comp(int v, const double* q, const Kin& k
 }
 
 // MC-limited slope: minmod(2 dq-, (dq- + dq+)/2, 2 dq+).
-__device__ __forceinline__ double mc_slope(double qm, double q0, double qp)
+template <typename T>
+__device__ __forceinline__ T mc_slope(T qm, T q0, T qp)
 {
-    double dl = q0 - qm, dr = qp - q0, dc = 0.5 * (qp - qm);
-    double s = fmin(fmin(2.0 * fabs(dl), 2.0 * fabs(dr)), fabs(dc));
-    return (dl * dr > 0.0) ? copysign(s, dc) : 0.0;
+    T dl = q0 - qm, dr = qp - q0, dc = T(0.5) * (qp - qm);
+    T s = fmin(fmin(T(2) * fabs(dl), T(2) * fabs(dr)), fabs(dc));
+    return (dl * dr > T(0)) ? copysign(s, dc) : T(0);
 }
 
 // A class test, not arithmetic: with FMA contraction "x - x" may be evaluated
@@ -496,10 +523,11 @@ __device__ __forceinline__ int recover_cell(const Dev& d, const Geo& g, double* 
         p[1] = d.p_atm;
     }
     if (flags & (FLAG_FAIL | FLAG_ATM | FLAG_PFLOOR)) {
-        Kin k = kinematics(p, g, d.gfac);
+        GeoT<double> gd = geo_cast<double>(g);
+        Kin<double> k = kinematics(p, gd, d.gfac);
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-            u[v] = cons_comp(v, p, k, g);
+            u[v] = cons_comp(v, p, k, gd);
     }
     return flags;
 }

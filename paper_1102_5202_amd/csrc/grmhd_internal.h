@@ -16,21 +16,30 @@ enum { CNT_FAIL = 0, CNT_ATM = 1, CNT_PFLOOR = 2, CNT_FALLBACK = 3, CNT_MAXIT = 
 enum { CNT_SLOTS = 256 };
 static constexpr size_t CNT_BYTES = sizeof(unsigned long long) * CNT_WORDS * CNT_SLOTS;
 
-hipError_t launch_fill(double* p, long long n, double v, hipStream_t s);
+// Launchers; T (double or float) is the type of the primitive caches and the
+// face-flux buffers.  Conserved variables and U arrays are always double.
+template <typename T>
+hipError_t launch_fill(T* p, long long n, double v, hipStream_t s);
 hipError_t launch_zero_counters(unsigned long long* cnt, hipStream_t s);
-hipError_t launch_ghosts(double* Pc, const Dev& d, hipStream_t s);
-hipError_t launch_flux(int kind, int dir, const double* Pc, double* F, const Dev& d, hipStream_t s);
-hipError_t launch_update(int kind, const double* Fx, const double* Fy, const double* Fz, double* Pc,
-                         const double* Un, const double* Us, double* Uout, const Dev& d, double dt,
-                         double a, double b, unsigned long long* cnt, hipStream_t s);
-hipError_t launch_update_zmarch(int kind, const double* Fx, const double* Fy, const double* Pc,
-                                double* Pn, const double* Un, const double* Us, double* Uout,
-                                const Dev& d, double dt, double a, double b, unsigned long long* cnt,
-                                hipStream_t s);
-hipError_t launch_rhs(int kind, const double* Fx, const double* Fy, const double* Fz, const double* Pc,
-                      double* R, const Dev& d, hipStream_t s);
-hipError_t launch_cons(int kind, const double* P, double* U, double* Pc, const Dev& d, hipStream_t s);
-hipError_t launch_prim(int kind, const double* U, double* P, double* Pc, const Dev& d,
-                       unsigned long long* cnt, hipStream_t s);
+template <typename T>
+hipError_t launch_ghosts(T* Pc, const Dev& d, hipStream_t s);
+template <typename T>
+hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipStream_t s);
+template <typename T>
+hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, T* Pc, const double* Un,
+                         const double* Us, double* Uout, const Dev& d, double dt, double a, double b,
+                         unsigned long long* cnt, hipStream_t s);
+template <typename T>
+hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc, T* Pn, const double* Un,
+                                const double* Us, double* Uout, const Dev& d, double dt, double a,
+                                double b, unsigned long long* cnt, hipStream_t s);
+template <typename T>
+hipError_t launch_rhs(int kind, const T* Fx, const T* Fy, const T* Fz, const T* Pc, double* R,
+                      const Dev& d, hipStream_t s);
+template <typename T>
+hipError_t launch_cons(int kind, const double* P, double* U, T* Pc, const Dev& d, hipStream_t s);
+template <typename T>
+hipError_t launch_prim(int kind, const double* U, double* P, T* Pc, const Dev& d, unsigned long long* cnt,
+                       hipStream_t s);
 
 }  // namespace grmhd

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_PKG, "libgrmhd.so")
 FLAT, ISO_SCHW = 0, 1
 SOFT_SQRT, SOFT_MAX = 0, 1
 PERIODIC, OUTFLOW = 0, 1
-FP64 = 0
+FP64, MIXED = 0, 1
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 KERNELS = ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs")
 NVAR = 9
 
@@ -103,8 +104,10 @@ def make_grid(n, lo, hi, bc) -> Grid:
     return g
 
 
-def workspace_bytes(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0, 0, 0)) -> int:
-    return int(load().grmhd_workspace_bytes(C.byref(make_grid(n, lo, hi, bc)), None))
+def workspace_bytes(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0, 0, 0), precision="fp64") -> int:
+    o = Opts()
+    o.precision = PRECISIONS[precision]
+    return int(load().grmhd_workspace_bytes(C.byref(make_grid(n, lo, hi, bc)), C.byref(o)))
 
 
 class Solver:
@@ -113,12 +116,13 @@ class Solver:
 
     Tensors are float64, contiguous, shape (9, nz, ny, nx), on the solver's
     device: P = (rho, p, u~x, u~y, u~z, Bx, By, Bz, Phi),
-    U = (D, tau, Sx, Sy, Sz, Bdx, Bdy, Bdz, Phi)."""
+    U = (D, tau, Sx, Sy, Sz, Bdx, Bdy, Bdz, Phi).  precision "fp64" or
+    "mixed" (float face physics and caches, double accumulation and recovery)."""
 
     def __init__(self, n, lo, hi, bc, metric=FLAT, M=0.0, soft=SOFT_SQRT, r_min=1.0,
                  gamma=5.0 / 3.0, K=0.0, rk_order=3, c_h=1.0, kappa=1.0, rho_atm=1e-12,
                  p_atm=1e-12, newton_tol=1e-12, newton_maxit=50, timing=False, device="cuda",
-                 stream=None):
+                 stream=None, precision="fp64"):
         L = load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -128,14 +132,19 @@ class Solver:
         self._grid = make_grid(n, lo, hi, bc)
         self._metric = Metric(int(metric), int(soft), float(M), float(r_min))
         self._eos = Eos(0, float(gamma), float(K))
-        nbytes = int(L.grmhd_workspace_bytes(C.byref(self._grid), None))
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
+        self.precision = precision
+        self._opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa),
+                          float(rho_atm), float(p_atm), float(newton_tol), int(newton_maxit),
+                          int(bool(timing)), None, 0)
+        nbytes = int(L.grmhd_workspace_bytes(C.byref(self._grid), C.byref(self._opts)))
         if nbytes == 0:
             raise ValueError("invalid grid")
         # torch's caching allocator returns 512-byte aligned blocks
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self._opts = Opts(int(rk_order), FP64, float(c_h), float(kappa), float(rho_atm),
-                          float(p_atm), float(newton_tol), int(newton_maxit), int(bool(timing)),
-                          C.c_void_p(self.workspace.data_ptr()), nbytes)
+        self._opts.workspace = C.c_void_p(self.workspace.data_ptr())
+        self._opts.workspace_bytes = nbytes
         ctx = C.c_void_p()
         _check(L.grmhd_init(C.byref(ctx), C.byref(self._metric), C.byref(self._grid),
                             C.byref(self._eos), C.byref(self._opts)), "grmhd_init")

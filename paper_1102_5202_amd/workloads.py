@@ -306,3 +306,69 @@ def pulse_1d(n: int, v: float = 0.5, amp: float = 0.5, axis: int = 0, p: float =
     P[5 + axis] = bx
     return Workload(name="pulse_%d" % n, P=P, n=tuple(nn), lo=(0.0,) * 3, hi=(1.0,) * 3,
                     bc=(PERIODIC,) * 3, gamma=gamma, rk_order=3, dt=0.4 / n, nsteps=0)
+
+
+# -----------------------------------------------------------------------------
+# inputs of the derivative checks
+
+def smooth_box(n=(8, 7, 6), k: int = 0, metric: int = FLAT, rk_order: int = 2,
+               lo=None, hi=None, nsteps: int = 2) -> Workload:
+    """Smooth data monotone along every axis in every variable (a seeded linear
+    profile plus a small quadratic), outflow boundaries, Gamma = 4/3.  The MC
+    slopes then stay on their central branch away from the boundary cells, so
+    that finite differences of the step converge.  metric ISO_SCHW puts the box
+    off the origin at [2,4]x[1,3]x[1.5,3.5] with M = 1."""
+    rng = rng_for(40, k)
+    nn = tuple(int(v) for v in n)
+    if lo is None:
+        lo = (2.0, 1.0, 1.5) if metric == ISO_SCHW else (0.0, 0.0, 0.0)
+    if hi is None:
+        hi = (4.0, 3.0, 3.5) if metric == ISO_SCHW else (1.0, 1.0, 1.0)
+    X = centres(nn, lo, hi)
+    t = [np.broadcast_to((X[d] - lo[d]) / (hi[d] - lo[d]), (nn[2], nn[1], nn[0])) for d in range(3)]
+    base = (1.0, 0.1, 0.05, -0.04, 0.03, 0.1, 0.05, 0.02, 0.01)
+    P = np.empty((9, nn[2], nn[1], nn[0]))
+    for v in range(9):
+        a = rng.uniform(0.5, 1.0, 3) * rng.choice([-1.0, 1.0], 3)
+        sc = 0.2 * base[v] if v < 2 else 0.3 * abs(base[v])
+        P[v] = base[v] + sc * (a[0] * t[0] + a[1] * t[1] + a[2] * t[2]
+                               + 0.1 * (t[0] * t[1] + t[2] * t[2]))
+    return Workload(name="smooth_box_%dx%dx%d" % nn, P=P, n=nn, lo=tuple(lo), hi=tuple(hi),
+                    bc=(OUTFLOW,) * 3, gamma=4.0 / 3.0, rk_order=rk_order,
+                    dt=cfl_dt(nn, lo, hi), nsteps=nsteps, metric=metric,
+                    M=1.0 if metric == ISO_SCHW else 0.0)
+
+
+def config4(n=64, k: int = 0, nsteps: int = 50) -> Workload:
+    """The adjoint workload: the periodic flat box of config2 (RK2) run for
+    nsteps, with a seeded target density rho_t = 1 + 0.1 sum of 16 other
+    Fourier modes (extra["target"]); the loss is sum (rho(T) - rho_t)^2."""
+    w = config2(n=n, k=k, nsteps=nsteps)
+    rng = rng_for(4, k)
+    nn = w.n
+    X = centres(nn, w.lo, w.hi)
+    ks = _modes(rng, 16, 4)
+    ph = rng.uniform(0.0, 2 * np.pi, 16)
+    am = rng.uniform(-1.0, 1.0, 16)
+    am /= np.abs(am).sum()
+    f = 0.0
+    for m in range(16):
+        f = f + am[m] * np.cos(2 * np.pi * (ks[m, 0] * X[0] + ks[m, 1] * X[1] + ks[m, 2] * X[2])
+                               + ph[m])
+    w.extra["target"] = np.ascontiguousarray(
+        np.broadcast_to(1.0 + 0.1 * f, (nn[2], nn[1], nn[0])))
+    w.name = "adjoint_periodic_%dx%dx%d" % nn
+    return w
+
+
+def direction(w: Workload, i: int, k: int = 0) -> np.ndarray:
+    """Seeded direction i in primitive space for directional-derivative
+    checks: standard normal values scaled per variable by the largest
+    magnitude of that variable in w.P.  Variables uniform in w.P are left
+    unperturbed: every MC slope of a uniform field sits on the limiter's kink
+    (both one-sided differences zero), where the step has no derivative."""
+    rng = np.random.default_rng(SEED_BASE + 41000 + 100 * k + i)
+    flat = w.P.reshape(9, -1)
+    scale = np.abs(flat).max(axis=1)
+    scale[flat.max(axis=1) == flat.min(axis=1)] = 0.0
+    return rng.standard_normal(w.P.shape) * scale.reshape(9, 1, 1, 1)

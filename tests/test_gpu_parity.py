@@ -257,3 +257,83 @@ def test_graph_replay_matches_eager(G):
         se.step(Ue, w.dt)
         torch.cuda.synchronize()
         assert torch.equal(Ug, Ue), r
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 face physics and caches, FP64 accumulation and
+# recovery.  Bar: relative L1 <= 1e-5 against the FP64 oracle.
+
+MIXED_BAR = 1e-5
+
+
+@pytest.mark.parametrize("k", [0, 3, 6])
+def test_mixed_riemann_1d(G, orc, k):
+    w = WL.config1(k)
+    U, P, st, _ = gpu_run(G, w, w.nsteps, precision="mixed")
+    Ur, _, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say("mixed riemann k=%d rel-L1" % k, err[:8].max(), st)
+    assert np.all(err[:8] <= MIXED_BAR)
+    assert np.array_equal(U[5], Ur[5]) and np.all(U[8] == 0.0)     # Bx, Phi exact in 1D
+
+
+def test_mixed_periodic_flat_box(G, orc):
+    w = WL.config2(n=(33, 30, 28), nsteps=100)
+    U, P, st, _ = gpu_run(G, w, w.nsteps, precision="mixed")
+    Ur, _, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say("mixed periodic box rel-L1", err, st)
+    assert np.all(err <= MIXED_BAR)
+
+
+def test_mixed_curved_blob(G, orc):
+    w = WL.config3(n=(40, 36, 34), nsteps=20)
+    U, P, st, _ = gpu_run(G, w, w.nsteps, precision="mixed")
+    Ur, _, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say("mixed curved blob rel-L1", err, st, sto)
+    assert np.all(err <= MIXED_BAR)
+
+
+def test_mixed_rhs_is_single_precision_accurate(G, orc):
+    """One right-hand side in mixed precision.  FP32 face fluxes differenced
+    across a cell lose the digits of |F| / |dF|, about one to two here (the
+    energy flux carries the lapse-weighted rest mass), so the bar is 1e-4."""
+    w = WL.config3(n=(41, 35, 30))
+    s = G.solver_for(w, device=DEV, precision="mixed")
+    R = s.rhs(torch.from_numpy(w.P).to(DEV)).cpu().numpy()
+    Rr = orc.rhs(orc.Problem(**w.problem_kwargs()), w.P)
+    err = rel_l1(R, Rr)
+    say("mixed rhs rel-L1", err)
+    assert np.all(err <= 1e-4)
+
+
+def _group_l1(a, b):
+    out = {}
+    for name, g in (("D", (0,)), ("tau", (1,)), ("S", (2, 3, 4)), ("B", (5, 6, 7)), ("Phi", (8,))):
+        num = sum(float((a[i] - b[i]).abs().sum()) for i in g)
+        den = max(float(b[i].abs().sum()) for i in g)
+        out[name] = num / den
+    return out
+
+
+def test_mixed_periodic_box_128(G):
+    """The periodic box at its full size, 128^3 and 100 RK2 steps: mixed
+    against FP64 on the GPU (the FP64 path matches the oracle to 1e-15 at the
+    sizes the oracle runs in seconds).  Physical variables within 1e-5; Phi,
+    whose size is the discretisation error of div B, within 1e-3 (FP32
+    rounding of the cached field feeds its source)."""
+    w = WL.config2(n=128, nsteps=100)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = G.solver_for(w, device=DEV, precision=prec)
+        U = s.cons(torch.from_numpy(w.P).to(DEV))
+        for _ in range(w.nsteps):
+            s.step(U, w.dt)
+        torch.cuda.synchronize()
+        res[prec] = U
+        del s
+    err = _group_l1(res["mixed"], res["fp64"])
+    say("mixed periodic 128^3 rel-L1 by group", err)
+    assert max(err[k] for k in ("D", "tau", "S", "B")) <= 1e-5
+    assert err["Phi"] <= 1e-3

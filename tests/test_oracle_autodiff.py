@@ -1,0 +1,160 @@
+"""Pins of the differentiable oracle (oracle/grmhd_autodiff.py).
+
+Its forward map is checked against the C oracle (itself pinned by the physics
+tests), and its derivatives against central finite differences of the C
+oracle, which share no code with torch.autograd.  The step has kinks (the MC
+limiter's branches, the min/max of the HLLE signal speeds), so a finite
+difference converges only linearly in h when a kink falls inside the
+stencil; the step-level checks use smooth data that is monotone along every
+axis (the limiter stays on one branch), and bound the error at h = 1e-6 well
+below what a wrong or dropped term gives (1e-3 and more)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1102_5202_amd import workloads as WL
+
+
+@pytest.fixture(scope="module")
+def AD(orc):
+    from oracle import grmhd_autodiff
+    return grmhd_autodiff
+
+
+def _vary_all(P):
+    """config2 data with p and Phi made to vary along every axis."""
+    P = P.copy()
+    nz, ny, nx = P.shape[1:]
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    P[1] *= 1 + 0.05 * np.sin(2 * np.pi * X / nx + 0.4) * np.cos(2 * np.pi * Y / ny + 0.2) \
+        * np.cos(2 * np.pi * Z / nz + 0.7)
+    P[8] = 0.01 * np.cos(2 * np.pi * Z / nz + 0.3) * np.sin(2 * np.pi * Y / ny + 0.5) \
+        * np.cos(2 * np.pi * X / nx + 0.9)
+    return P
+
+
+CASES = [lambda: WL.config2(n=(10, 9, 8), nsteps=2), lambda: WL.config3(n=(12, 10, 9), nsteps=2),
+         lambda: WL.config1(2, n=64), lambda: WL.smooth_box(metric=WL.ISO_SCHW, rk_order=3)]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_forward_matches_c_oracle(orc, AD, case):
+    w = CASES[case]()
+    pb = orc.Problem(**w.problem_kwargs())
+    P = torch.from_numpy(w.P)
+    R, Rr = AD.rhs(pb, P).numpy(), orc.rhs(pb, w.P)
+    assert np.abs(R - Rr).max() <= 1e-13 * np.abs(Rr).max()
+    U0 = orc.prim2con(pb, w.P)
+    assert np.abs(AD.prim2con(pb, P).numpy() - U0).max() <= 1e-14 * np.abs(U0).max()
+    Ur, Pr, st = orc.step(pb, U0, w.P, w.dt, 2)
+    Ut, Pt = AD.step(pb, torch.from_numpy(U0), P, w.dt, 2)
+    assert np.all(orc.parity_error(Ut.numpy(), Ur) <= 1e-13)
+    assert np.all(orc.parity_error(Pt.numpy(), Pr) <= 1e-13)
+
+
+def test_rhs_vjp_matches_finite_differences(orc, AD):
+    """Right-hand side VJP, one primitive variable at a time."""
+    w = WL.config2(n=(8, 7, 6), nsteps=1)
+    P0 = _vary_all(w.P)
+    pb = orc.Problem(**w.problem_kwargs())
+    rng = np.random.default_rng(7)
+    lam = rng.standard_normal(P0.shape)
+    P = torch.from_numpy(P0.copy()).requires_grad_(True)
+    (AD.rhs(pb, P) * torch.from_numpy(lam)).sum().backward()
+    g = P.grad.numpy()
+    h = 1e-7
+    for v in range(9):
+        d = np.zeros_like(P0)
+        d[v] = rng.standard_normal(P0[v].shape) * np.abs(P0[v]).max()
+        fd = ((orc.rhs(pb, P0 + h * d) - orc.rhs(pb, P0 - h * d)) * lam).sum() / (2 * h)
+        an = (g * d).sum()
+        # rounding of the differenced sums is relative to the summed magnitudes
+        assert abs(fd - an) <= 1e-6 * np.abs(g * d).sum(), (v, fd, an)
+
+
+def _loss_grad(orc, AD, w, P0, tgt, nsteps):
+    pb = orc.Problem(**w.problem_kwargs())
+    P = torch.from_numpy(P0.copy()).requires_grad_(True)
+    U, Pf = AD.step(pb, AD.prim2con(pb, P), P, w.dt, nsteps)
+    L = ((Pf[0] - torch.from_numpy(tgt)) ** 2).sum()
+    L.backward()
+
+    def lc(Px):
+        U, Pq, st = orc.step(pb, orc.prim2con(pb, Px), Px, w.dt, nsteps)
+        return ((Pq[0] - tgt) ** 2).sum()
+    return L.item(), P.grad.numpy(), lc
+
+
+@pytest.mark.parametrize("metric,rk", [(WL.FLAT, 2), (WL.ISO_SCHW, 3)])
+def test_step_gradient_matches_finite_differences(orc, AD, metric, rk):
+    w = WL.smooth_box(metric=metric, rk_order=rk)
+    rng = np.random.default_rng(11)
+    tgt = w.P[0] * (1 + 0.01 * rng.standard_normal(w.P[0].shape))
+    L, g, lc = _loss_grad(orc, AD, w, w.P, tgt, 2)
+    assert abs(L - lc(w.P)) <= 1e-13 * L
+    for i in range(3):
+        d = WL.direction(w, i)
+        an = (g * d).sum()
+        e4 = abs((lc(w.P + 1e-4 * d) - lc(w.P - 1e-4 * d)) / 2e-4 - an)
+        e6 = abs((lc(w.P + 1e-6 * d) - lc(w.P - 1e-6 * d)) / 2e-6 - an)
+        assert e6 <= 2e-6 * abs(an), (i, e6 / abs(an))
+        assert e6 < e4
+
+
+def test_recovery_derivative_is_inverse_of_cons(orc, AD):
+    """dP/dU of the recovery times dU/dP is the identity (unfloored cells)."""
+    w = WL.smooth_box(n=(3, 2, 2), metric=WL.ISO_SCHW)
+    pb = orc.Problem(**w.problem_kwargs())
+    U0 = orc.prim2con(pb, w.P)
+    J = AD.cons_jacobian(pb, torch.from_numpy(w.P))            # [nz, ny, nx, 9, 9]
+    Pg = torch.from_numpy(w.P)
+    for c in range(9):
+        U = torch.from_numpy(U0.copy()).requires_grad_(True)
+        AD.recover(pb, U, Pg)[0][c].sum().backward()
+        row = U.grad.movedim(0, -1)                            # d P_c / d U_j per cell
+        # (dP/dU)(dU/dP) = I: row c times J is e_c in every cell
+        rJ = torch.einsum("...j,...jk->...k", row, J)
+        e = torch.zeros(9, dtype=torch.float64)
+        e[c] = 1.0
+        assert torch.allclose(rJ, e.expand_as(rJ), atol=1e-11, rtol=0)
+
+
+def test_recovery_derivative_with_floors(orc, AD):
+    """Atmosphere and pressure-floor cells: the derivative of the recovery
+    (and of the rebuilt conserved state) matches finite differences of the C
+    oracle's recovery along directions that keep every cell's floor flags."""
+    w = WL.smooth_box(n=(6, 5, 4))
+    pb = orc.Problem(**w.problem_kwargs())
+    Pm = w.P.copy()
+    Z, Y, X = np.meshgrid(*[np.arange(m) for m in Pm.shape[1:]], indexing="ij")
+    atm_cells = (X + 2 * Y + 3 * Z) % 3 == 0
+    pfl_cells = (X + 2 * Y + 3 * Z) % 3 == 1
+    Pm[0][atm_cells] = 0.5 * pb.rho_atm          # recovers below the atmosphere density
+    Pm[1][atm_cells] = pb.p_atm
+    for v in (2, 3, 4, 5, 6, 7):                 # slow and weakly magnetised (a recovery at
+        Pm[v][atm_cells] *= 1e-5                 # magnetisation b^2/rho ~ 1e10 fails)
+    Pm[1][pfl_cells] = 0.5 * pb.p_atm            # recovers below the pressure floor
+    for v in (2, 3, 4, 5, 6, 7):                 # at rest and unmagnetised, so that the
+        Pm[v][pfl_cells] = 0.0                   # pressure is well conditioned in U
+    U1 = orc.prim2con(pb, Pm)
+    P1, Ua, flags, st = orc.con2prim(pb, U1, Pm)
+    assert st["fail"] == 0
+    assert np.all(flags[atm_cells] & orc.FLAG_ATM)
+    assert np.all(flags[pfl_cells] == orc.FLAG_PFLOOR)
+    assert np.all(flags[~(atm_cells | pfl_cells)] == 0)
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal(U1.shape) * np.abs(U1)     # relative to each value
+    lamP = rng.standard_normal(U1.shape)
+    lamU = rng.standard_normal(U1.shape)
+    U = torch.from_numpy(U1.copy()).requires_grad_(True)
+    P, Ur = AD.recover(pb, U, torch.from_numpy(Pm))
+    ((P * torch.from_numpy(lamP)).sum() + (Ur * torch.from_numpy(lamU)).sum()).backward()
+    an = (U.grad.numpy() * d).sum()
+    h = 1e-7
+
+    def f(Ux):
+        Px, Uax, fl, _ = orc.con2prim(pb, Ux, Pm)
+        assert np.array_equal(fl, flags)
+        return (Px * lamP).sum() + (Uax * lamU).sum()
+    fd = (f(U1 + h * d) - f(U1 - h * d)) / (2 * h)
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
