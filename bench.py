@@ -52,12 +52,13 @@ def algorithmic_bytes(kernel: str, n, nsub: int, precision: str = "fp64") -> flo
       flux_x / flux_y : the primitives once + one 9-value flux record per face;
       update          : the x and y face records (one unique record per cell and
                         axis), the primitives once (the z faces are computed in
-                        the kernel), U^n, U^(s) (not in the first substep, where it
-                        is U^n), U^(s+1) and the new primitives -- averaged over
-                        the substeps of a step;
+                        the kernel) and the new primitives, U^n, the stage state
+                        U^s read (all substeps but the first, which reads U^n)
+                        and U^(s+1) written -- averaged over the substeps of a
+                        step;
       bc              : read and write the 2-cell ghost slabs of the three axes.
-    In mixed precision the primitive caches and face records are FP32 and the
-    conserved arrays stay FP64."""
+    In mixed precision the primitive caches, face records and the intermediate
+    stage state are FP32; U^n and the step's result U^(n+1) stay FP64."""
     N = n[0] * n[1] * n[2]
     wu = 8.0 * 9                     # bytes of one 9-variable FP64 record
     w = wu if precision == "fp64" else 4.0 * 9
@@ -68,8 +69,8 @@ def algorithmic_bytes(kernel: str, n, nsub: int, precision: str = "fp64") -> flo
     if kernel == "update":
         fx = (n[0] + 1) / n[0]
         fy = (n[1] + 1) / n[1]
-        reads_us = (nsub - 1) / nsub
-        return N * (w * (fx + fy + 1 + 1) + wu * (1 + reads_us + 1))
+        inner = (nsub - 1) / nsub            # substeps that read / write the stage state
+        return N * (w * (fx + fy + 1 + 1) + wu + w * inner + (w * inner + wu / nsub))
     if kernel == "bc":
         g = 2
         return w * 2 * g * (n[1] * n[2] + n[0] * n[2] + n[0] * n[1]) * 2
@@ -183,6 +184,59 @@ def accuracy(grmhd, w, P0, dev, nsteps):
     return out
 
 
+def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
+    """Cost of the adjoint on workload w (FP64): the mean duration of one
+    grmhd_step_adjoint (which recomputes the stages of its step) over that of
+    one grmhd_step, and the wall time of a whole gradient (forward evolution
+    with checkpoints every `every` steps, then the checkpointed reverse sweep)
+    over that of the forward evolution alone."""
+    import torch
+    from paper_1102_5202_amd.adjoint import evolve
+    s = grmhd.solver_for(w, device=dev, adjoint=True)
+    P0 = torch.from_numpy(w.P).to(dev)
+    U = s.cons(P0)
+    for _ in range(2):
+        s.step(U, w.dt)
+    torch.cuda.synchronize()
+    n = max(4, min(steps, 20))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        s.step(U, w.dt)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / n
+    Ub = torch.randn_like(U)
+    s.step_adjoint(U, Ub, w.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        s.step_adjoint(U, Ub, w.dt)
+    torch.cuda.synchronize()
+    t_adj = (time.perf_counter() - t0) / n
+    # whole gradient of sum (rho - rho_t)^2 after `steps` steps
+    tgt = torch.from_numpy(w.extra["target"]).to(dev) if "target" in w.extra else P0[0] * 1.01
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U = s.cons(P0)
+    for _ in range(steps):
+        s.step(U, w.dt)
+    s.prim(U)
+    torch.cuda.synchronize()
+    t_evo = time.perf_counter() - t0
+    Pq = P0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Pn = evolve(s, Pq, w.dt, steps, every)
+    ((Pn[0] - tgt) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    return {"workload": w.name, "steps": steps, "checkpoint_every": every,
+            "forward_step_ms": round(1e3 * t_fwd, 4), "adjoint_step_ms": round(1e3 * t_adj, 4),
+            "adjoint_over_forward": round(t_adj / t_fwd, 3),
+            "gradient_ms": round(1e3 * t_grad, 3), "forward_evolution_ms": round(1e3 * t_evo, 3),
+            "gradient_over_forward": round(t_grad / t_evo, 3),
+            "finite": bool(torch.isfinite(Pq.grad).all().item())}
+
+
 def cpu_baseline(w, pb_kwargs):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -207,6 +261,7 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--accuracy-steps", type=int, default=200,
                     help="RK steps of the FP64-vs-mixed accuracy comparison")
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both",
@@ -324,6 +379,9 @@ def main(argv=None) -> int:
         "finite": main["finite"],
         "mixed": mixed if fp64 else None,
     }
+    if not args.no_adjoint and fp64:
+        # the adjoint workload (64^3 periodic box, 50 RK2 steps, checkpoints every 10)
+        out["adjoint"] = adjoint_cost(grmhd, workloads.config4(n=64, nsteps=50), dev, 50, 10)
     finite = all(r["finite"] for r in (fp64, mixed) if r)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, w.problem_kwargs())

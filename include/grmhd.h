@@ -56,7 +56,8 @@ typedef enum {
     GRMHD_ERR_ARG = -1,        /* invalid argument (null pointer, bad size or option) */
     GRMHD_ERR_WORKSPACE = -2,  /* workspace missing or smaller than grmhd_workspace_bytes() */
     GRMHD_ERR_HIP = -3,        /* a HIP runtime call or kernel launch failed */
-    GRMHD_ERR_STATE = -4       /* call out of order (e.g. step before cons/prim) */
+    GRMHD_ERR_STATE = -4,      /* call out of order (e.g. step before cons/prim) */
+    GRMHD_ERR_NO_ADJOINT = -5  /* adjoint call on a context made without opts.adjoint (FP64) */
 } grmhd_error;
 
 typedef enum { GRMHD_METRIC_FLAT = 0, GRMHD_METRIC_ISO_SCHW = 1 } grmhd_metric_kind;
@@ -113,6 +114,7 @@ typedef struct {
     double newton_tol;     /* relative step tolerance of the recovery (1e-12 if 0) */
     int newton_maxit;      /* iteration cap of the recovery (50 if 0) */
     int timing;            /* nonzero: time every kernel launch with HIP events */
+    int adjoint;           /* nonzero: reserve the workspace of the adjoint calls (FP64 only) */
     void *workspace;       /* device memory, >= grmhd_workspace_bytes(), 256-byte aligned */
     size_t workspace_bytes;
 } grmhd_opts;
@@ -136,7 +138,11 @@ typedef enum {
     GRMHD_K_CONS = 5,     /* primitive -> conserved                          */
     GRMHD_K_PRIM = 6,     /* conserved -> primitive                          */
     GRMHD_K_RHS = 7,      /* flux divergence + sources only                  */
-    GRMHD_K_COUNT = 8
+    GRMHD_K_ADJ_REC = 8,  /* adjoint: recovery + Runge-Kutta combination     */
+    GRMHD_K_ADJ_FACE = 9, /* adjoint: face solver, one axis                  */
+    GRMHD_K_ADJ_GATHER = 10, /* adjoint: reconstruction, one axis           */
+    GRMHD_K_ADJ_FOLD = 11,   /* adjoint: ghost fold + sources               */
+    GRMHD_K_COUNT = 12
 } grmhd_kernel;
 
 typedef struct grmhd_ctx grmhd_ctx;
@@ -180,6 +186,86 @@ int grmhd_prim(grmhd_ctx *ctx, const double *U, double *P);
  * substep (compact form eq. 3) for the primitives P, written to R (device).
  * Loads P into the context's primitive cache, as grmhd_cons does. */
 int grmhd_rhs(grmhd_ctx *ctx, const double *P, double *R);
+
+/* ---- Adjoint (reverse mode) of the discrete update, FP64 ----------------
+ * The step is a map U^n -> U^(n+1) (with P^n the primitives of U^n).  The
+ * adjoint calls return vector-Jacobian products of that map and of the
+ * primitive/conserved conversions, for gradient-based inverse problems (the
+ * source-parameter problems of section 1).  They need a context created with
+ * opts.adjoint = 1 and precision FP64 (else GRMHD_ERR_NO_ADJOINT).
+ * Derivatives follow the branch each limiter, min/max and upwind choice took;
+ * the recovery is differentiated implicitly, dP/dU = (dU/dP)^-1 at the root;
+ * floors hold their values constant and the rebuild of a floored cell's
+ * conserved matter part is differentiated; a cell whose recovery failed keeps
+ * its previous hydrodynamic primitives, which carry no derivative.  The
+ * calls use only the adjoint part of the workspace: the forward state (the
+ * primitive cache) is left as it was. */
+
+/* Ubar <- (d U^(n+1) / d U^n)^T Ubar for one step of size dt from the state U
+ * (device, read only; U's primitives are recovered first, then the step's
+ * stages recomputed and reversed).  Ubar (device) is read and overwritten.
+ * Recovery events of the recomputation are counted as in grmhd_step(). */
+int grmhd_step_adjoint(grmhd_ctx *ctx, const double *U, double *Ubar, double dt);
+
+/* Pbar = (dU/dP)^T Ubar at the primitives P (the adjoint of grmhd_cons).
+ * All device arrays; Pbar is written. */
+int grmhd_cons_adjoint(grmhd_ctx *ctx, const double *P, const double *Ubar, double *Pbar);
+
+/* Ubar = (dP/dU)^T Pbar = (dU/dP)^-T Pbar at the primitives of U, recovered
+ * here (the adjoint of grmhd_prim).  All device arrays; Ubar is written. */
+int grmhd_prim_adjoint(grmhd_ctx *ctx, const double *U, const double *Pbar, double *Ubar);
+
+/* ---- Batched ensemble of independent 1D problems ------------------------
+ * Many uneven 1D problems along x (flat metric, the equations and scheme of
+ * the single-grid calls) advanced in ONE persistent kernel launch: one
+ * workgroup per problem runs all of that problem's steps, the FP32 (mixed)
+ * primitive row held in LDS when it fits.  Arrays are packed: problem b's
+ * 9 x n_b values (variable-major, index 9*off_b + v*n_b + i with off_b the
+ * sum of the earlier n) follow those of problem b-1; all device, double.
+ * The same ownership and error rules as the single-grid calls apply. */
+typedef struct {
+    int nprob;             /* number of problems, >= 1                          */
+    const int *n;          /* host array: cells of each problem, >= 2           */
+    const double *lo;      /* host arrays: domain [lo, hi] of each problem      */
+    const double *hi;
+    const double *dt;      /* host array: time step of each problem             */
+    const int *steps;      /* host array: steps each problem takes in all, >= 0 */
+    int bc;                /* grmhd_bc_kind at both ends of every problem       */
+} grmhd_batch_desc;
+
+typedef struct grmhd_batch grmhd_batch;
+
+/* Workspace bytes of a batch (opts: rk_order, precision; 0 if invalid). */
+size_t grmhd_batch_workspace_bytes(const grmhd_batch_desc *desc, const grmhd_opts *opts);
+
+/* Create a batch context (host only; the descriptor arrays are copied).
+ * opts as for grmhd_init (its adjoint and timing fields are ignored). */
+int grmhd_batch_init(grmhd_batch **b, const grmhd_batch_desc *desc, const grmhd_eos *eos,
+                     const grmhd_opts *opts);
+
+int grmhd_batch_set_stream(grmhd_batch *b, void *stream);
+
+/* Conserved from primitives for every problem (packed arrays); loads the
+ * primitive rows and resets every problem's step count to zero. */
+int grmhd_batch_cons(grmhd_batch *b, const double *P, double *U);
+
+/* Advance every problem by min(max_steps, steps left) steps of its own dt,
+ * in place on U, in one launch.  Asynchronous. */
+int grmhd_batch_evolve(grmhd_batch *b, double *U, int max_steps);
+
+/* Primitives from conserved variables for every problem (packed). */
+int grmhd_batch_prim(grmhd_batch *b, const double *U, double *P);
+
+/* Time each launch shape (workgroup size; LDS or global primitive rows) on
+ * trial_steps steps of copies of the current state (U and the rows are left
+ * as they are), keep the fastest for grmhd_batch_evolve, and report it in
+ * *shape (threads) and *lds when not NULL.  Synchronises. */
+int grmhd_batch_tune(grmhd_batch *b, const double *U, int trial_steps, int *threads, int *lds);
+
+/* As grmhd_status, for the batch. */
+int grmhd_batch_status(grmhd_batch *b, grmhd_stats *st, int reset);
+
+int grmhd_batch_free(grmhd_batch *b);
 
 /* Copy the device counters to *st (synchronises the stream); reset them to 0
  * afterwards when reset != 0. */

@@ -309,6 +309,20 @@ def recover(pb: Problem, U, Pguess):
     return P, U
 
 
+def primitives_of(pb: Problem, U, Pguess):
+    """The primitives of U at the start of a step, P^n = P(U^n): the value
+    of the C oracle's recovery (floors included; U itself is not rebuilt,
+    the state is taken as it stands) with the derivative of the exact
+    inverse, dP/dU = (dU/dP)^-1 at that value, in every cell."""
+    Ps, _, flags, _ = con2prim(pb, U.detach().numpy(), np.ascontiguousarray(Pguess.detach().numpy()))
+    if (flags & FLAG_FAIL).any():
+        raise ValueError("recovery failure: derivative not defined")
+    Pd = torch.from_numpy(Ps)
+    J = cons_jacobian(pb, Pd)
+    dU = (U - U.detach()).movedim(0, -1)
+    return Pd + torch.linalg.solve(J, dU.unsqueeze(-1)).squeeze(-1).movedim(-1, 0)
+
+
 RK = {2: ((0.0, 1.0), (0.5, 0.5)), 3: ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))}
 
 

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libgrmhd.so")
-SOURCES = ["grmhd_kernels.hip", "grmhd_api.hip"]
+SOURCES = ["grmhd_kernels.hip", "grmhd_adjoint.hip", "grmhd_api.hip", "grmhd_batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

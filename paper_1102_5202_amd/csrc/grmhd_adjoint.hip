@@ -1,0 +1,643 @@
+// grmhd_adjoint.hip -- reverse (adjoint) kernels of one SSP Runge-Kutta step,
+// FP64.
+//
+// Forward stage s:  U~^(s+1) = U^s + a_s (U^n - U^s) + b_s dt R(P^s),
+//                   (P^(s+1), U^(s+1)) = recovery of U~^(s+1) with floors
+//                   (a floored cell's conserved matter part is rebuilt).
+// Reverse, given the cotangents (Ub, Pb) of (U^(s+1), P^(s+1)):
+//   k_adj_rec      recovery adjoint (dU/dP)^-T at P^(s+1) (implicit function
+//                  theorem), floors as constants, the rebuild differentiated;
+//                  then the RK combination: Ub^s = (1 - a_s) Ub~, Ub^n += a_s Ub~,
+//                  Rb = b_s dt Ub~;
+//   k_adj_face<D>  per face along D: the flux cotangent (Rb_right - Rb_left)/dx
+//                  pulled back through HLLE, the cleaning pair and the face
+//                  physics to the reconstructed left/right states;
+//   k_adj_gather<D> per cell (ghosts included): the reconstructed-state
+//                  cotangents pulled back through the MC reconstruction;
+//   k_adj_fold     ghost cotangents added to the cells they copy, plus the
+//                  source-term cotangent: Pb^s.
+// At the step's start P^0 is the primitives of U^n; k_adj_final adds
+// (dU/dP)^-T Pb^0 and the accumulated Ub^n.
+#include "grmhd_adjoint.h"
+#include "grmhd_internal.h"
+
+namespace grmhd {
+
+static constexpr int ABLOCK = 256;
+
+static inline unsigned ablocks(long long n)
+{
+    return (unsigned)((n + ABLOCK - 1) / ABLOCK);
+}
+
+__device__ __forceinline__ long long ghosted(const Dev& d, int i, int j, int k)
+{
+    return ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + (i + d.g[0]);
+}
+
+__device__ __forceinline__ double3 centre(const Dev& d, int i, int j, int k)
+{
+    return make_double3(d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
+                        d.lo[2] + (k + 0.5) * d.dx[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of the face solver (face_flux of the forward kernels, FP64):
+// Fb (9) -> qLb, qRb (9 each, written).
+template <int D, int KIND>
+__device__ __forceinline__ void face_flux_rev(const double* qL0, const double* qR0, double x, double y,
+                                              double z, const Dev& d, const double* Fb, double* qLb,
+                                              double* qRb)
+{
+    const GeoT<double> g = geo_cast<double>(geo_at<KIND>(d, x, y, z));
+    double qL[9], qR[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        qL[v] = qL0[v];
+        qR[v] = qR0[v];
+    }
+    const double BnL = g.sqrtmg * qL[5 + D], BnR = g.sqrtmg * qR[5 + D];
+    const double Bs = 0.5 * (BnL + BnR) - 0.5 * d.ic_h * (qR[8] - qL[8]);
+    qL[5 + D] = qR[5 + D] = Bs * g.isqrtmg;
+    const Kin<double> kL = kinematics(qL, g, d.gfac);
+    const Kin<double> kR = kinematics(qR, g, d.gfac);
+    double lmL, lpL, lmR, lpR;
+    speeds<D>(qL, kL, g, d.gamma, lmL, lpL);
+    speeds<D>(qR, kR, g, d.gamma, lmR, lpR);
+    const double sl = fmin(0.0, fmin(lmL, lmR));
+    const double sr = fmax(0.0, fmax(lpL, lpR));
+    double cL, cR, cU;
+    const bool central = !(sl == 0.0) && !(sr == 0.0);
+    if (sl == 0.0) {
+        cL = 1.0;
+        cR = 0.0;
+        cU = 0.0;
+    } else if (sr == 0.0) {
+        cL = 0.0;
+        cR = 1.0;
+        cU = 0.0;
+    } else {
+        const double inv = 1.0 / (sr - sl);
+        cL = sr * inv;
+        cR = -sl * inv;
+        cU = sl * sr * inv;
+    }
+
+    double aL[9], aR[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        aL[v] = aR[v] = 0.0;
+    KinBar kLb = kin_zero(), kRb = kin_zero();
+    double cLb = 0.0, cRb = 0.0, cUb = 0.0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        if (v == 5 + D)
+            continue;
+        const double c = Fb[v];
+        if (central) {
+            cLb += c * flux_comp<D>(v, qL, kL, g);
+            cRb += c * flux_comp<D>(v, qR, kR, g);
+            cUb += c * (cons_comp(v, qR, kR, g) - cons_comp(v, qL, kL, g));
+        }
+        if (cL != 0.0)
+            flux_comp_rev<D>(v, qL, kL, g, cL * c, aL, kLb);
+        if (cR != 0.0)
+            flux_comp_rev<D>(v, qR, kR, g, cR * c, aR, kRb);
+        if (cU != 0.0) {
+            cons_comp_rev(v, qR, kR, g, cU * c, aR, kRb);
+            cons_comp_rev(v, qL, kL, g, -cU * c, aL, kLb);
+        }
+    }
+    if (central) {
+        // cL = sr/(sr-sl), cR = -sl/(sr-sl), cU = sl sr/(sr-sl)
+        const double i2 = 1.0 / ((sr - sl) * (sr - sl));
+        const double slb = (cLb * sr - cRb * sr + cUb * sr * sr) * i2;
+        const double srb = (-cLb * sl + cRb * sl - cUb * sl * sl) * i2;
+        // sl = min(0, lmL, lmR) < 0 and sr = max(0, lpL, lpR) > 0 here
+        const bool leftmin = lmL <= lmR, leftmax = lpL >= lpR;
+        speeds_rev<D>(qL, kL, g, d.gamma, leftmin ? slb : 0.0, leftmax ? srb : 0.0, aL, kLb);
+        speeds_rev<D>(qR, kR, g, d.gamma, leftmin ? 0.0 : slb, leftmax ? 0.0 : srb, aR, kRb);
+    }
+    kinematics_rev(qL, kL, g, d.gfac, kLb, aL);
+    kinematics_rev(qR, kR, g, d.gfac, kRb, aR);
+
+    // cleaning pair: Fo[5+D] = phi*, Fo[8] = c_h^2 Bd*, and both states carry
+    // B^n = Bd* / sqrt(-g)
+    const double phb = Fb[5 + D];
+    const double Bsb = d.c_h2 * Fb[8] + (aL[5 + D] + aR[5 + D]) * g.isqrtmg;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        qLb[v] = aL[v];
+        qRb[v] = aR[v];
+    }
+    qLb[5 + D] = 0.5 * g.sqrtmg * Bsb + 0.5 * d.c_h * g.sqrtmg * phb;
+    qRb[5 + D] = 0.5 * g.sqrtmg * Bsb - 0.5 * d.c_h * g.sqrtmg * phb;
+    qLb[8] += 0.5 * d.ic_h * Bsb + 0.5 * phb;
+    qRb[8] += -0.5 * d.ic_h * Bsb + 0.5 * phb;
+}
+
+// One thread per face along D.  Face f sits between cells f-1 and f; the
+// flux cotangent is (Rb_f - Rb_(f-1)) / dx with out-of-domain cells absent.
+template <int D, int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_face(const double* __restrict__ Pc,
+                                                      const double* __restrict__ Rb,
+                                                      double* __restrict__ FB, Dev d)
+{
+    const long long nf = d.nf[D];
+    const long long f = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (f >= nf)
+        return;
+    int m[3] = {d.n[0], d.n[1], d.n[2]};
+    m[D] += 1;
+    int fi[3];
+    fi[0] = (int)(f % m[0]);
+    const long long t = f / m[0];
+    fi[1] = (int)(t % m[1]);
+    fi[2] = (int)(t / m[1]);
+    const int fD = fi[D];
+    double Fb[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        Fb[v] = 0.0;
+    if (fD < d.n[D]) {
+        const long long c = fi[0] + (long long)d.n[0] * (fi[1] + (long long)d.n[1] * fi[2]);
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            Fb[v] += Rb[v * d.N + c] * d.idx[D];
+    }
+    if (fD > 0) {
+        int ci[3] = {fi[0], fi[1], fi[2]};
+        ci[D] -= 1;
+        const long long c = ci[0] + (long long)d.n[0] * (ci[1] + (long long)d.n[1] * ci[2]);
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            Fb[v] -= Rb[v * d.N + c] * d.idx[D];
+    }
+    int bi[3] = {fi[0], fi[1], fi[2]};
+    bi[D] -= 2;
+    const long long base = ghosted(d, bi[0], bi[1], bi[2]);
+    const long long st = D == 0 ? 1 : (D == 1 ? (long long)d.px : (long long)d.px * d.py);
+    double qL[9], qR[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        const double* p = Pc + v * d.sv + base;
+        const double q0 = p[0], q1 = p[st], q2 = p[2 * st], q3 = p[3 * st];
+        qL[v] = q1 + 0.5 * mc_slope(q0, q1, q2);
+        qR[v] = q2 - 0.5 * mc_slope(q1, q2, q3);
+    }
+    double pos[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        pos[e] = e == D ? d.lo[e] + fi[e] * d.dx[e] : d.lo[e] + (fi[e] + 0.5) * d.dx[e];
+    double qLb[9], qRb[9];
+    face_flux_rev<D, KIND>(qL, qR, pos[0], pos[1], pos[2], d, Fb, qLb, qRb);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        FB[v * nf + f] = qLb[v];
+        FB[(9 + v) * nf + f] = qRb[v];
+    }
+}
+
+// One thread per cell along D over -2 .. n+1 (the ghosts of axis D
+// included), interior along the other axes.  Writes the cotangent of the
+// cell's primitives from the faces along D into MU (ghosted layout):
+// assigned at ghost positions and, for the first active axis, at interior
+// ones; added at interior positions otherwise.
+template <int D>
+__global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict__ Pc,
+                                                        const double* __restrict__ FB,
+                                                        double* __restrict__ MU, Dev d, int first)
+{
+    int m[3] = {d.n[0], d.n[1], d.n[2]};
+    m[D] += 4;
+    const long long total = (long long)m[0] * m[1] * m[2];
+    const long long t0 = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (t0 >= total)
+        return;
+    int ci[3];
+    ci[0] = (int)(t0 % m[0]);
+    const long long t = t0 / m[0];
+    ci[1] = (int)(t % m[1]);
+    ci[2] = (int)(t / m[1]);
+    ci[D] -= 2;
+    const int i = ci[D], n = d.n[D];
+    const long long nf = d.nf[D];
+    int fm[3] = {d.n[0], d.n[1], d.n[2]};
+    fm[D] += 1;
+    // face index of the face at position ff along D (same other coordinates)
+    auto face = [&](int ff) -> long long {
+        int fi[3] = {ci[0], ci[1], ci[2]};
+        fi[D] = ff;
+        return fi[0] + (long long)fm[0] * (fi[1] + (long long)fm[1] * fi[2]);
+    };
+    const long long st = D == 0 ? 1 : (D == 1 ? (long long)d.px : (long long)d.px * d.py);
+    const long long pc = ghosted(d, ci[0], ci[1], ci[2]);
+    const bool has_lo = i >= 0 && i <= n;            // face i exists
+    const bool has_hi = i + 1 >= 0 && i + 1 <= n;    // face i+1 exists
+    const long long f_lo = has_lo ? face(i) : 0, f_hi = has_hi ? face(i + 1) : 0;
+    const long long f_lm = (i - 1 >= 0 && i - 1 <= n) ? face(i - 1) : -1;   // face i-1
+    const long long f_hp = (i + 2 >= 0 && i + 2 <= n) ? face(i + 2) : -1;   // face i+2
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        const double* Fl = FB + v * nf;          // left-state cotangents
+        const double* Fr = FB + (9 + v) * nf;    // right-state cotangents
+        double mu = 0.0;
+        if (has_hi)
+            mu += Fl[f_hi];
+        if (has_lo)
+            mu += Fr[f_lo];
+        // slope of cell j feeds the left state at face j+1 and the right state
+        // at face j: sigma_b(j) = (Lb(face j+1) - Rb(face j)) / 2, j in [-1, n]
+        const double* P = Pc + v * d.sv + pc;
+        // j = i - 1 (q_i is its qp)
+        if (i - 1 >= -1 && i - 1 <= n) {
+            const double sb = 0.5 * ((has_lo ? Fl[f_lo] : 0.0) - (f_lm >= 0 ? Fr[f_lm] : 0.0));
+            if (sb != 0.0) {
+                double dm, d0, dp;
+                mc_slope_grad(P[-2 * st], P[-st], P[0], dm, d0, dp);
+                mu += sb * dp;
+            }
+        }
+        // j = i
+        if (i >= -1 && i <= n) {
+            const double sb = 0.5 * ((has_hi ? Fl[f_hi] : 0.0) - (has_lo ? Fr[f_lo] : 0.0));
+            if (sb != 0.0) {
+                double dm, d0, dp;
+                mc_slope_grad(P[-st], P[0], P[st], dm, d0, dp);
+                mu += sb * d0;
+            }
+        }
+        // j = i + 1 (q_i is its qm)
+        if (i + 1 >= -1 && i + 1 <= n) {
+            const double sb = 0.5 * ((f_hp >= 0 ? Fl[f_hp] : 0.0) - (has_hi ? Fr[f_hi] : 0.0));
+            if (sb != 0.0) {
+                double dm, d0, dp;
+                mc_slope_grad(P[0], P[st], P[2 * st], dm, d0, dp);
+                mu += sb * dm;
+            }
+        }
+        double* out = MU + v * d.sv + pc;
+        if (first || i < 0 || i >= n)
+            *out = mu;
+        else
+            *out += mu;
+    }
+}
+
+// Reverse of add_sources() (FP64): Rb (cotangent of R at the cell) -> qb.
+template <int KIND>
+__device__ __forceinline__ void sources_rev(const Dev& d, double x, double y, double z, const double* q,
+                                            const double* Rb, double* qb)
+{
+    qb[8] -= d.kappa * Rb[8];
+    if (KIND == FLAT)
+        return;
+    double ka, kp;
+    const Geo g0 = geo_deriv<KIND>(d, x, y, z, ka, kp);
+    const GeoT<double> g = geo_cast<double>(g0);
+    const Kin<double> k = kinematics(q, g, d.gfac);
+    const double ia2 = 1.0 / (g.alpha * g.alpha);
+    const double Kb = Rb[2] * x + Rb[3] * y + Rb[4] * z;
+    const double Tttb = Kb * 0.5 * g.sqrtmg * (-2.0 * g.alpha * ka);
+    const double Tkkb = Kb * 0.5 * g.sqrtmg * kp;
+    KinBar kb = kin_zero();
+    // Ttt = (wtot W^2 - ptot)/alpha^2 - bt^2
+    kb.wtot += Tttb * k.W * k.W * ia2;
+    kb.W += Tttb * 2.0 * k.wtot * k.W * ia2;
+    kb.ptot -= Tttb * ia2;
+    kb.bt -= 2.0 * Tttb * k.bt;
+    // Tkk = wtot |u~|^2 + 3 ptot / psi^4 - |b|^2
+    const double uu = q[2] * q[2] + q[3] * q[3] + q[4] * q[4];
+    kb.wtot += Tkkb * uu;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        qb[2 + i] += Tkkb * k.wtot * 2.0 * q[2 + i];
+        kb.b[i] -= 2.0 * Tkkb * k.b[i];
+    }
+    kb.ptot += 3.0 * Tkkb * g.ipsi4;
+    kinematics_rev(q, k, g, d.gfac, kb, qb);
+}
+
+// Per interior cell: Pb = MU + the MU of the ghosts that copy this cell +
+// the source cotangent.
+template <int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_fold(const double* __restrict__ Pc,
+                                                      const double* __restrict__ MU,
+                                                      const double* __restrict__ Rb,
+                                                      double* __restrict__ Pb, Dev d)
+{
+    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (c >= d.N)
+        return;
+    const int i = (int)(c % d.n[0]);
+    const long long t = c / d.n[0];
+    const int j = (int)(t % d.n[1]);
+    const int k = (int)(t / d.n[1]);
+    const long long pc = ghosted(d, i, j, k);
+    double pb[9], q[9], rb[9];
+    const bool any = d.act[0] || d.act[1] || d.act[2];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        pb[v] = any ? MU[v * d.sv + pc] : 0.0;
+        q[v] = Pc[v * d.sv + pc];
+        rb[v] = Rb[v * d.N + c];
+    }
+    const int idx[3] = {i, j, k};
+    const long long stride[3] = {1, d.px, (long long)d.px * d.py};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!d.act[a])
+            continue;
+        const int n = d.n[a];
+        const long long s = stride[a];
+        long long o[2];
+        int no = 0;
+        if (d.bc[a] == 0) {
+            if (idx[a] < 2)
+                o[no++] = n * s;
+            if (idx[a] >= n - 2)
+                o[no++] = -n * s;
+        } else if (idx[a] == 0) {
+            o[no++] = -s;
+            o[no++] = -2 * s;
+        } else if (idx[a] == n - 1) {
+            o[no++] = s;
+            o[no++] = 2 * s;
+        }
+        for (int e = 0; e < no; ++e)
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                pb[v] += MU[v * d.sv + pc + o[e]];
+    }
+    const double3 x = centre(d, i, j, k);
+    sources_rev<KIND>(d, x.x, x.y, x.z, q, rb, pb);
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        Pb[v * d.N + c] = pb[v];
+}
+
+// x = (dU/dP)^-T y at the primitives q of a cell at (x, y, z); false if the
+// matter block is singular.
+template <int KIND>
+__device__ __forceinline__ bool recovery_adjoint(const Dev& d, const double3& x, const double* q,
+                                                 const double* y, double* out, double J[5][8],
+                                                 GeoT<double>& g)
+{
+    g = geo_cast<double>(geo_at<KIND>(d, x.x, x.y, x.z));
+    cons_jacobian(q, g, d.gfac, J);
+    return cons_jacobian_solve_t(J, g.sqrtmg, y, out);
+}
+
+// Recovery + RK-combination adjoint of stage s (see the file header).  Ub is
+// updated in place to the cotangent of U^s; Pb (may be null: zero) is the
+// cotangent of P^(s+1); flags are the stage's recovery flags.
+template <int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_rec(double* __restrict__ Ub, const double* __restrict__ Pb,
+                                                     const double* __restrict__ Pn,
+                                                     const unsigned char* __restrict__ flags,
+                                                     double* __restrict__ Unacc, double* __restrict__ Rb,
+                                                     Dev d, double a, double b, double dt, int first)
+{
+    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (c >= d.N)
+        return;
+    const int i = (int)(c % d.n[0]);
+    const long long t = c / d.n[0];
+    const int j = (int)(t % d.n[1]);
+    const int k = (int)(t / d.n[1]);
+    const long long pc = ghosted(d, i, j, k);
+    double q[9], ub[9], pb[9], ut[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        q[v] = Pn[v * d.sv + pc];
+        ub[v] = Ub[v * d.N + c];
+        pb[v] = Pb ? Pb[v * d.N + c] : 0.0;
+    }
+    const int fl = flags[c];
+    const double3 x = centre(d, i, j, k);
+    double J[5][8];
+    GeoT<double> g;
+    if (fl & FLAG_ATM) {
+        // hydro primitives constant; B = Bd / sqrt(-g), Phi passed through;
+        // the matter part of U rebuilt from (constant hydro, B)
+        g = geo_cast<double>(geo_at<KIND>(d, x.x, x.y, x.z));
+        cons_jacobian(q, g, d.gfac, J);
+#pragma unroll
+        for (int e = 5; e < 8; ++e) {
+            double s = pb[e];
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                s += J[r][e] * ub[r];
+            ut[e] = ub[e] + s * g.isqrtmg;
+        }
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            ut[r] = 0.0;
+        ut[8] = ub[8] + pb[8];
+    } else if (fl & FLAG_FAIL) {
+        // the previous hydro primitives are kept: no derivative through them
+        g = geo_cast<double>(geo_at<KIND>(d, x.x, x.y, x.z));
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            ut[r] = ub[r];
+#pragma unroll
+        for (int e = 5; e < 8; ++e)
+            ut[e] = ub[e] + pb[e] * g.isqrtmg;
+        ut[8] = ub[8] + pb[8];
+    } else if (fl & FLAG_PFLOOR) {
+        // pressure constant; rho, u~ from the root; matter part rebuilt
+        g = geo_cast<double>(geo_at<KIND>(d, x.x, x.y, x.z));
+        cons_jacobian(q, g, d.gfac, J);
+        double pt[9];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            double s = pb[e];
+#pragma unroll
+            for (int r = 0; r < 5; ++r)
+                s += J[r][e] * ub[r];
+            pt[e] = s;
+        }
+        pt[1] = 0.0;
+        pt[8] = pb[8];
+        if (!cons_jacobian_solve_t(J, g.sqrtmg, pt, ut)) {
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                ut[v] = __builtin_nan("");
+        }
+#pragma unroll
+        for (int v = 5; v < 9; ++v)
+            ut[v] += ub[v];
+    } else {
+        if (!recovery_adjoint<KIND>(d, x, q, pb, ut, J, g)) {
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                ut[v] = __builtin_nan("");
+        }
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            ut[v] += ub[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        Ub[v * d.N + c] = (1.0 - a) * ut[v];
+        Unacc[v * d.N + c] = (first ? 0.0 : Unacc[v * d.N + c]) + a * ut[v];
+        Rb[v * d.N + c] = b * dt * ut[v];
+    }
+}
+
+// Ubar = Ub + Unacc + (dU/dP)^-T Pb at P^0 (the step's first primitives).
+// With Ub = Unacc = null: Ubar = (dU/dP)^-T Pb (adjoint of the recovery).
+template <int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_final(const double* __restrict__ Ub,
+                                                       const double* __restrict__ Pb,
+                                                       const double* __restrict__ P0,
+                                                       const double* __restrict__ Unacc,
+                                                       double* __restrict__ Ubar, Dev d)
+{
+    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (c >= d.N)
+        return;
+    const int i = (int)(c % d.n[0]);
+    const long long t = c / d.n[0];
+    const int j = (int)(t % d.n[1]);
+    const int k = (int)(t / d.n[1]);
+    const long long pc = ghosted(d, i, j, k);
+    double q[9], pb[9], ut[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        q[v] = P0[v * d.sv + pc];
+        pb[v] = Pb[v * d.N + c];
+    }
+    double J[5][8];
+    GeoT<double> g;
+    if (!recovery_adjoint<KIND>(d, centre(d, i, j, k), q, pb, ut, J, g)) {
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            ut[v] = __builtin_nan("");
+    }
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        double s = ut[v];
+        if (Ub)
+            s += Ub[v * d.N + c] + Unacc[v * d.N + c];
+        Ubar[v * d.N + c] = s;
+    }
+}
+
+// Pbar = (dU/dP)^T Ubar at the primitives P (dense interior arrays).
+template <int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_cons(const double* __restrict__ P,
+                                                      const double* __restrict__ Ubar,
+                                                      double* __restrict__ Pbar, Dev d)
+{
+    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (c >= d.N)
+        return;
+    const int i = (int)(c % d.n[0]);
+    const long long t = c / d.n[0];
+    const int j = (int)(t % d.n[1]);
+    const int k = (int)(t / d.n[1]);
+    double q[9], ub[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        q[v] = P[v * d.N + c];
+        ub[v] = Ubar[v * d.N + c];
+    }
+    const double3 x = centre(d, i, j, k);
+    const GeoT<double> g = geo_cast<double>(geo_at<KIND>(d, x.x, x.y, x.z));
+    double J[5][8];
+    cons_jacobian(q, g, d.gfac, J);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        double s = e >= 5 ? g.sqrtmg * ub[e] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            s += J[r][e] * ub[r];
+        Pbar[e * d.N + c] = s;
+    }
+    Pbar[8 * d.N + c] = ub[8];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+hipError_t launch_adj_rec(int kind, double* Ub, const double* Pb, const double* Pn, const unsigned char* flags,
+                          double* Unacc, double* Rb, const Dev& d, double a, double b, double dt, int first,
+                          hipStream_t s)
+{
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_adj_rec<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pb, Pn, flags, Unacc,
+                           Rb, d, a, b, dt, first);
+    else
+        hipLaunchKernelGGL((k_adj_rec<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pb, Pn, flags, Unacc,
+                           Rb, d, a, b, dt, first);
+    return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t adj_face_k(int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
+                             hipStream_t s)
+{
+    const unsigned nb = ablocks(d.nf[dir]);
+    if (dir == 0)
+        hipLaunchKernelGGL((k_adj_face<0, KIND>), dim3(nb), dim3(ABLOCK), 0, s, Pc, Rb, FB, d);
+    else if (dir == 1)
+        hipLaunchKernelGGL((k_adj_face<1, KIND>), dim3(nb), dim3(ABLOCK), 0, s, Pc, Rb, FB, d);
+    else
+        hipLaunchKernelGGL((k_adj_face<2, KIND>), dim3(nb), dim3(ABLOCK), 0, s, Pc, Rb, FB, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_face(int kind, int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
+                           hipStream_t s)
+{
+    return kind == FLAT ? adj_face_k<FLAT>(dir, Pc, Rb, FB, d, s) : adj_face_k<ISO>(dir, Pc, Rb, FB, d, s);
+}
+
+hipError_t launch_adj_gather(int dir, const double* Pc, const double* FB, double* MU, const Dev& d, int first,
+                             hipStream_t s)
+{
+    long long m[3] = {d.n[0], d.n[1], d.n[2]};
+    m[dir] += 4;
+    const unsigned nb = ablocks(m[0] * m[1] * m[2]);
+    if (dir == 0)
+        hipLaunchKernelGGL((k_adj_gather<0>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
+    else if (dir == 1)
+        hipLaunchKernelGGL((k_adj_gather<1>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
+    else
+        hipLaunchKernelGGL((k_adj_gather<2>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_fold(int kind, const double* Pc, const double* MU, const double* Rb, double* Pb,
+                           const Dev& d, hipStream_t s)
+{
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_adj_fold<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Pb, d);
+    else
+        hipLaunchKernelGGL((k_adj_fold<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Pb, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_final(int kind, const double* Ub, const double* Pb, const double* P0, const double* Unacc,
+                            double* Ubar, const Dev& d, hipStream_t s)
+{
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_adj_final<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pb, P0, Unacc, Ubar,
+                           d);
+    else
+        hipLaunchKernelGGL((k_adj_final<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pb, P0, Unacc, Ubar, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_cons(int kind, const double* P, const double* Ubar, double* Pbar, const Dev& d,
+                           hipStream_t s)
+{
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_adj_cons<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, P, Ubar, Pbar, d);
+    else
+        hipLaunchKernelGGL((k_adj_cons<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, P, Ubar, Pbar, d);
+    return hipGetLastError();
+}
+
+}  // namespace grmhd

@@ -25,7 +25,14 @@ struct TimedLaunch {
 struct Layout {
     int g[3], px, py, pz;
     long long sv, N, nf[3];
-    size_t off_cnt, off_pc[3], off_us, off_f[3], total;
+    size_t off_cnt, off_pc[3], off_us, off_f[3];
+    // adjoint part (FP64): stage primitive caches P^0..P^ns, the stages'
+    // recovery flags, the recomputed stage state, the U^n cotangent
+    // accumulator, the R and P cotangents, the ghosted reconstruction
+    // cotangent and the face-state cotangents of one axis
+    bool adj;
+    size_t off_ac[4], off_aflags, off_aus, off_unacc, off_rb, off_pb, off_mu, off_fb;
+    size_t total;
 };
 
 size_t round_up(size_t x, size_t a)
@@ -48,7 +55,7 @@ bool grid_ok(const grmhd_grid* g)
     return true;
 }
 
-Layout make_layout(const grmhd_grid* g, size_t esize)
+Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int ns = 3)
 {
     Layout L{};
     for (int d = 0; d < 3; ++d)
@@ -73,14 +80,42 @@ Layout make_layout(const grmhd_grid* g, size_t esize)
         if (b == 0 || g->n[2] > 1)   // the extra caches serve the fused 3D update only
             off = round_up(off + esize * 9 * (size_t)L.sv, 256);
     }
-    L.off_us = off;
-    off = round_up(off + sizeof(double) * 9 * (size_t)L.N, 256);
+    L.off_us = off;                  // intermediate Runge-Kutta stage state
+    off = round_up(off + esize * 9 * (size_t)L.N, 256);
     for (int d = 0; d < 3; ++d) {
         L.off_f[d] = off;
         off = round_up(off + esize * 9 * (size_t)L.nf[d], 256);
     }
+    L.adj = adjoint;
+    if (adjoint) {
+        const size_t cache = sizeof(double) * 9 * (size_t)L.sv, dense = sizeof(double) * 9 * (size_t)L.N;
+        long long nfmax = 0;
+        for (int d = 0; d < 3; ++d)
+            nfmax = L.nf[d] > nfmax ? L.nf[d] : nfmax;
+        for (int b = 0; b < 4; ++b) {
+            L.off_ac[b] = off;
+            if (b <= ns)
+                off = round_up(off + cache, 256);
+        }
+        L.off_aflags = off;
+        off = round_up(off + (size_t)ns * L.N, 256);
+        size_t* dense_offs[4] = {&L.off_aus, &L.off_unacc, &L.off_rb, &L.off_pb};
+        for (size_t* o : dense_offs) {
+            *o = off;
+            off = round_up(off + dense, 256);
+        }
+        L.off_mu = off;
+        off = round_up(off + cache, 256);
+        L.off_fb = off;
+        off = round_up(off + sizeof(double) * 18 * (size_t)nfmax, 256);
+    }
     L.total = off;
     return L;
+}
+
+bool wants_adjoint(const grmhd_opts* o)
+{
+    return o && o->adjoint && o->precision == GRMHD_FP64;
 }
 
 // bytes of one value of the primitive caches and face buffers
@@ -103,9 +138,18 @@ struct grmhd_ctx {
     // -> 0) so that every substep writes a cache it does not read and the step
     // ends in Pbuf[0] (a captured step can be replayed).
     void* Pbuf[3] = {nullptr, nullptr, nullptr};
-    double* Us = nullptr;
+    void* Us = nullptr;                     // intermediate stage state (cache type)
     void* F[3] = {nullptr, nullptr, nullptr};
+    // cache b has its ghost slabs filled: every kernel that writes a cache
+    // (cons, prim, the updates) writes the ghost images of its cells as well
+    bool ghosts_ok[3] = {false, false, false};
     bool mixed = false;                     // float caches and face physics
+    // adjoint workspace (FP64)
+    bool adj = false;
+    bool adj_prepared = false;
+    double* Ac[4] = {nullptr, nullptr, nullptr, nullptr};
+    unsigned char* Aflags = nullptr;
+    double *Aus = nullptr, *Unacc = nullptr, *Rb = nullptr, *Pb = nullptr, *MU = nullptr, *FB = nullptr;
     unsigned long long* cnt = nullptr;
     bool prepared = false;
     bool cache_valid = false;
@@ -183,13 +227,19 @@ T* faces(grmhd_ctx* c, int d)
     return (T*)c->F[d];
 }
 
-// Ghost fill of the cache P and the face fluxes of the active axes up to ndir.
+// Ghost fill of cache b (unless the kernel that wrote it filled them) and the
+// face fluxes of the active axes up to ndir.
 template <typename T>
-int fluxes(grmhd_ctx* c, T* P, int ndir)
+int fluxes(grmhd_ctx* c, int b, int ndir)
 {
-    int rc = timed(c, GRMHD_K_BC, [&] { return grmhd::launch_ghosts(P, c->d, c->stream); });
-    if (rc)
-        return rc;
+    T* P = cache<T>(c, b);
+    int rc = GRMHD_OK;
+    if (!c->ghosts_ok[b]) {
+        rc = timed(c, GRMHD_K_BC, [&] { return grmhd::launch_ghosts(P, c->d, c->stream); });
+        if (rc)
+            return rc;
+        c->ghosts_ok[b] = true;
+    }
     for (int dir = 0; dir < ndir; ++dir) {
         if (!c->d.act[dir])
             continue;
@@ -212,6 +262,7 @@ int cons_t(grmhd_ctx* c, const double* P, double* U)
     if (rc)
         return rc;
     c->cache_valid = true;
+    c->ghosts_ok[0] = true;
     return GRMHD_OK;
 }
 
@@ -227,6 +278,7 @@ int prim_t(grmhd_ctx* c, const double* U, double* P)
     if (rc)
         return rc;
     c->cache_valid = true;
+    c->ghosts_ok[0] = true;
     return GRMHD_OK;
 }
 
@@ -242,12 +294,30 @@ int rhs_t(grmhd_ctx* c, const double* P, double* R)
     if (rc)
         return rc;
     c->cache_valid = true;
-    rc = fluxes<T>(c, cache<T>(c), 3);
+    c->ghosts_ok[0] = true;
+    rc = fluxes<T>(c, 0, 3);
     if (rc)
         return rc;
     return timed(c, GRMHD_K_RHS, [&] {
         return grmhd::launch_rhs(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
                                  (const T*)faces<T>(c, 2), (const T*)cache<T>(c), R, c->d, c->stream);
+    });
+}
+
+// One substep's update launch with the stage-state types TS (read) and TO
+// (written).
+template <typename T, typename TS, typename TO>
+int update_stage(grmhd_ctx* c, bool zmarch, int src, int dst, const double* U, const TS* Us, TO* Uout,
+                 double dt, double a, double b)
+{
+    return timed(c, GRMHD_K_UPDATE, [&] {
+        if (zmarch)
+            return grmhd::launch_update_zmarch(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
+                                               (const T*)cache<T>(c, src), cache<T>(c, dst), U, Us, Uout,
+                                               c->d, dt, a, b, c->cnt, (unsigned char*)nullptr, c->stream);
+        return grmhd::launch_update(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
+                                    (const T*)faces<T>(c, 2), (const T*)cache<T>(c, src), cache<T>(c, dst), U,
+                                    Us, Uout, c->d, dt, a, b, c->cnt, (unsigned char*)nullptr, c->stream);
     });
 }
 
@@ -263,29 +333,134 @@ int step_t(grmhd_ctx* c, double* U, double dt)
     const double* B = ns == 3 ? rk3b : rk2b;
     // 3D grids: the z faces are computed inside the fused update kernel, which
     // writes the new primitives to another cache; otherwise the update works
-    // in place on the cache with all face fluxes precomputed.
+    // in place on the cache with all face fluxes precomputed.  The first stage
+    // reads U^n as its stage state; the intermediate stage state has the cache
+    // type (float in the mixed path); the last stage writes U.
     const bool zmarch = c->d.act[2] != 0;
+    T* Us = (T*)c->Us;
     for (int s = 0; s < ns; ++s) {
-        T* src = zmarch ? cache<T>(c, s) : cache<T>(c);
-        T* dst = zmarch ? cache<T>(c, s == ns - 1 ? 0 : s + 1) : cache<T>(c);
+        const int src = zmarch ? s : 0;
+        const int dst = zmarch ? (s == ns - 1 ? 0 : s + 1) : 0;
         int rc = fluxes<T>(c, src, zmarch ? 2 : 3);
         if (rc)
             return rc;
-        const double* Us = s == 0 ? U : c->Us;
-        double* Uout = s == ns - 1 ? U : c->Us;
+        if (s == 0)
+            rc = update_stage<T>(c, zmarch, src, dst, U, (const double*)U, Us, dt, A[s], B[s]);
+        else if (s < ns - 1)
+            rc = update_stage<T>(c, zmarch, src, dst, U, (const T*)Us, Us, dt, A[s], B[s]);
+        else
+            rc = update_stage<T>(c, zmarch, src, dst, U, (const T*)Us, U, dt, A[s], B[s]);
+        if (rc)
+            return rc;
+        c->ghosts_ok[dst] = true;
+    }
+    return GRMHD_OK;
+}
+
+// Adjoint: first use fills the stage caches with NaN (their never-written
+// edge and corner ghosts included), so that the first recovery of P^0 has no
+// valid guess and takes the bracketed solve.
+int adj_prepare(grmhd_ctx* c)
+{
+    int rc = prepare_t<double>(c);
+    if (rc)
+        return rc;
+    if (c->adj_prepared)
+        return GRMHD_OK;
+    for (int b = 0; b <= c->rk_order; ++b)
+        if (grmhd::launch_fill(c->Ac[b], 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
+    c->adj_prepared = true;
+    return GRMHD_OK;
+}
+
+// Recompute the stages of the step from U: P^0 (recovered, guess = the
+// previous call's P^0), then P^(s+1), U^(s+1) and the recovery flags of every
+// stage.  The forward caches are not touched.
+int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, const double* B)
+{
+    const int ns = c->rk_order;
+    const bool zmarch = c->d.act[2] != 0;
+    int rc = timed(c, GRMHD_K_PRIM, [&] {
+        return grmhd::launch_prim(c->kind, U, c->Pb, c->Ac[0], c->d, c->cnt, c->stream);
+    });
+    if (rc)
+        return rc;
+    for (int s = 0; s < ns; ++s) {
+        const double* Ps = c->Ac[s];
+        for (int dir = 0; dir < (zmarch ? 2 : 3); ++dir) {
+            if (!c->d.act[dir])
+                continue;
+            rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
+                return grmhd::launch_flux(c->kind, dir, Ps, (double*)c->F[dir], c->d, c->stream);
+            });
+            if (rc)
+                return rc;
+        }
+        const double* Us = s == 0 ? U : c->Aus;
+        unsigned char* fl = c->Aflags + (size_t)s * c->L.N;
         rc = timed(c, GRMHD_K_UPDATE, [&] {
             if (zmarch)
-                return grmhd::launch_update_zmarch(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
-                                                   (const T*)src, dst, U, Us, Uout, c->d, dt, A[s], B[s],
-                                                   c->cnt, c->stream);
-            return grmhd::launch_update(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
-                                        (const T*)faces<T>(c, 2), src, U, Us, Uout, c->d, dt, A[s], B[s],
-                                        c->cnt, c->stream);
+                return grmhd::launch_update_zmarch(c->kind, (const double*)c->F[0], (const double*)c->F[1], Ps,
+                                                   c->Ac[s + 1], U, Us, c->Aus, c->d, dt, A[s], B[s], c->cnt,
+                                                   fl, c->stream);
+            return grmhd::launch_update(c->kind, (const double*)c->F[0], (const double*)c->F[1],
+                                        (const double*)c->F[2], Ps, c->Ac[s + 1], U, Us, c->Aus, c->d, dt,
+                                        A[s], B[s], c->cnt, fl, c->stream);
         });
         if (rc)
             return rc;
     }
     return GRMHD_OK;
+}
+
+int step_adjoint(grmhd_ctx* c, const double* U, double* Ubar, double dt)
+{
+    static const double rk3a[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double rk3b[3] = {1.0, 0.25, 2.0 / 3.0};
+    static const double rk2a[2] = {0.0, 0.5};
+    static const double rk2b[2] = {1.0, 0.5};
+    const int ns = c->rk_order;
+    const double* A = ns == 3 ? rk3a : rk2a;
+    const double* B = ns == 3 ? rk3b : rk2b;
+    int rc = adj_recompute(c, U, dt, A, B);
+    if (rc)
+        return rc;
+    for (int s = ns - 1; s >= 0; --s) {
+        const double* Pn = c->Ac[s + 1];
+        const unsigned char* fl = c->Aflags + (size_t)s * c->L.N;
+        rc = timed(c, GRMHD_K_ADJ_REC, [&] {
+            return grmhd::launch_adj_rec(c->kind, Ubar, s == ns - 1 ? nullptr : c->Pb, Pn, fl, c->Unacc, c->Rb,
+                                         c->d, A[s], B[s], dt, s == ns - 1, c->stream);
+        });
+        if (rc)
+            return rc;
+        const double* Ps = c->Ac[s];
+        int first = 1;
+        for (int dir = 0; dir < 3; ++dir) {
+            if (!c->d.act[dir])
+                continue;
+            rc = timed(c, GRMHD_K_ADJ_FACE, [&] {
+                return grmhd::launch_adj_face(c->kind, dir, Ps, c->Rb, c->FB, c->d, c->stream);
+            });
+            if (rc)
+                return rc;
+            rc = timed(c, GRMHD_K_ADJ_GATHER, [&] {
+                return grmhd::launch_adj_gather(dir, Ps, c->FB, c->MU, c->d, first, c->stream);
+            });
+            if (rc)
+                return rc;
+            first = 0;
+        }
+        rc = timed(c, GRMHD_K_ADJ_FOLD, [&] {
+            return grmhd::launch_adj_fold(c->kind, Ps, c->MU, c->Rb, c->Pb, c->d, c->stream);
+        });
+        if (rc)
+            return rc;
+    }
+    return timed(c, GRMHD_K_ADJ_REC, [&] {
+        return grmhd::launch_adj_final(c->kind, Ubar, c->Pb, c->Ac[0], c->Unacc, Ubar, c->d, c->stream);
+    });
 }
 
 }  // namespace
@@ -296,7 +471,8 @@ size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_opts* opts)
 {
     if (!grid_ok(grid))
         return 0;
-    return make_layout(grid, elem_size(opts)).total;
+    const int ns = opts && opts->rk_order == 2 ? 2 : 3;
+    return make_layout(grid, elem_size(opts), wants_adjoint(opts), ns).total;
 }
 
 int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
@@ -325,7 +501,9 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
         return GRMHD_ERR_ARG;
     if (opts->newton_tol < 0.0 || opts->newton_maxit < 0)
         return GRMHD_ERR_ARG;
-    Layout L = make_layout(grid, elem_size(opts));
+    if (opts->adjoint && opts->precision != GRMHD_FP64)
+        return GRMHD_ERR_ARG;
+    Layout L = make_layout(grid, elem_size(opts), wants_adjoint(opts), opts->rk_order);
     if (!opts->workspace || opts->workspace_bytes < L.total)
         return GRMHD_ERR_WORKSPACE;
     if (((uintptr_t)opts->workspace) % 256 != 0)
@@ -375,9 +553,21 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     c->cnt = (unsigned long long*)(c->ws + L.off_cnt);
     for (int b = 0; b < 3; ++b)
         c->Pbuf[b] = (void*)(c->ws + L.off_pc[b]);
-    c->Us = (double*)(c->ws + L.off_us);
+    c->Us = (void*)(c->ws + L.off_us);
     for (int a = 0; a < 3; ++a)
         c->F[a] = L.nf[a] ? (void*)(c->ws + L.off_f[a]) : nullptr;
+    if (L.adj) {
+        c->adj = true;
+        for (int b = 0; b <= c->rk_order; ++b)
+            c->Ac[b] = (double*)(c->ws + L.off_ac[b]);
+        c->Aflags = c->ws + L.off_aflags;
+        c->Aus = (double*)(c->ws + L.off_aus);
+        c->Unacc = (double*)(c->ws + L.off_unacc);
+        c->Rb = (double*)(c->ws + L.off_rb);
+        c->Pb = (double*)(c->ws + L.off_pb);
+        c->MU = (double*)(c->ws + L.off_mu);
+        c->FB = (double*)(c->ws + L.off_fb);
+    }
     *out = c;
     return GRMHD_OK;
 }
@@ -418,6 +608,46 @@ int grmhd_step(grmhd_ctx* c, double* U, double dt)
     if (!c->cache_valid)
         return GRMHD_ERR_STATE;
     return c->mixed ? step_t<float>(c, U, dt) : step_t<double>(c, U, dt);
+}
+
+int grmhd_step_adjoint(grmhd_ctx* c, const double* U, double* Ubar, double dt)
+{
+    if (!c || !U || !Ubar || !std::isfinite(dt))
+        return GRMHD_ERR_ARG;
+    if (!c->adj)
+        return GRMHD_ERR_NO_ADJOINT;
+    int rc = adj_prepare(c);
+    if (rc)
+        return rc;
+    return step_adjoint(c, U, Ubar, dt);
+}
+
+int grmhd_cons_adjoint(grmhd_ctx* c, const double* P, const double* Ubar, double* Pbar)
+{
+    if (!c || !P || !Ubar || !Pbar)
+        return GRMHD_ERR_ARG;
+    if (!c->adj)
+        return GRMHD_ERR_NO_ADJOINT;
+    return timed(c, GRMHD_K_ADJ_REC, [&] { return grmhd::launch_adj_cons(c->kind, P, Ubar, Pbar, c->d, c->stream); });
+}
+
+int grmhd_prim_adjoint(grmhd_ctx* c, const double* U, const double* Pbar, double* Ubar)
+{
+    if (!c || !U || !Pbar || !Ubar)
+        return GRMHD_ERR_ARG;
+    if (!c->adj)
+        return GRMHD_ERR_NO_ADJOINT;
+    int rc = adj_prepare(c);
+    if (rc)
+        return rc;
+    rc = timed(c, GRMHD_K_PRIM, [&] {
+        return grmhd::launch_prim(c->kind, U, c->Pb, c->Ac[0], c->d, c->cnt, c->stream);
+    });
+    if (rc)
+        return rc;
+    return timed(c, GRMHD_K_ADJ_REC, [&] {
+        return grmhd::launch_adj_final(c->kind, nullptr, Pbar, c->Ac[0], nullptr, Ubar, c->d, c->stream);
+    });
 }
 
 int grmhd_status(grmhd_ctx* c, grmhd_stats* st, int reset)
@@ -508,6 +738,8 @@ const char* grmhd_strerror(int code)
         return "HIP runtime or kernel launch error";
     case GRMHD_ERR_STATE:
         return "primitive cache not initialised: call grmhd_cons or grmhd_prim first";
+    case GRMHD_ERR_NO_ADJOINT:
+        return "adjoint call on a context created without opts.adjoint (FP64 only)";
     default:
         return "unknown error";
     }

@@ -239,6 +239,90 @@ __device__ __forceinline__ bool finite(double x)
 }
 
 // ---------------------------------------------------------------------------
+// Face solver: from the reconstructed left/right primitives at a face along D
+// (positions x, y, z), the 9 components Fo of the numerical flux: exact
+// (Bd^n, Phi) cleaning pair, then HLLE on the rest.
+template <int D, int KIND, typename T>
+__device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, double z, const Dev& d,
+                                          T* Fo)
+{
+    const GeoT<T> g = geo_cast<T>(geo_at<KIND>(d, x, y, z));
+    const T half = T(0.5), ch = (T)d.c_h, ich = (T)d.ic_h;
+
+    // cleaning pair: exact solution of the linear (Bd^n, Phi) Riemann problem
+    T BnL = g.sqrtmg * qL[5 + D], BnR = g.sqrtmg * qR[5 + D];
+    T Bs = half * (BnL + BnR) - half * ich * (qR[8] - qL[8]);
+    T phs = half * (qL[8] + qR[8]) - half * ch * (BnR - BnL);
+    qL[5 + D] = qR[5 + D] = Bs * g.isqrtmg;
+
+    const T gfac = (T)d.gfac, gam = (T)d.gamma;
+    Kin<T> kL = kinematics(qL, g, gfac);
+    Kin<T> kR = kinematics(qR, g, gfac);
+    T lmL, lpL, lmR, lpR;
+    speeds<D>(qL, kL, g, gam, lmL, lpL);
+    speeds<D>(qR, kR, g, gam, lmR, lpR);
+    T sl = fmin(T(0), fmin(lmL, lmR));
+    T sr = fmax(T(0), fmax(lpL, lpR));
+    T cL, cR, cU;
+    if (sl == T(0)) {
+        cL = T(1);
+        cR = T(0);
+        cU = T(0);
+    } else if (sr == T(0)) {
+        cL = T(0);
+        cR = T(1);
+        cU = T(0);
+    } else {
+        T inv = T(1) / (sr - sl);
+        cL = sr * inv;
+        cR = -sl * inv;
+        cU = sl * sr * inv;
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        if (v == 5 + D)
+            continue;
+        T fl = flux_comp<D>(v, qL, kL, g);
+        T fr = flux_comp<D>(v, qR, kR, g);
+        T o = cL * fl + cR * fr;
+        if (cU != T(0))
+            o += cU * (cons_comp(v, qR, kR, g) - cons_comp(v, qL, kL, g));
+        Fo[v] = o;
+    }
+    Fo[5 + D] = phs;
+    Fo[8] = (T)d.c_h2 * Bs;
+}
+
+
+// ---------------------------------------------------------------------------
+// Metric sources at a cell centre (x, y, z) with primitives q, added to R:
+// 1/2 sqrt(-g) [T^tt d_j g_tt + sum_k T^kk d_j g_kk] on the momenta (d_j g_tt =
+// -2 alpha d_j alpha), zero on mass and energy (static metric), -kappa Phi on
+// the cleaning scalar.  The source is evaluated in T; the centre geometry is
+// returned in g (double, for the recovery).
+template <int KIND, typename T>
+__device__ __forceinline__ void add_sources(const Dev& d, double x, double y, double z, const T* q,
+                                            Geo& g, double* R)
+{
+    double ka, kp;
+    g = geo_deriv<KIND>(d, x, y, z, ka, kp);
+    if (KIND != FLAT) {
+        const GeoT<T> gt = geo_cast<T>(g);
+        Kin<T> kk = kinematics(q, gt, (T)d.gfac);
+        T ia2 = T(1) / (gt.alpha * gt.alpha);
+        T Ttt = (kk.wtot * kk.W * kk.W - kk.ptot) * ia2 - kk.bt * kk.bt;
+        T uu = q[2] * q[2] + q[3] * q[3] + q[4] * q[4];
+        T bb = kk.b[0] * kk.b[0] + kk.b[1] * kk.b[1] + kk.b[2] * kk.b[2];
+        T Tkk = kk.wtot * uu + T(3) * kk.ptot * gt.ipsi4 - bb;
+        T K = T(0.5) * gt.sqrtmg * (-T(2) * gt.alpha * Ttt * (T)ka + Tkk * (T)kp);
+        R[2] += (double)(K * (T)x);
+        R[3] += (double)(K * (T)y);
+        R[4] += (double)(K * (T)z);
+    }
+    R[8] -= d.kappa * (double)q[8];
+}
+
+// ---------------------------------------------------------------------------
 // Primitive recovery (section 2.2; the 2D_W equations of Noble et al. 2006 in
 // the unknowns Wc = rho h W^2 and v^2).
 

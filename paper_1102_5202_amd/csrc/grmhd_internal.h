@@ -17,7 +17,7 @@ enum { CNT_SLOTS = 256 };
 static constexpr size_t CNT_BYTES = sizeof(unsigned long long) * CNT_WORDS * CNT_SLOTS;
 
 // Launchers; T (double or float) is the type of the primitive caches and the
-// face-flux buffers.  Conserved variables and U arrays are always double.
+// face-flux buffers.  The caller's conserved arrays are always double.
 template <typename T>
 hipError_t launch_fill(T* p, long long n, double v, hipStream_t s);
 hipError_t launch_zero_counters(unsigned long long* cnt, hipStream_t s);
@@ -25,14 +25,19 @@ template <typename T>
 hipError_t launch_ghosts(T* Pc, const Dev& d, hipStream_t s);
 template <typename T>
 hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipStream_t s);
-template <typename T>
-hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, T* Pc, const double* Un,
-                         const double* Us, double* Uout, const Dev& d, double dt, double a, double b,
-                         unsigned long long* cnt, hipStream_t s);
-template <typename T>
+// TS / TO: types of the stage state read (U^s) and written (U^(s+1)); double,
+// or float for the intermediate stages of the mixed-precision path.  U^n is
+// always double.  The update kernels read the primitives from Pc and write
+// the new ones, with their ghost images, to Pn (Pc == Pn allowed for
+// launch_update only); fout (may be null) receives per-cell recovery flags.
+template <typename T, typename TS, typename TO>
+hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, const T* Pc, T* Pn, const double* Un,
+                         const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
+                         unsigned long long* cnt, unsigned char* fout, hipStream_t s);
+template <typename T, typename TS, typename TO>
 hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc, T* Pn, const double* Un,
-                                const double* Us, double* Uout, const Dev& d, double dt, double a,
-                                double b, unsigned long long* cnt, hipStream_t s);
+                                const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
+                                unsigned long long* cnt, unsigned char* fout, hipStream_t s);
 template <typename T>
 hipError_t launch_rhs(int kind, const T* Fx, const T* Fy, const T* Fz, const T* Pc, double* R,
                       const Dev& d, hipStream_t s);
@@ -41,5 +46,50 @@ hipError_t launch_cons(int kind, const double* P, double* U, T* Pc, const Dev& d
 template <typename T>
 hipError_t launch_prim(int kind, const double* U, double* P, T* Pc, const Dev& d, unsigned long long* cnt,
                        hipStream_t s);
+
+// Batched ensemble of independent 1D problems along x (flat metric).  One
+// record per problem, in device memory.
+struct BatchProb {
+    int n;              // cells
+    int steps;          // Runge-Kutta steps to take in all
+    int done;           // steps taken so far (advanced by the evolve kernel)
+    int pad;
+    long long off;      // first cell of the problem in the packed arrays
+    long long poff;     // first element of its ghosted primitive row (9 rows of n + 4)
+    double lo, dx, idx, dt;
+};
+
+// Launch shapes of the batched evolve kernel: threads per workgroup.
+static constexpr int BATCH_SHAPES = 3;
+static constexpr int BATCH_THREADS[BATCH_SHAPES] = {256, 512, 1024};
+
+template <typename T>
+hipError_t launch_batch_cons(const BatchProb* probs, int nprob, long long ncell, const double* P, double* U,
+                             T* Prow, const Dev& d, hipStream_t s);
+template <typename T>
+hipError_t launch_batch_prim(const BatchProb* probs, int nprob, long long ncell, const double* U, double* P,
+                             T* Prow, const Dev& d, unsigned long long* cnt, hipStream_t s);
+// shape: index into BATCH_THREADS; lds: keep the primitive rows in LDS (needs
+// lds_bytes <= 160 KiB).  order: the problem each workgroup takes.  Pnext is
+// a second set of rows (the next substep's, or the staging of the LDS rows).
+template <typename T>
+hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
+                               double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps,
+                               unsigned long long* cnt, hipStream_t s);
+
+// Adjoint kernels (FP64; grmhd_adjoint.hip).
+hipError_t launch_adj_rec(int kind, double* Ub, const double* Pb, const double* Pn, const unsigned char* flags,
+                          double* Unacc, double* Rb, const Dev& d, double a, double b, double dt, int first,
+                          hipStream_t s);
+hipError_t launch_adj_face(int kind, int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
+                           hipStream_t s);
+hipError_t launch_adj_gather(int dir, const double* Pc, const double* FB, double* MU, const Dev& d, int first,
+                             hipStream_t s);
+hipError_t launch_adj_fold(int kind, const double* Pc, const double* MU, const double* Rb, double* Pb,
+                           const Dev& d, hipStream_t s);
+hipError_t launch_adj_final(int kind, const double* Ub, const double* Pb, const double* P0, const double* Unacc,
+                            double* Ubar, const Dev& d, hipStream_t s);
+hipError_t launch_adj_cons(int kind, const double* P, const double* Ubar, double* Pbar, const Dev& d,
+                           hipStream_t s);
 
 }  // namespace grmhd

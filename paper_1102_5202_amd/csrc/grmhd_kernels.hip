@@ -43,7 +43,8 @@ __global__ __launch_bounds__(BLOCK) void k_zero_counters(unsigned long long* cnt
 }
 
 // Ghost fill: one thread per ghost cell of the three face slabs (no edges or
-// corners: the stencil is a cross).  Segment a covers axis a: 2*g layers times
+// corners: the stencil is a cross).  The kernels that write a cache fill its
+// ghost images themselves; this one remains for caches written otherwise.  Segment a covers axis a: 2*g layers times
 // the interior extent of the other two axes.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_ghosts(T* __restrict__ Pc, Dev d, long long s0, long long s1,
@@ -86,61 +87,6 @@ __global__ __launch_bounds__(BLOCK) void k_ghosts(T* __restrict__ Pc, Dev d, lon
 #pragma unroll
     for (int v = 0; v < 9; ++v)
         Pc[v * d.sv + dst] = Pc[v * d.sv + sp];
-}
-
-// ---------------------------------------------------------------------------
-// Face solver: from the reconstructed left/right primitives at a face along D
-// (positions x, y, z), the 9 components Fo of the numerical flux: exact
-// (Bd^n, Phi) cleaning pair, then HLLE on the rest.
-template <int D, int KIND, typename T>
-__device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, double z, const Dev& d,
-                                          T* Fo)
-{
-    const GeoT<T> g = geo_cast<T>(geo_at<KIND>(d, x, y, z));
-    const T half = T(0.5), ch = (T)d.c_h, ich = (T)d.ic_h;
-
-    // cleaning pair: exact solution of the linear (Bd^n, Phi) Riemann problem
-    T BnL = g.sqrtmg * qL[5 + D], BnR = g.sqrtmg * qR[5 + D];
-    T Bs = half * (BnL + BnR) - half * ich * (qR[8] - qL[8]);
-    T phs = half * (qL[8] + qR[8]) - half * ch * (BnR - BnL);
-    qL[5 + D] = qR[5 + D] = Bs * g.isqrtmg;
-
-    const T gfac = (T)d.gfac, gam = (T)d.gamma;
-    Kin<T> kL = kinematics(qL, g, gfac);
-    Kin<T> kR = kinematics(qR, g, gfac);
-    T lmL, lpL, lmR, lpR;
-    speeds<D>(qL, kL, g, gam, lmL, lpL);
-    speeds<D>(qR, kR, g, gam, lmR, lpR);
-    T sl = fmin(T(0), fmin(lmL, lmR));
-    T sr = fmax(T(0), fmax(lpL, lpR));
-    T cL, cR, cU;
-    if (sl == T(0)) {
-        cL = T(1);
-        cR = T(0);
-        cU = T(0);
-    } else if (sr == T(0)) {
-        cL = T(0);
-        cR = T(1);
-        cU = T(0);
-    } else {
-        T inv = T(1) / (sr - sl);
-        cL = sr * inv;
-        cR = -sl * inv;
-        cU = sl * sr * inv;
-    }
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        if (v == 5 + D)
-            continue;
-        T fl = flux_comp<D>(v, qL, kL, g);
-        T fr = flux_comp<D>(v, qR, kR, g);
-        T o = cL * fl + cR * fr;
-        if (cU != T(0))
-            o += cU * (cons_comp(v, qR, kR, g) - cons_comp(v, qL, kL, g));
-        Fo[v] = o;
-    }
-    Fo[5 + D] = phs;
-    Fo[8] = (T)d.c_h2 * Bs;
 }
 
 template <int D, int KIND, typename T>
@@ -249,34 +195,6 @@ __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, 
     }
 }
 
-// ---------------------------------------------------------------------------
-// Metric sources at a cell centre (x, y, z) with primitives q, added to R:
-// 1/2 sqrt(-g) [T^tt d_j g_tt + sum_k T^kk d_j g_kk] on the momenta (d_j g_tt =
-// -2 alpha d_j alpha), zero on mass and energy (static metric), -kappa Phi on
-// the cleaning scalar.  The source is evaluated in T; the centre geometry is
-// returned in g (double, for the recovery).
-template <int KIND, typename T>
-__device__ __forceinline__ void add_sources(const Dev& d, double x, double y, double z, const T* q,
-                                            Geo& g, double* R)
-{
-    double ka, kp;
-    g = geo_deriv<KIND>(d, x, y, z, ka, kp);
-    if (KIND != FLAT) {
-        const GeoT<T> gt = geo_cast<T>(g);
-        Kin<T> kk = kinematics(q, gt, (T)d.gfac);
-        T ia2 = T(1) / (gt.alpha * gt.alpha);
-        T Ttt = (kk.wtot * kk.W * kk.W - kk.ptot) * ia2 - kk.bt * kk.bt;
-        T uu = q[2] * q[2] + q[3] * q[3] + q[4] * q[4];
-        T bb = kk.b[0] * kk.b[0] + kk.b[1] * kk.b[1] + kk.b[2] * kk.b[2];
-        T Tkk = kk.wtot * uu + T(3) * kk.ptot * gt.ipsi4 - bb;
-        T K = T(0.5) * gt.sqrtmg * (-T(2) * gt.alpha * Ttt * (T)ka + Tkk * (T)kp);
-        R[2] += (double)(K * (T)x);
-        R[3] += (double)(K * (T)y);
-        R[4] += (double)(K * (T)z);
-    }
-    R[8] -= d.kappa * (double)q[8];
-}
-
 // Flux differences + sources for cell c (i,j,k); q are its primitives.
 template <int KIND, typename T>
 __device__ __forceinline__ void rhs_cell(const Dev& d, const T* __restrict__ Fx, const T* __restrict__ Fy,
@@ -350,39 +268,89 @@ __device__ __forceinline__ void tally(int flags, int iters, int& nf, int& na, in
     itmax = max(itmax, iters);
 }
 
-// RK combination U^(s+1) = U^(s) + a (U^n - U^(s)) + b dt R and the recovery
-// of the primitives for one cell (all in double); q are the cell's current
-// primitives (the Newton guess).  Writes U^(s+1) and the new primitives.
+// Store the primitives of cell (i, j, k) at cache position pc, and at the
+// ghost positions whose boundary rule copies this cell, so that the cache
+// leaves the kernel with its ghost slabs filled (only the face slabs are
+// ghosts: every stencil is 1D).  Periodic: the cell is the image of ghost
+// idx + n when idx < g and of ghost idx - n when idx >= n - g.  Outflow
+// (zero gradient): the first and last cells fill both ghost layers beside
+// them.  Active axes have n >= 2 = g, so these are all the images.
 template <typename T>
+__device__ __forceinline__ void store_prim(const Dev& d, T* __restrict__ P, long long pc, int i, int j,
+                                           int k, const double* p)
+{
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        P[v * d.sv + pc] = (T)p[v];
+    const int idx[3] = {i, j, k};
+    const long long stride[3] = {1, d.px, (long long)d.px * d.py};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!d.act[a])
+            continue;
+        const int n = d.n[a];
+        const long long st = stride[a];
+        if (d.bc[a] == 0) {
+            if (idx[a] < 2) {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    P[v * d.sv + pc + n * st] = (T)p[v];
+            }
+            if (idx[a] >= n - 2) {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    P[v * d.sv + pc - n * st] = (T)p[v];
+            }
+        } else if (idx[a] == 0 || idx[a] == n - 1) {
+            const long long s1 = idx[a] == 0 ? -st : st;
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                P[v * d.sv + pc + s1] = (T)p[v];
+                P[v * d.sv + pc + 2 * s1] = (T)p[v];
+            }
+        }
+    }
+}
+
+// Runge-Kutta combination U^(s+1) = U^s + a (U^n - U^s) + b dt R and recovery
+// of the primitives for one cell (all in double); q are the cell's current
+// primitives (the Newton guess).  Writes U^(s+1) and the new primitives (with
+// their ghost images).  TS and TO are the types of the stage states read and
+// written: double, or float for the intermediate stages of the mixed path.
+// fout (may be null) receives the cell's recovery flags.
+template <typename T, typename TS, typename TO>
 __device__ __forceinline__ int stage_cell(const Dev& d, const Geo& g, const double* R, const T* q,
-                                          const double* Un, const double* Us, double* Uout, long long c,
-                                          T* Pout, long long pc, double dt, double a, double b,
-                                          int& iters)
+                                          const double* Un, const TS* Us, TO* Uout, long long c,
+                                          T* Pout, long long pc, int i, int j, int k, double dt,
+                                          double a, double b, unsigned char* fout, int& iters)
 {
     double u[9], p[9], qg[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
-        double un = Un[v * d.N + c], us = Us[v * d.N + c];
+        double un = Un[v * d.N + c], us = (double)Us[v * d.N + c];
         u[v] = us + a * (un - us) + b * (dt * R[v]);
         qg[v] = (double)q[v];
     }
     int flags = recover_cell(d, g, u, qg, p, iters);
 #pragma unroll
-    for (int v = 0; v < 9; ++v) {
-        Uout[v * d.N + c] = u[v];
-        Pout[v * d.sv + pc] = (T)p[v];
-    }
+    for (int v = 0; v < 9; ++v)
+        Uout[v * d.N + c] = (TO)u[v];
+    store_prim(d, Pout, pc, i, j, k, p);
+    if (fout)
+        fout[c] = (unsigned char)flags;
     return flags;
 }
 
 // 1D/2D update: flux differences, sources, RK combination and recovery of the
-// primitives (in place in the cache), for every cell.
-template <int KIND, typename T>
+// primitives for every cell.  The cell's primitives are read from Pc and the
+// new ones written to Pn (which may be Pc: each thread reads only its own cell).
+template <int KIND, typename T, typename TS, typename TO>
 __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, const T* __restrict__ Fy,
-                                                 const T* __restrict__ Fz, T* __restrict__ Pc,
-                                                 const double* Un, const double* Us, double* Uout, Dev d,
+                                                 const T* __restrict__ Fz, const T* Pc, T* Pn,
+                                                 const double* Un, const TS* Us, TO* Uout, Dev d,
                                                  double dt, double a, double b,
-                                                 unsigned long long* __restrict__ cnt)
+                                                 unsigned long long* __restrict__ cnt,
+                                                 unsigned char* __restrict__ fout)
 {
     long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
     int nf = 0, na = 0, np = 0, nb = 0, itmax = 0;
@@ -400,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, cons
         Geo g;
         rhs_cell<KIND>(d, Fx, Fy, Fz, c, i, j, k, q, g, R);
         int iters = 0;
-        int flags = stage_cell(d, g, R, q, Un, Us, Uout, c, Pc, pc, dt, a, b, iters);
+        int flags = stage_cell(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
         tally(flags, iters, nf, na, np, nb, itmax);
     }
     count_sums(cnt, nf, na, np, nb, itmax);
@@ -413,11 +381,11 @@ __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, cons
 // x/y face fluxes, adds the sources, combines the RK stage and recovers the
 // primitives, written to the other primitive cache Pn (segments of one column
 // overlap by two cells, so the cache read here cannot be updated in place).
-template <int KIND, int SEG, typename T>
+template <int KIND, int SEG, typename T, typename TS, typename TO>
 __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
     const T* __restrict__ Fx, const T* __restrict__ Fy, const T* __restrict__ Pc, T* __restrict__ Pn,
-    const double* Un, const double* Us, double* Uout, Dev d, double dt, double a, double b,
-    unsigned long long* __restrict__ cnt)
+    const double* Un, const TS* Us, TO* Uout, Dev d, double dt, double a, double b,
+    unsigned long long* __restrict__ cnt, unsigned char* __restrict__ fout)
 {
     const int nz = d.n[2];
     const int nseg = (nz + SEG - 1) / SEG;
@@ -501,7 +469,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
             add_sources<KIND>(d, x, y, z, q, g, R);
             int iters = 0;
             const long long pc = col + (long long)(k + d.g[2]) * st;
-            int flags = stage_cell(d, g, R, q, Un, Us, Uout, c, Pn, pc, dt, a, b, iters);
+            int flags = stage_cell(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
             tally(flags, iters, nfail, natm, npf, nfb, itmax);
         }
     }
@@ -548,10 +516,9 @@ __global__ __launch_bounds__(BLOCK) void k_cons(const double* __restrict__ P, do
     long long pc = cache_index(d, i, j, k);
     double q[9];
 #pragma unroll
-    for (int v = 0; v < 9; ++v) {
+    for (int v = 0; v < 9; ++v)
         q[v] = P[v * d.N + c];
-        Pc[v * d.sv + pc] = (T)q[v];
-    }
+    store_prim(d, Pc, pc, i, j, k, q);
     if (U) {
         const GeoT<double> g = geo_cast<double>(geo_at<KIND>(
             d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1], d.lo[2] + (k + 0.5) * d.dx[2]));
@@ -588,13 +555,249 @@ __global__ __launch_bounds__(BLOCK) void k_prim(const double* __restrict__ U, do
         int iters = 0;
         int flags = recover_cell(d, g, u, q, p, iters);
 #pragma unroll
-        for (int v = 0; v < 9; ++v) {
+        for (int v = 0; v < 9; ++v)
             P[v * d.N + c] = p[v];
-            Pc[v * d.sv + pc] = (T)p[v];
-        }
+        store_prim(d, Pc, pc, i, j, k, p);
         tally(flags, iters, nf, na, np, nb, itmax);
     }
     count_sums(cnt, nf, na, np, nb, itmax);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched ensemble of independent 1D problems (flat metric, along x).
+//
+// Every problem b has n_b cells, its own dx and dt, and a step budget.  The
+// packed arrays hold problem b's 9 x n_b values from element 9 * off_b on,
+// variable-major.  The primitive row of a problem (9 rows of n_b + 4 values,
+// two ghosts each side) lives in global memory between calls and, during the
+// evolve kernel, in LDS when it fits.
+//
+// k_batch_evolve: one persistent workgroup per problem runs all its steps.
+// Thread t owns the contiguous cells [t*ch, (t+1)*ch) with ch = ceil(n/NT);
+// per substep it marches over them computing each face once (the
+// previous face flux stays in registers), forms the flux difference and the
+// source, combines the Runge-Kutta stage (U^n from U, the intermediate stage
+// state in Us) and recovers the primitives, written to the next row.  A
+// barrier ends the substep (with the row in LDS, after a copy of the own
+// cells from the global staging row back into LDS and a second barrier).
+
+__device__ __forceinline__ int batch_find(const BatchProb* __restrict__ probs, int nprob, long long c)
+{
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].off <= c)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Primitive value and its ghost images in a ghosted row of pitch n + 4.
+template <typename T>
+__device__ __forceinline__ void row_store(T* __restrict__ row, int pitch, int n, int bc, int c, const double* p)
+{
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        row[v * pitch + c + 2] = (T)p[v];
+    int o[2], no = 0;
+    if (bc == 0) {
+        if (c < 2)
+            o[no++] = c + n;
+        if (c >= n - 2)
+            o[no++] = c - n;
+    } else if (c == 0) {
+        o[no++] = -1;
+        o[no++] = -2;
+    } else if (c == n - 1) {
+        o[no++] = n;
+        o[no++] = n + 1;
+    }
+    for (int e = 0; e < no; ++e)
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            row[v * pitch + o[e] + 2] = (T)p[v];
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_batch_cons(const BatchProb* __restrict__ probs, int nprob,
+                                                     long long ncell, const double* __restrict__ P,
+                                                     double* __restrict__ U, T* __restrict__ Prow, Dev d)
+{
+    const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (g >= ncell)
+        return;
+    const int b = batch_find(probs, nprob, g);
+    const BatchProb pr = probs[b];
+    const int c = (int)(g - pr.off);
+    double q[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        q[v] = P[9 * pr.off + (long long)v * pr.n + c];
+    row_store(Prow + pr.poff, pr.n + 4, pr.n, d.bc[0], c, q);
+    if (U) {
+        const GeoT<double> gt = geo_cast<double>(geo_at<FLAT>(d, 0.0, 0.0, 0.0));
+        const Kin<double> kk = kinematics(q, gt, d.gfac);
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            U[9 * pr.off + (long long)v * pr.n + c] = cons_comp(v, q, kk, gt);
+        U[9 * pr.off + 8LL * pr.n + c] = q[8];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_batch_prim(const BatchProb* __restrict__ probs, int nprob,
+                                                     long long ncell, const double* __restrict__ U,
+                                                     double* __restrict__ P, T* __restrict__ Prow, Dev d,
+                                                     unsigned long long* __restrict__ cnt)
+{
+    const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    int nf = 0, na = 0, np = 0, nb = 0, itmax = 0;
+    if (g < ncell) {
+        const int b = batch_find(probs, nprob, g);
+        const BatchProb pr = probs[b];
+        const int c = (int)(g - pr.off);
+        const int pitch = pr.n + 4;
+        double u[9], q[9], p[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            u[v] = U[9 * pr.off + (long long)v * pr.n + c];
+            q[v] = (double)Prow[pr.poff + v * pitch + c + 2];
+        }
+        const Geo geo = geo_at<FLAT>(d, 0.0, 0.0, 0.0);
+        int iters = 0;
+        const int flags = recover_cell(d, geo, u, q, p, iters);
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            P[9 * pr.off + (long long)v * pr.n + c] = p[v];
+        row_store(Prow + pr.poff, pitch, pr.n, d.bc[0], c, p);
+        tally(flags, iters, nf, na, np, nb, itmax);
+    }
+    count_sums(cnt, nf, na, np, nb, itmax);
+}
+
+template <typename T, int NT, bool LDS>
+__global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ probs, const int* __restrict__ order,
+                                                     double* __restrict__ U, T* __restrict__ Us,
+                                                     T* __restrict__ Prow, T* __restrict__ Pnext, Dev d, int ns,
+                                                     int max_steps, unsigned long long* __restrict__ cnt)
+{
+    extern __shared__ unsigned char smem[];
+    const int b = order[blockIdx.x];
+    const BatchProb pr = probs[b];
+    const int n = pr.n, pitch = n + 4;
+    // LDS: the row lives in LDS and new values go through the global row
+    // Pnext (own cells only).  Global: the rows Prow and Pnext alternate.
+    T* cur = LDS ? (T*)smem : Prow + pr.poff;
+    T* nxt = Pnext + pr.poff;
+    if (LDS) {
+        for (int e = threadIdx.x; e < 9 * pitch; e += NT)
+            cur[e] = Prow[pr.poff + e];
+        __syncthreads();
+    }
+    const int nsteps = min(max_steps, pr.steps - pr.done);
+    const int ch = (n + NT - 1) / NT;
+    const int c0 = min((int)threadIdx.x * ch, n), c1 = min(c0 + ch, n);
+    double* Ub = U + 9 * pr.off;
+    T* Usb = Us + 9 * pr.off;
+    const Geo geo = geo_at<FLAT>(d, 0.0, 0.0, 0.0);
+    const T half = T(0.5);
+    int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
+    for (int step = 0; step < nsteps; ++step) {
+        for (int s = 0; s < ns; ++s) {
+            const double a = ns == 3 ? (s == 0 ? 0.0 : (s == 1 ? 0.75 : 1.0 / 3.0)) : (s == 0 ? 0.0 : 0.5);
+            const double bb = ns == 3 ? (s == 0 ? 1.0 : (s == 1 ? 0.25 : 2.0 / 3.0)) : (s == 0 ? 1.0 : 0.5);
+            T Fp[9];
+            if (c0 < c1) {
+                // face c0 - 1/2 from cells c0-2 .. c0+1 (row index + 2)
+                T qL[9], qR[9];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    const T* r = cur + v * pitch + c0;
+                    const T q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3];
+                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
+                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                }
+                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, d, Fp);
+            }
+            for (int c = c0; c < c1; ++c) {
+                T qL[9], qR[9], Fc[9], q[9];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    const T* r = cur + v * pitch + c + 1;      // cells c-1 .. c+2
+                    const T q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3];
+                    q[v] = q1;
+                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
+                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                }
+                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, d, Fc);
+                double R[9];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    R[v] = -((double)Fc[v] - (double)Fp[v]) * pr.idx;
+                    Fp[v] = Fc[v];
+                }
+                R[8] -= d.kappa * (double)q[8];
+                double u[9], qg[9], p[9];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    const double un = Ub[(long long)v * n + c];
+                    const double us = s == 0 ? un : (double)Usb[(long long)v * n + c];
+                    u[v] = us + a * (un - us) + bb * (pr.dt * R[v]);
+                    qg[v] = (double)q[v];
+                }
+                int iters = 0;
+                const int flags = recover_cell(d, geo, u, qg, p, iters);
+                tally(flags, iters, nfail, natm, npf, nfb, itmax);
+                if (s == ns - 1) {
+#pragma unroll
+                    for (int v = 0; v < 9; ++v)
+                        Ub[(long long)v * n + c] = u[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 9; ++v)
+                        Usb[(long long)v * n + c] = (T)u[v];
+                }
+                if (LDS) {
+#pragma unroll
+                    for (int v = 0; v < 9; ++v)
+                        nxt[v * pitch + c + 2] = (T)p[v];
+                } else {
+                    row_store(nxt, pitch, n, d.bc[0], c, p);
+                }
+            }
+            __syncthreads();
+            if (LDS) {
+                // own cells only: this thread wrote them, so no fence is needed
+                for (int c = c0; c < c1; ++c) {
+                    double p[9];
+#pragma unroll
+                    for (int v = 0; v < 9; ++v)
+                        p[v] = (double)nxt[v * pitch + c + 2];
+                    row_store(cur, pitch, n, d.bc[0], c, p);
+                }
+                __syncthreads();
+            } else {
+                T* t = cur;
+                cur = nxt;
+                nxt = t;
+            }
+        }
+    }
+    if (LDS) {
+        for (int e = threadIdx.x; e < 9 * pitch; e += NT)
+            Prow[pr.poff + e] = cur[e];
+    } else if (cur != Prow + pr.poff) {
+        // an odd number of substeps left the row in Pnext (every write to it
+        // is behind the last barrier)
+        for (int e = threadIdx.x; e < 9 * pitch; e += NT)
+            Prow[pr.poff + e] = cur[e];
+    }
+    if (threadIdx.x == 0)
+        probs[b].done = pr.done + nsteps;
+    count_sums(cnt, nfail, natm, npf, nfb, itmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,34 +860,34 @@ hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipSt
     return kind == FLAT ? launch_flux_k<FLAT>(dir, Pc, F, d, s) : launch_flux_k<ISO>(dir, Pc, F, d, s);
 }
 
-template <typename T>
-hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, T* Pc, const double* Un,
-                         const double* Us, double* Uout, const Dev& d, double dt, double a, double b,
-                         unsigned long long* cnt, hipStream_t s)
+template <typename T, typename TS, typename TO>
+hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, const T* Pc, T* Pn, const double* Un,
+                         const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
+                         unsigned long long* cnt, unsigned char* fout, hipStream_t s)
 {
     unsigned nb = blocks_for(d.N);
     if (kind == FLAT)
-        hipLaunchKernelGGL((k_update<FLAT, T>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Un, Us, Uout, d,
-                           dt, a, b, cnt);
+        hipLaunchKernelGGL((k_update<FLAT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
+                           Uout, d, dt, a, b, cnt, fout);
     else
-        hipLaunchKernelGGL((k_update<ISO, T>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Un, Us, Uout, d,
-                           dt, a, b, cnt);
+        hipLaunchKernelGGL((k_update<ISO, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
+                           Uout, d, dt, a, b, cnt, fout);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename TS, typename TO>
 hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc, T* Pn, const double* Un,
-                                const double* Us, double* Uout, const Dev& d, double dt, double a,
-                                double b, unsigned long long* cnt, hipStream_t s)
+                                const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
+                                unsigned long long* cnt, unsigned char* fout, hipStream_t s)
 {
     long long nseg = (d.n[2] + MARCH_SEG - 1) / MARCH_SEG;
     unsigned nb = blocks_for((long long)d.n[0] * d.n[1] * nseg);
     if (kind == FLAT)
-        hipLaunchKernelGGL((k_update_zmarch<FLAT, MARCH_SEG, T>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
-                           Un, Us, Uout, d, dt, a, b, cnt);
+        hipLaunchKernelGGL((k_update_zmarch<FLAT, MARCH_SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy,
+                           Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
     else
-        hipLaunchKernelGGL((k_update_zmarch<ISO, MARCH_SEG, T>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
-                           Un, Us, Uout, d, dt, a, b, cnt);
+        hipLaunchKernelGGL((k_update_zmarch<ISO, MARCH_SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy,
+                           Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
     return hipGetLastError();
 }
 
@@ -723,17 +926,90 @@ hipError_t launch_prim(int kind, const double* U, double* P, T* Pc, const Dev& d
     return hipGetLastError();
 }
 
+
+template <typename T>
+hipError_t launch_batch_cons(const BatchProb* probs, int nprob, long long ncell, const double* P, double* U,
+                             T* Prow, const Dev& d, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batch_cons<T>), dim3(blocks_for(ncell)), dim3(BLOCK), 0, s, probs, nprob, ncell, P, U,
+                       Prow, d);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_prim(const BatchProb* probs, int nprob, long long ncell, const double* U, double* P,
+                             T* Prow, const Dev& d, unsigned long long* cnt, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batch_prim<T>), dim3(blocks_for(ncell)), dim3(BLOCK), 0, s, probs, nprob, ncell, U, P,
+                       Prow, d, cnt);
+    return hipGetLastError();
+}
+
+template <typename T, int NT>
+static hipError_t batch_evolve_k(int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
+                                 double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int ns, int max_steps,
+                                 unsigned long long* cnt, hipStream_t s)
+{
+    if (lds) {
+        // dynamic LDS beyond the default launch limit must be allowed explicitly
+        hipError_t e = hipFuncSetAttribute((const void*)k_batch_evolve<T, NT, true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((k_batch_evolve<T, NT, true>), dim3(nprob), dim3(NT), lds_bytes, s, probs, order, U,
+                           Us, Prow, Pnext, d, ns, max_steps, cnt);
+    } else
+        hipLaunchKernelGGL((k_batch_evolve<T, NT, false>), dim3(nprob), dim3(NT), 0, s, probs, order, U, Us,
+                           Prow, Pnext, d, ns, max_steps, cnt);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
+                               double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps,
+                               unsigned long long* cnt, hipStream_t s)
+{
+    switch (shape) {
+    case 0:
+        return batch_evolve_k<T, 256>(lds, lds_bytes, probs, order, nprob, U, Us, Prow, Pnext, d, rk_order,
+                                          max_steps, cnt, s);
+    case 1:
+        return batch_evolve_k<T, 512>(lds, lds_bytes, probs, order, nprob, U, Us, Prow, Pnext, d, rk_order,
+                                         max_steps, cnt, s);
+    default:
+        return batch_evolve_k<T, 1024>(lds, lds_bytes, probs, order, nprob, U, Us, Prow, Pnext, d, rk_order,
+                                          max_steps, cnt, s);
+    }
+}
+
 // explicit instantiations for the two precisions
+#define GRMHD_INSTANTIATE_UPDATE(T, TS, TO)                                                             \
+    template hipError_t launch_update<T, TS, TO>(int, const T*, const T*, const T*, const T*, T*,       \
+                                                 const double*, const TS*, TO*, const Dev&, double,     \
+                                                 double, double, unsigned long long*, unsigned char*,   \
+                                                 hipStream_t);                                          \
+    template hipError_t launch_update_zmarch<T, TS, TO>(int, const T*, const T*, const T*, T*,          \
+                                                        const double*, const TS*, TO*, const Dev&,      \
+                                                        double, double, double, unsigned long long*,    \
+                                                        unsigned char*, hipStream_t);
+#define GRMHD_INSTANTIATE_BATCH(T)                                                                      \
+    template hipError_t launch_batch_cons<T>(const BatchProb*, int, long long, const double*, double*, T*,     \
+                                             const Dev&, hipStream_t);                                        \
+    template hipError_t launch_batch_prim<T>(const BatchProb*, int, long long, const double*, double*, T*,     \
+                                             const Dev&, unsigned long long*, hipStream_t);                   \
+    template hipError_t launch_batch_evolve<T>(int, int, size_t, BatchProb*, const int*, int, double*, T*, T*, \
+                                               T*, const Dev&, int, int, unsigned long long*, hipStream_t);
+GRMHD_INSTANTIATE_BATCH(double)
+GRMHD_INSTANTIATE_BATCH(float)
+GRMHD_INSTANTIATE_UPDATE(double, double, double)
+GRMHD_INSTANTIATE_UPDATE(float, double, float)
+GRMHD_INSTANTIATE_UPDATE(float, float, float)
+GRMHD_INSTANTIATE_UPDATE(float, float, double)
+
 #define GRMHD_INSTANTIATE(T)                                                                            \
     template hipError_t launch_fill<T>(T*, long long, double, hipStream_t);                             \
     template hipError_t launch_ghosts<T>(T*, const Dev&, hipStream_t);                                  \
     template hipError_t launch_flux<T>(int, int, const T*, T*, const Dev&, hipStream_t);               \
-    template hipError_t launch_update<T>(int, const T*, const T*, const T*, T*, const double*,          \
-                                         const double*, double*, const Dev&, double, double, double,    \
-                                         unsigned long long*, hipStream_t);                             \
-    template hipError_t launch_update_zmarch<T>(int, const T*, const T*, const T*, T*, const double*,   \
-                                                const double*, double*, const Dev&, double, double,     \
-                                                double, unsigned long long*, hipStream_t);              \
     template hipError_t launch_rhs<T>(int, const T*, const T*, const T*, const T*, double*, const Dev&,  \
                                       hipStream_t);                                                     \
     template hipError_t launch_cons<T>(int, const double*, double*, T*, const Dev&, hipStream_t);      \

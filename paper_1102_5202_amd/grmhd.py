@@ -19,13 +19,17 @@ SOFT_SQRT, SOFT_MAX = 0, 1
 PERIODIC, OUTFLOW = 0, 1
 FP64, MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
-KERNELS = ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs")
+KERNELS = ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs", "adj_rec",
+           "adj_face", "adj_gather", "adj_fold")
 NVAR = 9
 
 # exported symbols of include/grmhd.h
 SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_cons", "grmhd_step",
-           "grmhd_prim", "grmhd_rhs", "grmhd_status", "grmhd_timing", "grmhd_free",
-           "grmhd_strerror")
+           "grmhd_prim", "grmhd_rhs", "grmhd_step_adjoint", "grmhd_cons_adjoint",
+           "grmhd_prim_adjoint", "grmhd_status", "grmhd_timing", "grmhd_free", "grmhd_strerror",
+           "grmhd_batch_workspace_bytes", "grmhd_batch_init", "grmhd_batch_set_stream",
+           "grmhd_batch_cons", "grmhd_batch_evolve", "grmhd_batch_prim", "grmhd_batch_tune",
+           "grmhd_batch_status", "grmhd_batch_free")
 
 
 class Metric(C.Structure):
@@ -45,7 +49,13 @@ class Opts(C.Structure):
     _fields_ = [("rk_order", C.c_int), ("precision", C.c_int), ("c_h", C.c_double),
                 ("kappa", C.c_double), ("rho_atm", C.c_double), ("p_atm", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("timing", C.c_int),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("adjoint", C.c_int), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("nprob", C.c_int), ("n", C.POINTER(C.c_int)), ("lo", C.POINTER(C.c_double)),
+                ("hi", C.POINTER(C.c_double)), ("dt", C.POINTER(C.c_double)),
+                ("steps", C.POINTER(C.c_int)), ("bc", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -76,13 +86,26 @@ def load(path: str = LIB_PATH):
     L.grmhd_step.argtypes = [vp, vp, C.c_double]
     L.grmhd_prim.argtypes = [vp, vp, vp]
     L.grmhd_rhs.argtypes = [vp, vp, vp]
+    L.grmhd_step_adjoint.argtypes = [vp, vp, vp, C.c_double]
+    L.grmhd_cons_adjoint.argtypes = [vp, vp, vp, vp]
+    L.grmhd_prim_adjoint.argtypes = [vp, vp, vp, vp]
     L.grmhd_status.argtypes = [vp, C.POINTER(Stats), C.c_int]
+    L.grmhd_batch_workspace_bytes.argtypes = [C.POINTER(BatchDesc), C.POINTER(Opts)]
+    L.grmhd_batch_workspace_bytes.restype = C.c_size_t
+    L.grmhd_batch_init.argtypes = [C.POINTER(vp), C.POINTER(BatchDesc), C.POINTER(Eos), C.POINTER(Opts)]
+    L.grmhd_batch_set_stream.argtypes = [vp, vp]
+    L.grmhd_batch_cons.argtypes = [vp, vp, vp]
+    L.grmhd_batch_evolve.argtypes = [vp, vp, C.c_int]
+    L.grmhd_batch_prim.argtypes = [vp, vp, vp]
+    L.grmhd_batch_tune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.grmhd_batch_status.argtypes = [vp, C.POINTER(Stats), C.c_int]
+    L.grmhd_batch_free.argtypes = [vp]
     L.grmhd_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
     L.grmhd_free.argtypes = [vp]
     L.grmhd_strerror.argtypes = [C.c_int]
     L.grmhd_strerror.restype = C.c_char_p
     for name in SYMBOLS:
-        if name not in ("grmhd_workspace_bytes", "grmhd_strerror"):
+        if name not in ("grmhd_workspace_bytes", "grmhd_strerror", "grmhd_batch_workspace_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -104,9 +127,12 @@ def make_grid(n, lo, hi, bc) -> Grid:
     return g
 
 
-def workspace_bytes(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0, 0, 0), precision="fp64") -> int:
+def workspace_bytes(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0, 0, 0), precision="fp64",
+                    rk_order=3, adjoint=False) -> int:
     o = Opts()
     o.precision = PRECISIONS[precision]
+    o.rk_order = int(rk_order)
+    o.adjoint = int(bool(adjoint))
     return int(load().grmhd_workspace_bytes(C.byref(make_grid(n, lo, hi, bc)), C.byref(o)))
 
 
@@ -117,12 +143,13 @@ class Solver:
     Tensors are float64, contiguous, shape (9, nz, ny, nx), on the solver's
     device: P = (rho, p, u~x, u~y, u~z, Bx, By, Bz, Phi),
     U = (D, tau, Sx, Sy, Sz, Bdx, Bdy, Bdz, Phi).  precision "fp64" or
-    "mixed" (float face physics and caches, double accumulation and recovery)."""
+    "mixed" (float face physics and caches, double accumulation and recovery).
+    adjoint=True (FP64 only) reserves the workspace of the adjoint calls."""
 
     def __init__(self, n, lo, hi, bc, metric=FLAT, M=0.0, soft=SOFT_SQRT, r_min=1.0,
                  gamma=5.0 / 3.0, K=0.0, rk_order=3, c_h=1.0, kappa=1.0, rho_atm=1e-12,
                  p_atm=1e-12, newton_tol=1e-12, newton_maxit=50, timing=False, device="cuda",
-                 stream=None, precision="fp64"):
+                 stream=None, precision="fp64", adjoint=False):
         L = load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -137,7 +164,7 @@ class Solver:
         self.precision = precision
         self._opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa),
                           float(rho_atm), float(p_atm), float(newton_tol), int(newton_maxit),
-                          int(bool(timing)), None, 0)
+                          int(bool(timing)), int(bool(adjoint)), None, 0)
         nbytes = int(L.grmhd_workspace_bytes(C.byref(self._grid), C.byref(self._opts)))
         if nbytes == 0:
             raise ValueError("invalid grid")
@@ -190,6 +217,30 @@ class Solver:
                "grmhd_rhs")
         return R
 
+    # -- adjoint (vector-Jacobian products) ----------------------------------
+    def step_adjoint(self, U: torch.Tensor, Ubar: torch.Tensor, dt: float) -> torch.Tensor:
+        """Ubar <- (dU^(n+1)/dU^n)^T Ubar for one step from U (not modified)."""
+        _check(load().grmhd_step_adjoint(self._ctx, C.c_void_p(self._t(U, "U")),
+                                         C.c_void_p(self._t(Ubar, "Ubar")), float(dt)),
+               "grmhd_step_adjoint")
+        return Ubar
+
+    def cons_adjoint(self, P: torch.Tensor, Ubar: torch.Tensor, Pbar: torch.Tensor = None) -> torch.Tensor:
+        """Pbar = (dU/dP)^T Ubar at P."""
+        Pbar = self.empty() if Pbar is None else Pbar
+        _check(load().grmhd_cons_adjoint(self._ctx, C.c_void_p(self._t(P, "P")),
+                                         C.c_void_p(self._t(Ubar, "Ubar")),
+                                         C.c_void_p(self._t(Pbar, "Pbar"))), "grmhd_cons_adjoint")
+        return Pbar
+
+    def prim_adjoint(self, U: torch.Tensor, Pbar: torch.Tensor, Ubar: torch.Tensor = None) -> torch.Tensor:
+        """Ubar = (dU/dP)^-T Pbar at the primitives of U."""
+        Ubar = self.empty() if Ubar is None else Ubar
+        _check(load().grmhd_prim_adjoint(self._ctx, C.c_void_p(self._t(U, "U")),
+                                         C.c_void_p(self._t(Pbar, "Pbar")),
+                                         C.c_void_p(self._t(Ubar, "Ubar"))), "grmhd_prim_adjoint")
+        return Ubar
+
     def status(self, reset: bool = False) -> dict:
         st = Stats()
         _check(load().grmhd_status(self._ctx, C.byref(st), int(bool(reset))), "grmhd_status")
@@ -212,6 +263,119 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class BatchSolver:
+    """An ensemble of independent 1D problems along x (flat metric), advanced
+    in one persistent launch per call.  Packed float64 device arrays: problem
+    b's (9, n_b) block follows problem b-1's; ``pack``/``unpack`` convert
+    from and to per-problem (9, n_b) arrays."""
+
+    def __init__(self, n, lo, hi, dt, steps, bc=OUTFLOW, gamma=5.0 / 3.0, K=0.0, rk_order=3,
+                 c_h=1.0, kappa=1.0, rho_atm=1e-12, p_atm=1e-12, newton_tol=1e-12, newton_maxit=50,
+                 device="cuda", stream=None, precision="fp64"):
+        L = load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise RuntimeError("BatchSolver needs a GPU device; got %s" % self.device)
+        self.n = [int(v) for v in n]
+        self.nprob = len(self.n)
+        self.offsets = [0]
+        for v in self.n[:-1]:
+            self.offsets.append(self.offsets[-1] + v)
+        self.ncell = sum(self.n)
+        self._arrays = ((C.c_int * self.nprob)(*self.n), (C.c_double * self.nprob)(*map(float, lo)),
+                        (C.c_double * self.nprob)(*map(float, hi)), (C.c_double * self.nprob)(*map(float, dt)),
+                        (C.c_int * self.nprob)(*map(int, steps)))
+        self._desc = BatchDesc(self.nprob, *self._arrays, int(bc))
+        self._eos = Eos(0, float(gamma), float(K))
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
+        self.precision = precision
+        self._opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa), float(rho_atm),
+                          float(p_atm), float(newton_tol), int(newton_maxit), 0, 0, None, 0)
+        nbytes = int(L.grmhd_batch_workspace_bytes(C.byref(self._desc), C.byref(self._opts)))
+        if nbytes == 0:
+            raise ValueError("invalid batch description")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._opts.workspace = C.c_void_p(self.workspace.data_ptr())
+        self._opts.workspace_bytes = nbytes
+        ctx = C.c_void_p()
+        _check(L.grmhd_batch_init(C.byref(ctx), C.byref(self._desc), C.byref(self._eos),
+                                  C.byref(self._opts)), "grmhd_batch_init")
+        self._ctx = ctx
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = st
+        _check(L.grmhd_batch_set_stream(self._ctx, C.c_void_p(st.cuda_stream)), "grmhd_batch_set_stream")
+
+    def _t(self, x: torch.Tensor, name: str) -> int:
+        if (not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_contiguous()
+                or x.device != self.device or x.numel() != 9 * self.ncell):
+            raise ValueError("%s must be a contiguous float64 tensor of %d values on %s"
+                             % (name, 9 * self.ncell, self.device))
+        return x.data_ptr()
+
+    def pack(self, arrays) -> torch.Tensor:
+        """Per-problem arrays of shape (9, n_b) (or (9, 1, 1, n_b)) to one packed tensor."""
+        return torch.cat([torch.as_tensor(a, dtype=torch.float64).reshape(9, -1).reshape(-1)
+                          for a in arrays]).to(self.device)
+
+    def unpack(self, x: torch.Tensor):
+        return [x[9 * o:9 * (o + n)].reshape(9, n) for o, n in zip(self.offsets, self.n)]
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(9 * self.ncell, dtype=torch.float64, device=self.device)
+
+    def cons(self, P: torch.Tensor, U: torch.Tensor = None) -> torch.Tensor:
+        U = self.empty() if U is None else U
+        _check(load().grmhd_batch_cons(self._ctx, C.c_void_p(self._t(P, "P")), C.c_void_p(self._t(U, "U"))),
+               "grmhd_batch_cons")
+        return U
+
+    def evolve(self, U: torch.Tensor, max_steps: int = 2 ** 31 - 1) -> torch.Tensor:
+        _check(load().grmhd_batch_evolve(self._ctx, C.c_void_p(self._t(U, "U")), int(max_steps)),
+               "grmhd_batch_evolve")
+        return U
+
+    def prim(self, U: torch.Tensor, P: torch.Tensor = None) -> torch.Tensor:
+        P = self.empty() if P is None else P
+        _check(load().grmhd_batch_prim(self._ctx, C.c_void_p(self._t(U, "U")), C.c_void_p(self._t(P, "P"))),
+               "grmhd_batch_prim")
+        return P
+
+    def tune(self, U: torch.Tensor, trial_steps: int = 20):
+        """Pick the fastest launch shape on copies of the state; returns
+        (threads per workgroup, primitive rows in LDS)."""
+        th, lds = C.c_int(), C.c_int()
+        _check(load().grmhd_batch_tune(self._ctx, C.c_void_p(self._t(U, "U")), int(trial_steps),
+                                       C.byref(th), C.byref(lds)), "grmhd_batch_tune")
+        return th.value, bool(lds.value)
+
+    def status(self, reset: bool = False) -> dict:
+        st = Stats()
+        _check(load().grmhd_batch_status(self._ctx, C.byref(st), int(bool(reset))), "grmhd_batch_status")
+        return {"fail": st.c2p_fail, "atm": st.atm_hits, "pfloor": st.p_floor_hits,
+                "fallback_1d": st.fallback_1d, "max_newton_it": st.max_newton_it}
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None):
+            load().grmhd_batch_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_for(ensemble, **over) -> BatchSolver:
+    """A BatchSolver for a :class:`workloads.Ensemble`."""
+    kw = dict(n=ensemble.n, lo=[0.0] * len(ensemble.n), hi=[1.0] * len(ensemble.n), dt=ensemble.dt,
+              steps=ensemble.steps, bc=ensemble.bc, gamma=ensemble.gamma, rk_order=ensemble.rk_order,
+              rho_atm=ensemble.rho_atm, p_atm=ensemble.p_atm)
+    kw.update(over)
+    return BatchSolver(**kw)
 
 
 def solver_for(workload, **over) -> Solver:

@@ -339,6 +339,53 @@ def smooth_box(n=(8, 7, 6), k: int = 0, metric: int = FLAT, rk_order: int = 2,
                     M=1.0 if metric == ISO_SCHW else 0.0)
 
 
+@dataclass
+class Ensemble:
+    """Independent 1D problems on [0, 1] along x (flat metric, shared EOS and
+    boundary rule): problem b has n[b] cells, time step dt[b] and takes
+    steps[b] steps; P[b] is its (9, n[b]) initial primitive array."""
+    name: str
+    P: list
+    n: list
+    dt: list
+    steps: list
+    gamma: float = 5.0 / 3.0
+    rk_order: int = 3
+    bc: int = OUTFLOW
+    rho_atm: float = 1e-12
+    p_atm: float = 1e-12
+
+    @property
+    def ncell(self) -> int:
+        return int(sum(self.n))
+
+    def problem(self, b: int) -> Workload:
+        """Problem b as a single-grid workload."""
+        n = self.n[b]
+        return Workload(name="%s_%d" % (self.name, b), P=self.P[b].reshape(9, 1, 1, n), n=(n, 1, 1),
+                        lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(self.bc,) * 3, gamma=self.gamma,
+                        rk_order=self.rk_order, dt=self.dt[b], nsteps=self.steps[b],
+                        rho_atm=self.rho_atm, p_atm=self.p_atm)
+
+
+def config5(nprob: int = 256, nmin: int = 200, nmax: int = 4000, k: int = 0,
+            t_end: float = 0.4) -> Ensemble:
+    """The batched ensemble: nprob magnetised 1D Riemann problems with lengths
+    n_b uniform in [nmin, nmax] and states drawn as config1 (one seeded
+    stream: all lengths first, then the states of each problem in turn), each
+    on [0, 1] with dt_b = 0.4 / n_b (CFL 0.4) to t_end: steps_b = t_end / dt_b."""
+    rng = rng_for(5, k)
+    ns = [int(v) for v in rng.integers(nmin, nmax + 1, size=nprob)]
+    P, dts, steps = [], [], []
+    for n in ns:
+        L, R = riemann_states(rng)
+        P.append(riemann_1d(L, R, n=n).reshape(9, n))
+        dt = 0.4 / n
+        dts.append(dt)
+        steps.append(int(round(t_end / dt)))
+    return Ensemble(name="ensemble%d_%d_%d" % (nprob, nmin, nmax), P=P, n=ns, dt=dts, steps=steps)
+
+
 def config4(n=64, k: int = 0, nsteps: int = 50) -> Workload:
     """The adjoint workload: the periodic flat box of config2 (RK2) run for
     nsteps, with a seeded target density rho_t = 1 + 0.1 sum of 16 other

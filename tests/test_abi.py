@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 11, names
+    assert len(names) == 23, names
     assert set(names) == set(lib.SYMBOLS)
     L = lib.load()
     for n in names:
@@ -67,18 +67,18 @@ def test_workspace_and_init_validation(lib):
             assert L.grmhd_free(ctx) == 0
         return rc
 
-    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, C.c_void_p(addr), nb)
+    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)
     assert init(ok) == 0
-    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, C.c_void_p(addr), nb - 8)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, C.c_void_p(addr + 8), nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, None, nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb - 8)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr + 8), nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, None, nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)) == -1
     assert init(ok, eos=lib.Eos(0, 2.5, 0.0)) == -1
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 0.4)) == -1   # r_min <= M/2
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 1.0)) == 0
     assert init(ok, metric=lib.Metric(7, 0, 1.0, 1.0)) == -1
-    for code in (0, -1, -2, -3, -4, -99):
+    for code in (0, -1, -2, -3, -4, -5, -99):
         assert L.grmhd_strerror(code)
     # calls out of order are refused before any device work
     ctx = C.c_void_p()
@@ -86,5 +86,73 @@ def test_workspace_and_init_validation(lib):
     assert L.grmhd_step(ctx, C.c_void_p(addr), C.c_double(0.1)) == -4
     assert L.grmhd_step(ctx, None, C.c_double(0.1)) == -1
     assert L.grmhd_cons(ctx, None, None) == -1
+    # adjoint calls on a context without the adjoint workspace
+    p = C.c_void_p(addr)
+    assert L.grmhd_step_adjoint(ctx, p, p, C.c_double(0.1)) == -5
+    assert L.grmhd_prim_adjoint(ctx, p, p, p) == -5
+    assert L.grmhd_cons_adjoint(ctx, p, p, p) == -5
+    assert L.grmhd_step_adjoint(ctx, None, p, C.c_double(0.1)) == -1
     assert L.grmhd_free(ctx) == 0
     assert L.grmhd_free(None) == -1
+
+
+def test_adjoint_workspace(lib):
+    """The adjoint part of the workspace: FP64 only, ns+1 ghosted stage caches,
+    stage flags, four dense arrays, a ghosted cotangent and one axis' 18
+    face-state cotangents on top of the forward workspace."""
+    L = lib.load()
+    n = (16, 8, 6)
+    g = lib.make_grid(n, (0, 0, 0), (1, 1, 1), (0, 1, 1))
+    for rk in (2, 3):
+        o = lib.Opts()
+        o.rk_order = rk
+        fwd = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        o.adjoint = 1
+        adj = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        px = ((16 + 4 + 7) // 8) * 8
+        sv = px * 12 * 10
+        N = 16 * 8 * 6
+        nfmax = max(17 * 8 * 6, 16 * 9 * 6, 16 * 8 * 7)
+        assert adj - fwd >= 8 * 9 * ((rk + 2) * sv + 4 * N) + rk * N + 8 * 18 * nfmax
+        assert adj - fwd <= 8 * 9 * ((rk + 2) * sv + 4 * N) + rk * N + 8 * 18 * nfmax + 256 * 12
+        o.precision = 1                      # mixed: no adjoint workspace, and init refuses it
+        assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) < fwd
+    raw, addr = _host_ws(adj)
+    m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
+    e = lib.Eos(0, 5.0 / 3.0, 0.0)
+    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 1, C.c_void_p(addr), adj)
+    ctx = C.c_void_p()
+    assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
+    o.precision = 0
+    assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == 0
+    assert L.grmhd_free(ctx) == 0
+
+
+def test_batch_workspace_and_init_validation(lib):
+    L = lib.load()
+    n = [20, 35, 7]
+    arrs = ((C.c_int * 3)(*n), (C.c_double * 3)(0, 0, 0), (C.c_double * 3)(1, 1, 1),
+            (C.c_double * 3)(0.02, 0.01, 0.05), (C.c_int * 3)(20, 40, 8))
+    desc = lib.BatchDesc(3, *arrs, lib.OUTFLOW)
+    o = lib.Opts()
+    o.rk_order = 3
+    nb = L.grmhd_batch_workspace_bytes(C.byref(desc), C.byref(o))
+    ncell, nrow = sum(n), sum(9 * (v + 4) for v in n)
+    # counters, two record arrays, order, three rows, stage state, tuning state
+    assert nb >= 8 * (3 * nrow + 9 * ncell + 9 * ncell)
+    o.precision = 1
+    assert L.grmhd_batch_workspace_bytes(C.byref(desc), C.byref(o)) < nb
+    bad = lib.BatchDesc(3, (C.c_int * 3)(20, 1, 7), *arrs[1:], lib.OUTFLOW)
+    assert L.grmhd_batch_workspace_bytes(C.byref(bad), C.byref(o)) == 0
+    o.precision = 0
+    raw, addr = _host_ws(nb)
+    e = lib.Eos(0, 5.0 / 3.0, 0.0)
+    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)
+    ctx = C.c_void_p()
+    assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == 0
+    assert L.grmhd_batch_evolve(ctx, C.c_void_p(addr), 5) == -4      # before cons
+    assert L.grmhd_batch_evolve(ctx, None, 5) == -1
+    assert L.grmhd_batch_tune(ctx, C.c_void_p(addr), 5, None, None) == -4
+    assert L.grmhd_batch_free(ctx) == 0
+    o.workspace_bytes = nb - 8
+    assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == -2

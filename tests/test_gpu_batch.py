@@ -1,0 +1,115 @@
+"""Batched ensemble of 1D problems (grmhd_batch_*) against the oracle run on
+each problem alone.
+
+FP64 bar: relative L1 <= 1e-10 per problem (the oracle and the batch kernel
+evaluate the same scheme in different operation orders).  Mixed: <= 1e-5 on
+the physical variables.  The launch shape and the LDS/global choice change
+which thread computes a face, not what it computes, so results are
+bitwise independent of them."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1102_5202_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_1102_5202_amd import grmhd
+    grmhd.load()
+    return grmhd
+
+
+def _oracle_problem(orc, e, b):
+    w = e.problem(b)
+    pb = orc.Problem(**w.problem_kwargs())
+    U0 = orc.prim2con(pb, w.P)
+    U, P, st = orc.step(pb, U0, w.P, w.dt, w.nsteps)
+    return U.reshape(9, -1), P.reshape(9, -1)
+
+
+@pytest.mark.parametrize("bc", [WL.OUTFLOW, WL.PERIODIC])
+def test_batch_matches_oracle(G, orc, bc):
+    e = WL.config5(nprob=12, nmin=20, nmax=150, k=1)
+    e.bc = bc
+    s = G.batch_for(e, device=DEV)
+    P0 = s.pack(e.P)
+    U = s.cons(P0)
+    s.evolve(U)
+    P = s.prim(U)
+    st = s.status()
+    Us, Ps = s.unpack(U.cpu()), s.unpack(P.cpu())
+    worst = 0.0
+    for b in range(e.n.__len__()):
+        Ur, Pr = _oracle_problem(orc, e, b)
+        err = orc.parity_error(Us[b].numpy(), Ur)
+        worst = max(worst, float(err[:8].max()))
+        assert np.all(err[:8] <= 1e-10), (b, e.n[b], err)
+        assert np.all(Us[b][8].numpy() == 0.0)
+    say("batch bc=%d worst rel-L1 %.3g" % (bc, worst), st)
+
+
+def test_batch_chunked_equals_one_shot_and_shapes_agree(G):
+    e = WL.config5(nprob=9, nmin=30, nmax=300, k=2)
+    ref = None
+    for chunk in (None, 7):
+        s = G.batch_for(e, device=DEV)
+        U = s.cons(s.pack(e.P))
+        if chunk is None:
+            s.evolve(U)
+        else:
+            for _ in range(max(e.steps) // chunk + 1):
+                s.evolve(U, chunk)
+        out = U.cpu().numpy()
+        if ref is None:
+            ref = out
+        assert np.array_equal(out, ref)
+    # every launch shape: the tuner's trial runs leave U and the rows alone,
+    # and whichever shape it keeps gives the same result
+    s = G.batch_for(e, device=DEV)
+    U = s.cons(s.pack(e.P))
+    U0 = U.clone()
+    th, lds = s.tune(U, trial_steps=5)
+    assert torch.equal(U, U0)
+    s.evolve(U)
+    say("tuned shape", th, lds)
+    assert np.array_equal(U.cpu().numpy(), ref)
+
+
+def test_batch_full_size_sampled(G, orc):
+    """The ensemble at full size (256 problems, 200..4000 cells, each to
+    t = 0.4): the three smallest problems against the oracle, every state
+    finite, mixed against FP64 per problem."""
+    e = WL.config5()
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = G.batch_for(e, device=DEV, precision=prec)
+        U = s.cons(s.pack(e.P))
+        th, lds = s.tune(U, trial_steps=20)
+        s.evolve(U)
+        torch.cuda.synchronize()
+        say(prec, "tuned", th, lds, s.status())
+        assert bool(torch.isfinite(U).all())
+        res[prec] = [x.numpy() for x in s.unpack(U.cpu())]
+    for b in np.argsort(e.n)[:3]:
+        Ur, _ = _oracle_problem(orc, e, int(b))
+        err = orc.parity_error(res["fp64"][b], Ur)
+        say("problem", b, "n", e.n[b], "rel-L1", err[:8].max())
+        assert np.all(err[:8] <= 1e-10)
+    worst = 0.0
+    for b in range(len(e.n)):
+        err = orc.parity_error(res["mixed"][b], res["fp64"][b])
+        worst = max(worst, float(err[:8].max()))
+    say("mixed vs fp64 worst per-problem rel-L1", worst)
+    assert worst <= 1e-5

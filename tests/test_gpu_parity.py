@@ -274,7 +274,11 @@ def test_mixed_riemann_1d(G, orc, k):
     err = rel_l1(U, Ur)
     say("mixed riemann k=%d rel-L1" % k, err[:8].max(), st)
     assert np.all(err[:8] <= MIXED_BAR)
-    assert np.array_equal(U[5], Ur[5]) and np.all(U[8] == 0.0)     # Bx, Phi exact in 1D
+    # 1D: the normal field keeps zero divergence exactly (one value in every
+    # cell; the FP32 intermediate stage state rounds that value, so it stays
+    # within FP32 rounding of the initial one) and Phi stays exactly zero
+    assert np.ptp(U[5]) == 0.0 and abs(U[5].flat[0] - Ur[5].flat[0]) <= 1e-7 * abs(Ur[5].flat[0])
+    assert np.all(U[8] == 0.0)
 
 
 def test_mixed_periodic_flat_box(G, orc):

@@ -158,3 +158,25 @@ def test_recovery_derivative_with_floors(orc, AD):
         return (Px * lamP).sum() + (Uax * lamU).sum()
     fd = (f(U1 + h * d) - f(U1 - h * d)) / (2 * h)
     assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def test_primitives_of_derivative_is_inverse_everywhere(orc, AD):
+    """primitives_of(U): the recovery's value, with dP/dU = (dU/dP)^-1 in
+    every cell, floored ones included (the start-of-step reading)."""
+    w = WL.config3(n=(6, 5, 4), nsteps=1)
+    pb = orc.Problem(**w.problem_kwargs())
+    U0 = orc.prim2con(pb, w.P)
+    P0, _, flags, _ = orc.con2prim(pb, U0, w.P)
+    assert (flags != 0).any()
+    Pv = AD.primitives_of(pb, torch.from_numpy(U0), torch.from_numpy(w.P))
+    assert np.array_equal(Pv.numpy(), P0)
+    J = AD.cons_jacobian(pb, torch.from_numpy(P0))
+    for c in range(9):
+        U = torch.from_numpy(U0.copy()).requires_grad_(True)
+        AD.primitives_of(pb, U, torch.from_numpy(w.P))[c].sum().backward()
+        row = U.grad.movedim(0, -1)
+        rJ = torch.einsum("...j,...jk->...k", row, J)
+        scale = torch.einsum("...j,...jk->...k", row.abs(), J.abs())   # rounding scale per entry
+        e = torch.zeros(9, dtype=torch.float64)
+        e[c] = 1.0
+        assert torch.all((rJ - e).abs() <= 1e-12 + 1e-11 * scale)
