@@ -237,6 +237,32 @@ def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
             "finite": bool(torch.isfinite(Pq.grad).all().item())}
 
 
+def batch_throughput(grmhd, e, dev):
+    """The batched ensemble e evolved to its end in one persistent launch per
+    precision, after the launch-shape tuner: zone-updates per second per
+    Runge-Kutta substep (sum over problems of cells x steps x substeps, over
+    the wall time of the evolve call)."""
+    import torch
+    work = sum(n * s for n, s in zip(e.n, e.steps)) * e.rk_order
+    out = {"workload": e.name, "problems": len(e.n), "cells": e.ncell, "zone_substeps": work}
+    for prec in ("fp64", "mixed"):
+        s = grmhd.batch_for(e, device=dev, precision=prec)
+        P0 = s.pack(e.P)
+        U = s.cons(P0)
+        th, lds = s.tune(U, trial_steps=20)
+        U = s.cons(P0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.evolve(U)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[prec] = {"value": work / t, "seconds": round(t, 4), "threads": th, "lds_rows": lds,
+                     "recovery": s.status(), "finite": bool(torch.isfinite(U).all().item())}
+        del s, U
+    out["mixed"]["speedup_vs_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)
+    return out
+
+
 def cpu_baseline(w, pb_kwargs):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -262,6 +288,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--accuracy-steps", type=int, default=200,
                     help="RK steps of the FP64-vs-mixed accuracy comparison")
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both",
@@ -382,6 +409,9 @@ def main(argv=None) -> int:
     if not args.no_adjoint and fp64:
         # the adjoint workload (64^3 periodic box, 50 RK2 steps, checkpoints every 10)
         out["adjoint"] = adjoint_cost(grmhd, workloads.config4(n=64, nsteps=50), dev, 50, 10)
+    if not args.no_batch and fp64:
+        # 256 magnetised 1D Riemann problems of 200..4000 cells, each to t = 0.4
+        out["batch"] = batch_throughput(grmhd, workloads.config5(), dev)
     finite = all(r["finite"] for r in (fp64, mixed) if r)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, w.problem_kwargs())

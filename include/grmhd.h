@@ -262,6 +262,11 @@ int grmhd_batch_prim(grmhd_batch *b, const double *U, double *P);
  * *shape (threads) and *lds when not NULL.  Synchronises. */
 int grmhd_batch_tune(grmhd_batch *b, const double *U, int trial_steps, int *threads, int *lds);
 
+/* Choose the launch shape of grmhd_batch_evolve by hand: threads per
+ * workgroup (256, 512 or 1024) and whether the primitive rows live in LDS
+ * (refused with GRMHD_ERR_ARG when the largest row does not fit in 160 KiB). */
+int grmhd_batch_set_shape(grmhd_batch *b, int threads, int lds);
+
 /* As grmhd_status, for the batch. */
 int grmhd_batch_status(grmhd_batch *b, grmhd_stats *st, int reset);
 

@@ -166,11 +166,17 @@ def source(G, s, kappa):
 # Reconstruction and interface fluxes.
 
 def minmod3(a, b, c):
+    """The argument of least magnitude when all three share a sign, else 0.
+    At exact ties of magnitude the derivative follows one argument, in the
+    order a, c, b (a kink has no derivative; this is the convention taken)."""
     pos = (a > 0) & (b > 0) & (c > 0)
     neg = (a < 0) & (b < 0) & (c < 0)
     zero = torch.zeros_like(a)
-    return torch.where(pos, torch.minimum(a, torch.minimum(b, c)),
-                       torch.where(neg, torch.maximum(a, torch.maximum(b, c)), zero))
+    ma, mb, mc = a.abs(), b.abs(), c.abs()
+    take_a = (ma <= mc) & (ma <= mb)
+    take_c = ~take_a & (mc <= mb)
+    least = torch.where(take_a, a, torch.where(take_c, c, b))
+    return torch.where(pos | neg, least, zero)
 
 
 def mc_slope(qm, q0, qp):
@@ -192,8 +198,10 @@ def face_flux(G, gamma, c_h, d, qL, qR):
     lmL, lpL = speeds(G, sL, gamma, d)
     lmR, lpR = speeds(G, sR, gamma, d)
     zero = torch.zeros_like(lmL)
-    sl = torch.minimum(zero, torch.minimum(lmL, lmR))[..., None]
-    sr = torch.maximum(zero, torch.maximum(lpL, lpR))[..., None]
+    # extreme speeds; at an exact tie (identical states) the derivative goes
+    # through the left state's speed, the convention of a kink taken here
+    sl = torch.minimum(zero, torch.where(lmL <= lmR, lmL, lmR))[..., None]
+    sr = torch.maximum(zero, torch.where(lpL >= lpR, lpL, lpR))[..., None]
     hll = (sr * FL - sl * FR + sl * sr * (UR - UL)) / torch.where(sr - sl == 0, 1.0, sr - sl)
     F = torch.where(sl == 0, FL, torch.where(sr == 0, FR, hll))
     F = torch.where(col, phis[..., None], F)

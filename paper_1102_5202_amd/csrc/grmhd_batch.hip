@@ -357,6 +357,21 @@ int grmhd_batch_tune(grmhd_batch* b, const double* U, int trial_steps, int* thre
     return rc;
 }
 
+int grmhd_batch_set_shape(grmhd_batch* b, int threads, int lds)
+{
+    if (!b)
+        return GRMHD_ERR_ARG;
+    int shape = -1;
+    for (int s = 0; s < grmhd::BATCH_SHAPES; ++s)
+        if (grmhd::BATCH_THREADS[s] == threads)
+            shape = s;
+    if (shape < 0 || (lds && b->lds_bytes > LDS_LIMIT))
+        return GRMHD_ERR_ARG;
+    b->shape = shape;
+    b->lds = lds ? 1 : 0;
+    return GRMHD_OK;
+}
+
 int grmhd_batch_status(grmhd_batch* b, grmhd_stats* st, int reset)
 {
     if (!b || !st)

@@ -29,7 +29,7 @@ SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_con
            "grmhd_prim_adjoint", "grmhd_status", "grmhd_timing", "grmhd_free", "grmhd_strerror",
            "grmhd_batch_workspace_bytes", "grmhd_batch_init", "grmhd_batch_set_stream",
            "grmhd_batch_cons", "grmhd_batch_evolve", "grmhd_batch_prim", "grmhd_batch_tune",
-           "grmhd_batch_status", "grmhd_batch_free")
+           "grmhd_batch_set_shape", "grmhd_batch_status", "grmhd_batch_free")
 
 
 class Metric(C.Structure):
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     L.grmhd_batch_evolve.argtypes = [vp, vp, C.c_int]
     L.grmhd_batch_prim.argtypes = [vp, vp, vp]
     L.grmhd_batch_tune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.grmhd_batch_set_shape.argtypes = [vp, C.c_int, C.c_int]
     L.grmhd_batch_status.argtypes = [vp, C.POINTER(Stats), C.c_int]
     L.grmhd_batch_free.argtypes = [vp]
     L.grmhd_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
@@ -350,6 +351,11 @@ class BatchSolver:
         _check(load().grmhd_batch_tune(self._ctx, C.c_void_p(self._t(U, "U")), int(trial_steps),
                                        C.byref(th), C.byref(lds)), "grmhd_batch_tune")
         return th.value, bool(lds.value)
+
+    def set_shape(self, threads: int, lds: bool) -> None:
+        """Launch shape of evolve: threads per workgroup (256, 512, 1024) and
+        primitive rows in LDS."""
+        _check(load().grmhd_batch_set_shape(self._ctx, int(threads), int(bool(lds))), "grmhd_batch_set_shape")
 
     def status(self, reset: bool = False) -> dict:
         st = Stats()

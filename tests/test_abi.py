@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 23, names
+    assert len(names) == 24, names
     assert set(names) == set(lib.SYMBOLS)
     L = lib.load()
     for n in names:
@@ -153,6 +153,8 @@ def test_batch_workspace_and_init_validation(lib):
     assert L.grmhd_batch_evolve(ctx, C.c_void_p(addr), 5) == -4      # before cons
     assert L.grmhd_batch_evolve(ctx, None, 5) == -1
     assert L.grmhd_batch_tune(ctx, C.c_void_p(addr), 5, None, None) == -4
+    assert L.grmhd_batch_set_shape(ctx, 384, 0) == -1
+    assert L.grmhd_batch_set_shape(ctx, 1024, 1) == 0
     assert L.grmhd_batch_free(ctx) == 0
     o.workspace_bytes = nb - 8
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == -2

