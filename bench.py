@@ -136,6 +136,10 @@ def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: st
     for k in list(res[workload]):             # entries of an older layout
         if k not in ("fp64", "mixed"):
             del res[workload][k]
+    cal = res.setdefault("calibration", {})
+    for k in list(cal):
+        if not isinstance(cal[k], dict):
+            del cal[k]
     res[workload][precision] = {}
     res.setdefault("calibration", {})[workload + "/" + precision] = {
         "probe_bytes": probe_bytes, "fetch_factor": ff, "write_factor": fw}
