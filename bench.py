@@ -189,56 +189,57 @@ def accuracy(grmhd, w, P0, dev, nsteps):
 
 
 def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
-    """Cost of the adjoint on workload w (FP64): the mean duration of one
-    grmhd_step_adjoint (which recomputes the stages of its step) over that of
-    one grmhd_step, and the wall time of a whole gradient (forward evolution
-    with checkpoints every `every` steps, then the checkpointed reverse sweep)
-    over that of the forward evolution alone."""
+    """Cost of the adjoint on workload w (FP64), after a warm-up of every
+    call: the mean duration of one grmhd_step_adjoint (which recomputes the
+    stages of its step: about one forward step, measured apart as
+    recompute_ms) over that of one grmhd_step, and the wall time of a whole
+    gradient (forward evolution with checkpoints every `every` steps, then the
+    checkpointed reverse sweep) over that of the forward evolution alone."""
     import torch
     from paper_1102_5202_amd.adjoint import evolve
     s = grmhd.solver_for(w, device=dev, adjoint=True)
     P0 = torch.from_numpy(w.P).to(dev)
+    tgt = (torch.from_numpy(np.ascontiguousarray(w.extra["target"])).to(dev) if "target" in w.extra
+           else P0[0] * 1.01)
+
+    def gradient():
+        Pq = P0.clone().requires_grad_(True)
+        Pn = evolve(s, Pq, w.dt, steps, every)
+        ((Pn[0] - tgt) ** 2).sum().backward()
+        return Pq.grad
+
+    def forward_evolution():
+        U = s.cons(P0)
+        for _ in range(steps):
+            s.step(U, w.dt)
+        s.prim(U)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
     U = s.cons(P0)
     for _ in range(2):
         s.step(U, w.dt)
-    torch.cuda.synchronize()
-    n = max(4, min(steps, 20))
-    t0 = time.perf_counter()
-    for _ in range(n):
-        s.step(U, w.dt)
-    torch.cuda.synchronize()
-    t_fwd = (time.perf_counter() - t0) / n
     Ub = torch.randn_like(U)
     s.step_adjoint(U, Ub, w.dt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n):
-        s.step_adjoint(U, Ub, w.dt)
-    torch.cuda.synchronize()
-    t_adj = (time.perf_counter() - t0) / n
-    # whole gradient of sum (rho - rho_t)^2 after `steps` steps
-    tgt = torch.from_numpy(w.extra["target"]).to(dev) if "target" in w.extra else P0[0] * 1.01
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    U = s.cons(P0)
-    for _ in range(steps):
-        s.step(U, w.dt)
-    s.prim(U)
-    torch.cuda.synchronize()
-    t_evo = time.perf_counter() - t0
-    Pq = P0.clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Pn = evolve(s, Pq, w.dt, steps, every)
-    ((Pn[0] - tgt) ** 2).sum().backward()
-    torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
+    g = gradient()                      # warm-up of every path
+    n = max(4, min(steps, 20))
+    t_fwd = timed(lambda: s.step(U, w.dt), n)
+    t_adj = timed(lambda: s.step_adjoint(U, Ub, w.dt), n)
+    t_evo = timed(forward_evolution, 2)
+    t_grad = timed(gradient, 2)
     return {"workload": w.name, "steps": steps, "checkpoint_every": every,
             "forward_step_ms": round(1e3 * t_fwd, 4), "adjoint_step_ms": round(1e3 * t_adj, 4),
             "adjoint_over_forward": round(t_adj / t_fwd, 3),
+            "reverse_only_over_forward": round((t_adj - t_fwd) / t_fwd, 3),
             "gradient_ms": round(1e3 * t_grad, 3), "forward_evolution_ms": round(1e3 * t_evo, 3),
             "gradient_over_forward": round(t_grad / t_evo, 3),
-            "finite": bool(torch.isfinite(Pq.grad).all().item())}
+            "finite": bool(torch.isfinite(g).all().item())}
 
 
 def batch_throughput(grmhd, e, dev):

@@ -140,8 +140,8 @@ typedef enum {
     GRMHD_K_RHS = 7,      /* flux divergence + sources only                  */
     GRMHD_K_ADJ_REC = 8,  /* adjoint: recovery + Runge-Kutta combination     */
     GRMHD_K_ADJ_FACE = 9, /* adjoint: face solver, one axis                  */
-    GRMHD_K_ADJ_GATHER = 10, /* adjoint: reconstruction, one axis           */
-    GRMHD_K_ADJ_FOLD = 11,   /* adjoint: ghost fold + sources               */
+    GRMHD_K_ADJ_GATHER = 10, /* adjoint: reconstruction of all axes + ghost fold */
+    GRMHD_K_ADJ_CELL = 11,   /* adjoint: sources + the next recovery + RK adjoint */
     GRMHD_K_COUNT = 12
 } grmhd_kernel;
 

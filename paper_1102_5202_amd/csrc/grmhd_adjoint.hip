@@ -4,20 +4,23 @@
 // Forward stage s:  U~^(s+1) = U^s + a_s (U^n - U^s) + b_s dt R(P^s),
 //                   (P^(s+1), U^(s+1)) = recovery of U~^(s+1) with floors
 //                   (a floored cell's conserved matter part is rebuilt).
-// Reverse, given the cotangents (Ub, Pb) of (U^(s+1), P^(s+1)):
-//   k_adj_rec      recovery adjoint (dU/dP)^-T at P^(s+1) (implicit function
-//                  theorem), floors as constants, the rebuild differentiated;
-//                  then the RK combination: Ub^s = (1 - a_s) Ub~, Ub^n += a_s Ub~,
-//                  Rb = b_s dt Ub~;
+// Reverse, given the cotangents (Ub, Pb) of (U^(s+1), P^(s+1)), the recovery
+// adjoint ((dU/dP)^-T at P^(s+1) by the implicit function theorem, floors as
+// constants, the rebuild differentiated) and the RK combination
+// (Ub^s = (1 - a_s) Ub~, Ub^n += a_s Ub~, Rb = b_s dt Ub~), then the
+// right-hand side's adjoint at P^s:
+//   k_adj_rec      the recovery + RK adjoint of the last stage (Pb = 0);
 //   k_adj_face<D>  per face along D: the flux cotangent (Rb_right - Rb_left)/dx
 //                  pulled back through HLLE, the cleaning pair and the face
 //                  physics to the reconstructed left/right states;
-//   k_adj_gather<D> per cell (ghosts included): the reconstructed-state
-//                  cotangents pulled back through the MC reconstruction;
-//   k_adj_fold     ghost cotangents added to the cells they copy, plus the
-//                  source-term cotangent: Pb^s.
-// At the step's start P^0 is the primitives of U^n; k_adj_final adds
-// (dU/dP)^-T Pb^0 and the accumulated Ub^n.
+//   k_adj_gather<D> per position along D (ghosts included): those pulled back
+//                  through the MC reconstruction, accumulated over the axes;
+//   k_adj_cell     per cell: plus the cotangents of the ghosts that copy the
+//                  cell (the adjoint of the ghost fill) and the sources, =
+//                  Pb^s; then the recovery + RK adjoint of the stage below,
+//                  or, at the step's start (P^0 the primitives of U^n),
+//                  Ub^n += Unacc + (dU/dP)^-T Pb^0.
+// k_adj_final and k_adj_cons serve grmhd_prim_adjoint and grmhd_cons_adjoint.
 #include "grmhd_adjoint.h"
 #include "grmhd_internal.h"
 
@@ -198,33 +201,20 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_face(const double* __restrict__ 
     }
 }
 
-// One thread per cell along D over -2 .. n+1 (the ghosts of axis D
-// included), interior along the other axes.  Writes the cotangent of the
-// cell's primitives from the faces along D into MU (ghosted layout):
-// assigned at ghost positions and, for the first active axis, at interior
-// ones; added at interior positions otherwise.
+// Cotangent of the primitives at position ci (ci[D] in -2 .. n+1, ghosts of
+// axis D included; interior along the other axes) from the faces along D,
+// added to mu: the left/right reconstructed-state cotangents FB (18 rows of
+// nf values) pulled back through the MC reconstruction.  Face f sits between
+// cells f-1 and f; the slope of cell j feeds the left state at face j+1 and
+// the right state at face j.
 template <int D>
-__global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict__ Pc,
-                                                        const double* __restrict__ FB,
-                                                        double* __restrict__ MU, Dev d, int first)
+__device__ __forceinline__ void gather_pos(const Dev& d, const double* __restrict__ Pc,
+                                           const double* __restrict__ FB, const int* ci, double* mu)
 {
-    int m[3] = {d.n[0], d.n[1], d.n[2]};
-    m[D] += 4;
-    const long long total = (long long)m[0] * m[1] * m[2];
-    const long long t0 = (long long)blockIdx.x * ABLOCK + threadIdx.x;
-    if (t0 >= total)
-        return;
-    int ci[3];
-    ci[0] = (int)(t0 % m[0]);
-    const long long t = t0 / m[0];
-    ci[1] = (int)(t % m[1]);
-    ci[2] = (int)(t / m[1]);
-    ci[D] -= 2;
     const int i = ci[D], n = d.n[D];
     const long long nf = d.nf[D];
     int fm[3] = {d.n[0], d.n[1], d.n[2]};
     fm[D] += 1;
-    // face index of the face at position ff along D (same other coordinates)
     auto face = [&](int ff) -> long long {
         int fi[3] = {ci[0], ci[1], ci[2]};
         fi[D] = ff;
@@ -241,21 +231,19 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
     for (int v = 0; v < 9; ++v) {
         const double* Fl = FB + v * nf;          // left-state cotangents
         const double* Fr = FB + (9 + v) * nf;    // right-state cotangents
-        double mu = 0.0;
+        double m = 0.0;
         if (has_hi)
-            mu += Fl[f_hi];
+            m += Fl[f_hi];
         if (has_lo)
-            mu += Fr[f_lo];
-        // slope of cell j feeds the left state at face j+1 and the right state
-        // at face j: sigma_b(j) = (Lb(face j+1) - Rb(face j)) / 2, j in [-1, n]
+            m += Fr[f_lo];
         const double* P = Pc + v * d.sv + pc;
-        // j = i - 1 (q_i is its qp)
+        // j = i - 1 (q_i is its qp), j in [-1, n]
         if (i - 1 >= -1 && i - 1 <= n) {
             const double sb = 0.5 * ((has_lo ? Fl[f_lo] : 0.0) - (f_lm >= 0 ? Fr[f_lm] : 0.0));
             if (sb != 0.0) {
                 double dm, d0, dp;
                 mc_slope_grad(P[-2 * st], P[-st], P[0], dm, d0, dp);
-                mu += sb * dp;
+                m += sb * dp;
             }
         }
         // j = i
@@ -264,7 +252,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
             if (sb != 0.0) {
                 double dm, d0, dp;
                 mc_slope_grad(P[-st], P[0], P[st], dm, d0, dp);
-                mu += sb * d0;
+                m += sb * d0;
             }
         }
         // j = i + 1 (q_i is its qm)
@@ -273,14 +261,10 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
             if (sb != 0.0) {
                 double dm, d0, dp;
                 mc_slope_grad(P[0], P[st], P[2 * st], dm, d0, dp);
-                mu += sb * dm;
+                m += sb * dm;
             }
         }
-        double* out = MU + v * d.sv + pc;
-        if (first || i < 0 || i >= n)
-            *out = mu;
-        else
-            *out += mu;
+        mu[v] += m;
     }
 }
 
@@ -318,64 +302,6 @@ __device__ __forceinline__ void sources_rev(const Dev& d, double x, double y, do
     kinematics_rev(q, k, g, d.gfac, kb, qb);
 }
 
-// Per interior cell: Pb = MU + the MU of the ghosts that copy this cell +
-// the source cotangent.
-template <int KIND>
-__global__ __launch_bounds__(ABLOCK) void k_adj_fold(const double* __restrict__ Pc,
-                                                      const double* __restrict__ MU,
-                                                      const double* __restrict__ Rb,
-                                                      double* __restrict__ Pb, Dev d)
-{
-    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
-    if (c >= d.N)
-        return;
-    const int i = (int)(c % d.n[0]);
-    const long long t = c / d.n[0];
-    const int j = (int)(t % d.n[1]);
-    const int k = (int)(t / d.n[1]);
-    const long long pc = ghosted(d, i, j, k);
-    double pb[9], q[9], rb[9];
-    const bool any = d.act[0] || d.act[1] || d.act[2];
-#pragma unroll
-    for (int v = 0; v < 9; ++v) {
-        pb[v] = any ? MU[v * d.sv + pc] : 0.0;
-        q[v] = Pc[v * d.sv + pc];
-        rb[v] = Rb[v * d.N + c];
-    }
-    const int idx[3] = {i, j, k};
-    const long long stride[3] = {1, d.px, (long long)d.px * d.py};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (!d.act[a])
-            continue;
-        const int n = d.n[a];
-        const long long s = stride[a];
-        long long o[2];
-        int no = 0;
-        if (d.bc[a] == 0) {
-            if (idx[a] < 2)
-                o[no++] = n * s;
-            if (idx[a] >= n - 2)
-                o[no++] = -n * s;
-        } else if (idx[a] == 0) {
-            o[no++] = -s;
-            o[no++] = -2 * s;
-        } else if (idx[a] == n - 1) {
-            o[no++] = s;
-            o[no++] = 2 * s;
-        }
-        for (int e = 0; e < no; ++e)
-#pragma unroll
-            for (int v = 0; v < 9; ++v)
-                pb[v] += MU[v * d.sv + pc + o[e]];
-    }
-    const double3 x = centre(d, i, j, k);
-    sources_rev<KIND>(d, x.x, x.y, x.z, q, rb, pb);
-#pragma unroll
-    for (int v = 0; v < 9; ++v)
-        Pb[v * d.N + c] = pb[v];
-}
-
 // x = (dU/dP)^-T y at the primitives q of a cell at (x, y, z); false if the
 // matter block is singular.
 template <int KIND>
@@ -388,33 +314,13 @@ __device__ __forceinline__ bool recovery_adjoint(const Dev& d, const double3& x,
     return cons_jacobian_solve_t(J, g.sqrtmg, y, out);
 }
 
-// Recovery + RK-combination adjoint of stage s (see the file header).  Ub is
-// updated in place to the cotangent of U^s; Pb (may be null: zero) is the
-// cotangent of P^(s+1); flags are the stage's recovery flags.
+// Recovery adjoint of one cell: from the cotangents ub of the recovered
+// (and, where a floor fired, rebuilt) conserved state and pb of the
+// primitives q = P^(s+1), the cotangent ut of the state before the recovery.
 template <int KIND>
-__global__ __launch_bounds__(ABLOCK) void k_adj_rec(double* __restrict__ Ub, const double* __restrict__ Pb,
-                                                     const double* __restrict__ Pn,
-                                                     const unsigned char* __restrict__ flags,
-                                                     double* __restrict__ Unacc, double* __restrict__ Rb,
-                                                     Dev d, double a, double b, double dt, int first)
+__device__ __forceinline__ void rec_adjoint(const Dev& d, const double3& x, const double* q, int fl,
+                                            const double* ub, const double* pb, double* ut)
 {
-    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
-    if (c >= d.N)
-        return;
-    const int i = (int)(c % d.n[0]);
-    const long long t = c / d.n[0];
-    const int j = (int)(t % d.n[1]);
-    const int k = (int)(t / d.n[1]);
-    const long long pc = ghosted(d, i, j, k);
-    double q[9], ub[9], pb[9], ut[9];
-#pragma unroll
-    for (int v = 0; v < 9; ++v) {
-        q[v] = Pn[v * d.sv + pc];
-        ub[v] = Ub[v * d.N + c];
-        pb[v] = Pb ? Pb[v * d.N + c] : 0.0;
-    }
-    const int fl = flags[c];
-    const double3 x = centre(d, i, j, k);
     double J[5][8];
     GeoT<double> g;
     if (fl & FLAG_ATM) {
@@ -477,11 +383,163 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_rec(double* __restrict__ Ub, con
         for (int v = 0; v < 9; ++v)
             ut[v] += ub[v];
     }
+}
+
+// The last stage's recovery + RK-combination adjoint (the step's output
+// cotangent Ub, no primitive cotangent): Ub <- (1 - a) Ub~, Unacc = a Ub~,
+// Rb = b dt Ub~ with Ub~ the cotangent before the recovery.
+template <int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_rec(double* __restrict__ Ub, const double* __restrict__ Pn,
+                                                     const unsigned char* __restrict__ flags,
+                                                     double* __restrict__ Unacc, double* __restrict__ Rb,
+                                                     Dev d, double a, double b, double dt)
+{
+    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (c >= d.N)
+        return;
+    const int i = (int)(c % d.n[0]);
+    const long long t = c / d.n[0];
+    const int j = (int)(t % d.n[1]);
+    const int k = (int)(t / d.n[1]);
+    const long long pc = ghosted(d, i, j, k);
+    double q[9], ub[9], ut[9];
+    const double pb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        q[v] = Pn[v * d.sv + pc];
+        ub[v] = Ub[v * d.N + c];
+    }
+    rec_adjoint<KIND>(d, centre(d, i, j, k), q, flags[c], ub, pb, ut);
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
         Ub[v * d.N + c] = (1.0 - a) * ut[v];
-        Unacc[v * d.N + c] = (first ? 0.0 : Unacc[v * d.N + c]) + a * ut[v];
+        Unacc[v * d.N + c] = a * ut[v];
         Rb[v * d.N + c] = b * dt * ut[v];
+    }
+}
+
+// One thread per position along D over -2 .. n+1 (the ghosts of axis D
+// included), interior along the other axes: the cotangent of the primitives
+// there from the faces along D, into MU (ghosted layout).  Assigned at ghost
+// positions and, for the first active axis, at interior ones; added at
+// interior positions otherwise.  Light on registers: these kernels wait on
+// scattered loads and want occupancy.
+template <int D>
+__global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict__ Pc,
+                                                        const double* __restrict__ FB,
+                                                        double* __restrict__ MU, Dev d, int first)
+{
+    int m[3] = {d.n[0], d.n[1], d.n[2]};
+    m[D] += 4;
+    const long long total = (long long)m[0] * m[1] * m[2];
+    const long long t0 = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (t0 >= total)
+        return;
+    int ci[3];
+    ci[0] = (int)(t0 % m[0]);
+    const long long t = t0 / m[0];
+    ci[1] = (int)(t % m[1]);
+    ci[2] = (int)(t / m[1]);
+    ci[D] -= 2;
+    double mu[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        mu[v] = 0.0;
+    gather_pos<D>(d, Pc, FB, ci, mu);
+    const long long pc = ghosted(d, ci[0], ci[1], ci[2]);
+    const int i = ci[D];
+    const bool assign = first || i < 0 || i >= d.n[D];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        double* out = MU + v * d.sv + pc;
+        *out = assign ? mu[v] : *out + mu[v];
+    }
+}
+
+// Per interior cell, after the gathers of stage s: Pb^s = MU at the cell +
+// MU at the ghost positions that copy it (the adjoint of the ghost fill:
+// periodic images, or the zero-gradient copies beside the first and last
+// cells) + the sources' cotangent at P^s; then, for s > 0, the recovery + RK
+// adjoint of stage s-1 (whose output is U^s, P^s; flags of that recovery in
+// fprev, coefficients a, b): Ub <- (1 - a) Ub~, Unacc += a Ub~,
+// Rb = b dt Ub~; for s = 0 (fprev null) the step's input cotangent
+// Ub <- Ub + Unacc + (dU/dP)^-T Pb^0.
+template <int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_cell(const double* __restrict__ Pc,
+                                                      const double* __restrict__ MU,
+                                                      double* __restrict__ Rb, double* __restrict__ Ub,
+                                                      double* __restrict__ Unacc,
+                                                      const unsigned char* __restrict__ fprev, Dev d, double a,
+                                                      double b, double dt)
+{
+    const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (c >= d.N)
+        return;
+    const int i = (int)(c % d.n[0]);
+    const long long t = c / d.n[0];
+    const int j = (int)(t % d.n[1]);
+    const int k = (int)(t / d.n[1]);
+    const long long pc = ghosted(d, i, j, k);
+    const bool any = d.act[0] || d.act[1] || d.act[2];
+    double pb[9], q[9], rb[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        pb[v] = any ? MU[v * d.sv + pc] : 0.0;
+        q[v] = Pc[v * d.sv + pc];
+        rb[v] = Rb[v * d.N + c];
+    }
+    const int idx[3] = {i, j, k};
+    const long long stride[3] = {1, d.px, (long long)d.px * d.py};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!d.act[ax])
+            continue;
+        const int n = d.n[ax];
+        const long long st = stride[ax];
+        long long o[2];
+        int no = 0;
+        if (d.bc[ax] == 0) {
+            if (idx[ax] < 2)
+                o[no++] = n * st;
+            if (idx[ax] >= n - 2)
+                o[no++] = -n * st;
+        } else if (idx[ax] == 0) {
+            o[no++] = -st;
+            o[no++] = -2 * st;
+        } else if (idx[ax] == n - 1) {
+            o[no++] = st;
+            o[no++] = 2 * st;
+        }
+        for (int e = 0; e < no; ++e)
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                pb[v] += MU[v * d.sv + pc + o[e]];
+    }
+    const double3 x = centre(d, i, j, k);
+    sources_rev<KIND>(d, x.x, x.y, x.z, q, rb, pb);
+    double ub[9], ut[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        ub[v] = Ub[v * d.N + c];
+    if (fprev) {
+        rec_adjoint<KIND>(d, x, q, fprev[c], ub, pb, ut);
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            Ub[v * d.N + c] = (1.0 - a) * ut[v];
+            Unacc[v * d.N + c] += a * ut[v];
+            Rb[v * d.N + c] = b * dt * ut[v];
+        }
+    } else {
+        double J[5][8];
+        GeoT<double> g;
+        if (!recovery_adjoint<KIND>(d, x, q, pb, ut, J, g)) {
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                ut[v] = __builtin_nan("");
+        }
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            Ub[v * d.N + c] = ub[v] + Unacc[v * d.N + c] + ut[v];
     }
 }
 
@@ -561,16 +619,42 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_cons(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Launchers
 
-hipError_t launch_adj_rec(int kind, double* Ub, const double* Pb, const double* Pn, const unsigned char* flags,
-                          double* Unacc, double* Rb, const Dev& d, double a, double b, double dt, int first,
-                          hipStream_t s)
+hipError_t launch_adj_rec(int kind, double* Ub, const double* Pn, const unsigned char* flags, double* Unacc,
+                          double* Rb, const Dev& d, double a, double b, double dt, hipStream_t s)
 {
     if (kind == FLAT)
-        hipLaunchKernelGGL((k_adj_rec<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pb, Pn, flags, Unacc,
-                           Rb, d, a, b, dt, first);
+        hipLaunchKernelGGL((k_adj_rec<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pn, flags, Unacc, Rb, d,
+                           a, b, dt);
     else
-        hipLaunchKernelGGL((k_adj_rec<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pb, Pn, flags, Unacc,
-                           Rb, d, a, b, dt, first);
+        hipLaunchKernelGGL((k_adj_rec<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Ub, Pn, flags, Unacc, Rb, d,
+                           a, b, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_gather(int dir, const double* Pc, const double* FB, double* MU, const Dev& d, int first,
+                             hipStream_t s)
+{
+    long long m[3] = {d.n[0], d.n[1], d.n[2]};
+    m[dir] += 4;
+    const unsigned nb = ablocks(m[0] * m[1] * m[2]);
+    if (dir == 0)
+        hipLaunchKernelGGL((k_adj_gather<0>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
+    else if (dir == 1)
+        hipLaunchKernelGGL((k_adj_gather<1>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
+    else
+        hipLaunchKernelGGL((k_adj_gather<2>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_cell(int kind, const double* Pc, const double* MU, double* Rb, double* Ub, double* Unacc,
+                           const unsigned char* fprev, const Dev& d, double a, double b, double dt, hipStream_t s)
+{
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_adj_cell<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Ub, Unacc, fprev,
+                           d, a, b, dt);
+    else
+        hipLaunchKernelGGL((k_adj_cell<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Ub, Unacc, fprev,
+                           d, a, b, dt);
     return hipGetLastError();
 }
 
@@ -592,31 +676,6 @@ hipError_t launch_adj_face(int kind, int dir, const double* Pc, const double* Rb
                            hipStream_t s)
 {
     return kind == FLAT ? adj_face_k<FLAT>(dir, Pc, Rb, FB, d, s) : adj_face_k<ISO>(dir, Pc, Rb, FB, d, s);
-}
-
-hipError_t launch_adj_gather(int dir, const double* Pc, const double* FB, double* MU, const Dev& d, int first,
-                             hipStream_t s)
-{
-    long long m[3] = {d.n[0], d.n[1], d.n[2]};
-    m[dir] += 4;
-    const unsigned nb = ablocks(m[0] * m[1] * m[2]);
-    if (dir == 0)
-        hipLaunchKernelGGL((k_adj_gather<0>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
-    else if (dir == 1)
-        hipLaunchKernelGGL((k_adj_gather<1>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
-    else
-        hipLaunchKernelGGL((k_adj_gather<2>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_fold(int kind, const double* Pc, const double* MU, const double* Rb, double* Pb,
-                           const Dev& d, hipStream_t s)
-{
-    if (kind == FLAT)
-        hipLaunchKernelGGL((k_adj_fold<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Pb, d);
-    else
-        hipLaunchKernelGGL((k_adj_fold<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Pb, d);
-    return hipGetLastError();
 }
 
 hipError_t launch_adj_final(int kind, const double* Ub, const double* Pb, const double* P0, const double* Unacc,

@@ -28,8 +28,8 @@ struct Layout {
     size_t off_cnt, off_pc[3], off_us, off_f[3];
     // adjoint part (FP64): stage primitive caches P^0..P^ns, the stages'
     // recovery flags, the recomputed stage state, the U^n cotangent
-    // accumulator, the R and P cotangents, the ghosted reconstruction
-    // cotangent and the face-state cotangents of one axis
+    // accumulator, the R cotangent, a dense primitive scratch, the ghosted
+    // cotangent of the primitives and the face-state cotangents of one axis
     bool adj;
     size_t off_ac[4], off_aflags, off_aus, off_unacc, off_rb, off_pb, off_mu, off_fb;
     size_t total;
@@ -89,9 +89,6 @@ Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int 
     L.adj = adjoint;
     if (adjoint) {
         const size_t cache = sizeof(double) * 9 * (size_t)L.sv, dense = sizeof(double) * 9 * (size_t)L.N;
-        long long nfmax = 0;
-        for (int d = 0; d < 3; ++d)
-            nfmax = L.nf[d] > nfmax ? L.nf[d] : nfmax;
         for (int b = 0; b < 4; ++b) {
             L.off_ac[b] = off;
             if (b <= ns)
@@ -104,6 +101,9 @@ Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int 
             *o = off;
             off = round_up(off + dense, 256);
         }
+        long long nfmax = 0;
+        for (int d = 0; d < 3; ++d)
+            nfmax = L.nf[d] > nfmax ? L.nf[d] : nfmax;
         L.off_mu = off;
         off = round_up(off + cache, 256);
         L.off_fb = off;
@@ -426,15 +426,14 @@ int step_adjoint(grmhd_ctx* c, const double* U, double* Ubar, double dt)
     int rc = adj_recompute(c, U, dt, A, B);
     if (rc)
         return rc;
+    // the last stage's recovery + RK adjoint (its output is the step's)
+    rc = timed(c, GRMHD_K_ADJ_REC, [&] {
+        return grmhd::launch_adj_rec(c->kind, Ubar, c->Ac[ns], c->Aflags + (size_t)(ns - 1) * c->L.N, c->Unacc,
+                                     c->Rb, c->d, A[ns - 1], B[ns - 1], dt, c->stream);
+    });
+    if (rc)
+        return rc;
     for (int s = ns - 1; s >= 0; --s) {
-        const double* Pn = c->Ac[s + 1];
-        const unsigned char* fl = c->Aflags + (size_t)s * c->L.N;
-        rc = timed(c, GRMHD_K_ADJ_REC, [&] {
-            return grmhd::launch_adj_rec(c->kind, Ubar, s == ns - 1 ? nullptr : c->Pb, Pn, fl, c->Unacc, c->Rb,
-                                         c->d, A[s], B[s], dt, s == ns - 1, c->stream);
-        });
-        if (rc)
-            return rc;
         const double* Ps = c->Ac[s];
         int first = 1;
         for (int dir = 0; dir < 3; ++dir) {
@@ -452,15 +451,17 @@ int step_adjoint(grmhd_ctx* c, const double* U, double* Ubar, double dt)
                 return rc;
             first = 0;
         }
-        rc = timed(c, GRMHD_K_ADJ_FOLD, [&] {
-            return grmhd::launch_adj_fold(c->kind, Ps, c->MU, c->Rb, c->Pb, c->d, c->stream);
+        // Pb^s, then the recovery + RK adjoint of stage s-1 (or the step's start)
+        const unsigned char* fprev = s > 0 ? c->Aflags + (size_t)(s - 1) * c->L.N : nullptr;
+        const double a = s > 0 ? A[s - 1] : 0.0, b = s > 0 ? B[s - 1] : 0.0;
+        rc = timed(c, GRMHD_K_ADJ_CELL, [&] {
+            return grmhd::launch_adj_cell(c->kind, Ps, c->MU, c->Rb, Ubar, c->Unacc, fprev, c->d, a, b, dt,
+                                          c->stream);
         });
         if (rc)
             return rc;
     }
-    return timed(c, GRMHD_K_ADJ_REC, [&] {
-        return grmhd::launch_adj_final(c->kind, Ubar, c->Pb, c->Ac[0], c->Unacc, Ubar, c->d, c->stream);
-    });
+    return GRMHD_OK;
 }
 
 }  // namespace

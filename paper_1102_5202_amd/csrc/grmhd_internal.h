@@ -77,16 +77,17 @@ hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* 
                                double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps,
                                unsigned long long* cnt, hipStream_t s);
 
-// Adjoint kernels (FP64; grmhd_adjoint.hip).
-hipError_t launch_adj_rec(int kind, double* Ub, const double* Pb, const double* Pn, const unsigned char* flags,
-                          double* Unacc, double* Rb, const Dev& d, double a, double b, double dt, int first,
-                          hipStream_t s);
+// Adjoint kernels (FP64; grmhd_adjoint.hip).  FB: the face-state cotangents
+// of one axis (18 rows of nf[d] values); MU: a ghosted cotangent of the
+// primitives.
+hipError_t launch_adj_rec(int kind, double* Ub, const double* Pn, const unsigned char* flags, double* Unacc,
+                          double* Rb, const Dev& d, double a, double b, double dt, hipStream_t s);
 hipError_t launch_adj_face(int kind, int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
                            hipStream_t s);
 hipError_t launch_adj_gather(int dir, const double* Pc, const double* FB, double* MU, const Dev& d, int first,
                              hipStream_t s);
-hipError_t launch_adj_fold(int kind, const double* Pc, const double* MU, const double* Rb, double* Pb,
-                           const Dev& d, hipStream_t s);
+hipError_t launch_adj_cell(int kind, const double* Pc, const double* MU, double* Rb, double* Ub, double* Unacc,
+                           const unsigned char* fprev, const Dev& d, double a, double b, double dt, hipStream_t s);
 hipError_t launch_adj_final(int kind, const double* Ub, const double* Pb, const double* P0, const double* Unacc,
                             double* Ubar, const Dev& d, hipStream_t s);
 hipError_t launch_adj_cons(int kind, const double* P, const double* Ubar, double* Pbar, const Dev& d,

@@ -20,7 +20,7 @@ PERIODIC, OUTFLOW = 0, 1
 FP64, MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 KERNELS = ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs", "adj_rec",
-           "adj_face", "adj_gather", "adj_fold")
+           "adj_face", "adj_gather", "adj_cell")
 NVAR = 9
 
 # exported symbols of include/grmhd.h

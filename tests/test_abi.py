@@ -98,8 +98,8 @@ def test_workspace_and_init_validation(lib):
 
 def test_adjoint_workspace(lib):
     """The adjoint part of the workspace: FP64 only, ns+1 ghosted stage caches,
-    stage flags, four dense arrays, a ghosted cotangent and one axis' 18
-    face-state cotangents on top of the forward workspace."""
+    stage flags, four dense arrays, a ghosted cotangent and the 18 face-state
+    cotangents of one axis on top of the forward workspace."""
     L = lib.load()
     n = (16, 8, 6)
     g = lib.make_grid(n, (0, 0, 0), (1, 1, 1), (0, 1, 1))
