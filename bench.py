@@ -190,21 +190,25 @@ def accuracy(grmhd, w, P0, dev, nsteps):
 
 def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
     """Cost of the adjoint on workload w (FP64), after a warm-up of every
-    call: the mean duration of one grmhd_step_adjoint (which recomputes the
-    stages of its step: about one forward step, measured apart as
-    recompute_ms) over that of one grmhd_step, and the wall time of a whole
-    gradient (forward evolution with checkpoints every `every` steps, then the
-    checkpointed reverse sweep) over that of the forward evolution alone."""
+    call, as mean durations over that of one grmhd_step:
+    grmhd_step_adjoint, which recomputes its step's stages first (about one
+    forward step); grmhd_step_record, a forward step that keeps its stages;
+    and grmhd_step_adjoint_recorded, the reverse sweep of a recorded step.
+    Also the wall time of a whole gradient (forward evolution with checkpoints
+    every `every` steps, then the checkpointed reverse sweep, with the tape of
+    recorded steps and without it) over that of the forward evolution alone."""
+    import numpy as np
     import torch
     from paper_1102_5202_amd.adjoint import evolve
     s = grmhd.solver_for(w, device=dev, adjoint=True)
+    st = grmhd.solver_for(w, device=dev, adjoint=True, tape_steps=every)
     P0 = torch.from_numpy(w.P).to(dev)
     tgt = (torch.from_numpy(np.ascontiguousarray(w.extra["target"])).to(dev) if "target" in w.extra
            else P0[0] * 1.01)
 
-    def gradient():
+    def gradient(solver):
         Pq = P0.clone().requires_grad_(True)
-        Pn = evolve(s, Pq, w.dt, steps, every)
+        Pn = evolve(solver, Pq, w.dt, steps, every)
         ((Pn[0] - tgt) ** 2).sum().backward()
         return Pq.grad
 
@@ -227,19 +231,29 @@ def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
         s.step(U, w.dt)
     Ub = torch.randn_like(U)
     s.step_adjoint(U, Ub, w.dt)
-    g = gradient()                      # warm-up of every path
+    Ur = st.cons(P0)
+    st.step_record(Ur, w.dt, 0)
+    st.step_adjoint_recorded(0, Ub)
+    g = gradient(s)                     # warm-up of every path
+    gt = gradient(st)
     n = max(4, min(steps, 20))
     t_fwd = timed(lambda: s.step(U, w.dt), n)
     t_adj = timed(lambda: s.step_adjoint(U, Ub, w.dt), n)
+    t_rec = timed(lambda: st.step_record(Ur, w.dt, 0), n)
+    t_rev = timed(lambda: st.step_adjoint_recorded(0, Ub), n)
     t_evo = timed(forward_evolution, 2)
-    t_grad = timed(gradient, 2)
+    t_grad = timed(lambda: gradient(s), 2)
+    t_gradt = timed(lambda: gradient(st), 2)
     return {"workload": w.name, "steps": steps, "checkpoint_every": every,
             "forward_step_ms": round(1e3 * t_fwd, 4), "adjoint_step_ms": round(1e3 * t_adj, 4),
             "adjoint_over_forward": round(t_adj / t_fwd, 3),
-            "reverse_only_over_forward": round((t_adj - t_fwd) / t_fwd, 3),
-            "gradient_ms": round(1e3 * t_grad, 3), "forward_evolution_ms": round(1e3 * t_evo, 3),
-            "gradient_over_forward": round(t_grad / t_evo, 3),
-            "finite": bool(torch.isfinite(g).all().item())}
+            "record_step_ms": round(1e3 * t_rec, 4), "recorded_adjoint_step_ms": round(1e3 * t_rev, 4),
+            "recorded_adjoint_over_forward": round(t_rev / t_fwd, 3),
+            "gradient_ms": round(1e3 * t_gradt, 3), "gradient_untaped_ms": round(1e3 * t_grad, 3),
+            "forward_evolution_ms": round(1e3 * t_evo, 3),
+            "gradient_over_forward": round(t_gradt / t_evo, 3),
+            "gradient_untaped_over_forward": round(t_grad / t_evo, 3),
+            "finite": bool(torch.isfinite(g).all().item() and torch.isfinite(gt).all().item())}
 
 
 def batch_throughput(grmhd, e, dev):

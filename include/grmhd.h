@@ -115,6 +115,7 @@ typedef struct {
     int newton_maxit;      /* iteration cap of the recovery (50 if 0) */
     int timing;            /* nonzero: time every kernel launch with HIP events */
     int adjoint;           /* nonzero: reserve the workspace of the adjoint calls (FP64 only) */
+    int tape_steps;        /* with adjoint: slots of recorded steps (grmhd_step_record), 0..4096 */
     void *workspace;       /* device memory, >= grmhd_workspace_bytes(), 256-byte aligned */
     size_t workspace_bytes;
 } grmhd_opts;
@@ -206,6 +207,25 @@ int grmhd_rhs(grmhd_ctx *ctx, const double *P, double *R);
  * stages recomputed and reversed).  Ubar (device) is read and overwritten.
  * Recovery events of the recomputation are counted as in grmhd_step(). */
 int grmhd_step_adjoint(grmhd_ctx *ctx, const double *U, double *Ubar, double dt);
+
+/* A forward step exactly as grmhd_step (the same kernels on the same inputs:
+ * U and the context's primitives come out bitwise the same) that also keeps,
+ * in tape slot `slot` (0 <= slot < opts.tape_steps), what the reverse sweep
+ * of this step needs: the primitives of the step's start and of every
+ * stage's recovery, and the stages' floor flags.  A checkpointed reverse
+ * sweep recomputes each segment once with these calls and then reverses the
+ * recorded steps without recomputing them again.  The slot is overwritten;
+ * its memory is part of the workspace ((rk_order + 1) ghosted FP64 primitive
+ * arrays + rk_order bytes per cell per slot). */
+int grmhd_step_record(grmhd_ctx *ctx, double *U, double dt, int slot);
+
+/* Ubar <- (d U^(n+1) / d U^n)^T Ubar for the step recorded in tape slot
+ * `slot` (its dt and stages as recorded; no recomputation).  Returns
+ * GRMHD_ERR_STATE for a slot that was never recorded.  The result equals
+ * grmhd_step_adjoint from the step's starting state up to the rounding of
+ * the starting primitives (the recorded ones are those the forward step
+ * used; grmhd_step_adjoint recovers them from U afresh). */
+int grmhd_step_adjoint_recorded(grmhd_ctx *ctx, int slot, double *Ubar);
 
 /* Pbar = (dU/dP)^T Ubar at the primitives P (the adjoint of grmhd_cons).
  * All device arrays; Pbar is written. */

@@ -9,12 +9,13 @@ source-parameter inverse problems the paper motivates (section 1).
 
 Memory: the forward pass keeps the conserved state only every ``every``
 steps (checkpoints).  The backward pass walks the segments from the last to
-the first: it recomputes the states of a segment from its checkpoint with
-forward steps, then applies the step adjoint to them in reverse order.  The
-cost of a gradient is therefore about one forward evolution (the
-recomputation) plus ``nsteps`` step adjoints, each of which recomputes the
-stages of its step internally; the device memory is ``nsteps / every + every``
-states.
+the first and recomputes each segment from its checkpoint.  With a solver
+created with ``tape_steps >= every`` the recomputation records every step's
+stages (``grmhd_step_record``) and the reverse sweep uses them
+(``grmhd_step_adjoint_recorded``): a gradient costs one forward evolution
+(the recomputation) plus ``nsteps`` reverse sweeps, and the tape holds
+``every`` steps' stages.  Otherwise the recomputation keeps the segment's
+states and each ``grmhd_step_adjoint`` recomputes its step's stages again.
 
 Argument marshalling only: every operation runs in the library's kernels.
 """
@@ -45,14 +46,22 @@ class _Evolve(torch.autograd.Function):
         P0, U_end = ctx.saved_tensors
         Ubar = s.prim_adjoint(U_end, Pbar.contiguous())
         starts = sorted(ctx.checkpoints)
+        taped = s.tape_steps >= every
         for c in reversed(starts):
             stop = min(c + every, nsteps)
-            # recompute U_c .. U_(stop-1) from the checkpoint
+            # recompute the segment from its checkpoint
             U = ctx.checkpoints[c].clone()
             if c == 0:
                 s.cons(P0.detach().contiguous(), U)   # the step cache exactly as in the forward pass
             else:
                 s.prim(U)                   # the primitives of U_c into the step cache
+            if taped:
+                # every step of the segment recorded once, then reversed
+                for k in range(c, stop):
+                    s.step_record(U, dt, k - c)
+                for k in range(stop - 1, c - 1, -1):
+                    s.step_adjoint_recorded(k - c, Ubar)
+                continue
             states = [U.clone()]
             for _ in range(c + 1, stop):
                 s.step(U, dt)
@@ -67,7 +76,8 @@ class _Evolve(torch.autograd.Function):
 def evolve(solver, P0: torch.Tensor, dt: float, nsteps: int, every: int = 10) -> torch.Tensor:
     """Primitives after ``nsteps`` steps of size ``dt`` from ``P0`` (float64,
     shape (9, nz, ny, nx), on the solver's device), differentiable in ``P0``.
-    The solver must have been created with ``adjoint=True``; ``every`` is the
+    The solver must have been created with ``adjoint=True`` (and
+    ``tape_steps >= every`` to record the recomputed steps); ``every`` is the
     checkpoint interval of the backward pass."""
     if nsteps < 1 or every < 1:
         raise ValueError("nsteps and every must be >= 1")

@@ -13,12 +13,13 @@
 //   k_adj_face<D>  per face along D: the flux cotangent (Rb_right - Rb_left)/dx
 //                  pulled back through HLLE, the cleaning pair and the face
 //                  physics to the reconstructed left/right states;
-//   k_adj_gather<D> per position along D (ghosts included): those pulled back
-//                  through the MC reconstruction, accumulated over the axes;
-//   k_adj_cell     per cell: plus the cotangents of the ghosts that copy the
-//                  cell (the adjoint of the ghost fill) and the sources, =
-//                  Pb^s; then the recovery + RK adjoint of the stage below,
-//                  or, at the step's start (P^0 the primitives of U^n),
+//   k_adj_gather   per cell and per ghost position: those pulled back
+//                  through the MC reconstruction of every axis;
+//   k_adj_cell     per cell: plus the ghost positions that copy the cell (the
+//                  adjoint of the ghost fill) and the sources' cotangent,
+//                  = Pb^s; then the
+//                  recovery + RK adjoint of the stage below, or, at the
+//                  step's start (P^0 the primitives of U^n),
 //                  Ub^n += Unacc + (dU/dP)^-T Pb^0.
 // k_adj_final and k_adj_cons serve grmhd_prim_adjoint and grmhd_cons_adjoint.
 #include "grmhd_adjoint.h"
@@ -418,55 +419,136 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_rec(double* __restrict__ Ub, con
     }
 }
 
-// One thread per position along D over -2 .. n+1 (the ghosts of axis D
-// included), interior along the other axes: the cotangent of the primitives
-// there from the faces along D, into MU (ghosted layout).  Assigned at ghost
-// positions and, for the first active axis, at interior ones; added at
-// interior positions otherwise.  Light on registers: these kernels wait on
-// scattered loads and want occupancy.
+// Lines along axis D (cells of the other two axes) and the line of a cell.
 template <int D>
-__global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict__ Pc,
-                                                        const double* __restrict__ FB,
-                                                        double* __restrict__ MU, Dev d, int first)
+__device__ __forceinline__ long long line_of(const Dev& d, const int* ci)
 {
-    int m[3] = {d.n[0], d.n[1], d.n[2]};
-    m[D] += 4;
-    const long long total = (long long)m[0] * m[1] * m[2];
-    const long long t0 = (long long)blockIdx.x * ABLOCK + threadIdx.x;
-    if (t0 >= total)
-        return;
+    return D == 0 ? ci[1] + (long long)d.n[1] * ci[2]
+                  : (D == 1 ? ci[0] + (long long)d.n[0] * ci[2] : ci[0] + (long long)d.n[0] * ci[1]);
+}
+
+// The ghost positions of axis D, 4 per line (slots 0..3 = positions -2, -1,
+// n, n+1): the pull-back of the faces along D there, into G (layout
+// [9][4][lines]); the cell kernel adds each to the interior cell the ghost
+// fill copies into that position.
+template <int D>
+__device__ __forceinline__ void gather_ghost(const Dev& d, const double* __restrict__ Pc,
+                                             const double* __restrict__ FB, double* __restrict__ G,
+                                             long long t, long long lines)
+{
+    const int slot = (int)(t / lines);
+    const long long line = t - slot * lines;
     int ci[3];
-    ci[0] = (int)(t0 % m[0]);
-    const long long t = t0 / m[0];
-    ci[1] = (int)(t % m[1]);
-    ci[2] = (int)(t / m[1]);
-    ci[D] -= 2;
+    const int a = D == 0 ? 1 : 0, b = D == 2 ? 1 : 2;   // the two other axes
+    ci[a] = (int)(line % d.n[a]);
+    ci[b] = (int)(line / d.n[a]);
+    ci[D] = slot < 2 ? slot - 2 : d.n[D] + slot - 2;
     double mu[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v)
         mu[v] = 0.0;
     gather_pos<D>(d, Pc, FB, ci, mu);
-    const long long pc = ghosted(d, ci[0], ci[1], ci[2]);
-    const int i = ci[D];
-    const bool assign = first || i < 0 || i >= d.n[D];
 #pragma unroll
-    for (int v = 0; v < 9; ++v) {
-        double* out = MU + v * d.sv + pc;
-        *out = assign ? mu[v] : *out + mu[v];
+    for (int v = 0; v < 9; ++v)
+        G[(v * 4 + slot) * lines + line] = mu[v];
+}
+
+// Threads [0, N): one per interior cell, the cotangent of its primitives from
+// the face-state cotangents of every active axis (FB0/1/2, 18 rows of nf
+// values each) pulled back through the MC reconstruction, into MU (dense
+// [9][N]).  Then, per active axis, 4 threads per line for its ghost positions
+// (into G0/1/2).  Light on registers: this kernel waits on scattered loads
+// and wants occupancy.
+__global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict__ Pc,
+                                                        const double* __restrict__ FB0,
+                                                        const double* __restrict__ FB1,
+                                                        const double* __restrict__ FB2,
+                                                        double* __restrict__ MU, double* __restrict__ G0,
+                                                        double* __restrict__ G1, double* __restrict__ G2, Dev d)
+{
+    long long t = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (t < d.N) {
+        const long long r = t / d.n[0];
+        const int ci[3] = {(int)(t % d.n[0]), (int)(r % d.n[1]), (int)(r / d.n[1])};
+        double mu[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            mu[v] = 0.0;
+        if (d.act[0])
+            gather_pos<0>(d, Pc, FB0, ci, mu);
+        if (d.act[1])
+            gather_pos<1>(d, Pc, FB1, ci, mu);
+        if (d.act[2])
+            gather_pos<2>(d, Pc, FB2, ci, mu);
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            MU[v * d.N + t] = mu[v];
+        return;
+    }
+    t -= d.N;
+    if (d.act[0]) {
+        const long long lines = d.N / d.n[0];
+        if (t < 4 * lines) {
+            gather_ghost<0>(d, Pc, FB0, G0, t, lines);
+            return;
+        }
+        t -= 4 * lines;
+    }
+    if (d.act[1]) {
+        const long long lines = d.N / d.n[1];
+        if (t < 4 * lines) {
+            gather_ghost<1>(d, Pc, FB1, G1, t, lines);
+            return;
+        }
+        t -= 4 * lines;
+    }
+    if (d.act[2]) {
+        const long long lines = d.N / d.n[2];
+        if (t < 4 * lines)
+            gather_ghost<2>(d, Pc, FB2, G2, t, lines);
     }
 }
 
-// Per interior cell, after the gathers of stage s: Pb^s = MU at the cell +
-// MU at the ghost positions that copy it (the adjoint of the ghost fill:
-// periodic images, or the zero-gradient copies beside the first and last
-// cells) + the sources' cotangent at P^s; then, for s > 0, the recovery + RK
-// adjoint of stage s-1 (whose output is U^s, P^s; flags of that recovery in
+// The ghost slots of axis D that copy the interior cell ci (the adjoint of
+// the ghost fill: periodic images, or the zero-gradient copies beside the
+// first and last cells), added to pb.
+template <int D>
+__device__ __forceinline__ void fold_ghosts(const Dev& d, const double* __restrict__ G, const int* ci, double* pb)
+{
+    const int i = ci[D], n = d.n[D];
+    const long long lines = d.N / n, line = line_of<D>(d, ci);
+    int sl[2], ns = 0;
+    if (d.bc[D] == 0) {   // periodic: position n+i, or i-n
+        if (i < 2)
+            sl[ns++] = i + 2;
+        if (i >= n - 2)
+            sl[ns++] = i - n + 2;
+    } else if (i == 0) {
+        sl[ns++] = 0;
+        sl[ns++] = 1;
+    } else if (i == n - 1) {
+        sl[ns++] = 2;
+        sl[ns++] = 3;
+    }
+    for (int e = 0; e < ns; ++e)
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            pb[v] += G[(v * 4 + sl[e]) * lines + line];
+}
+
+// Per interior cell, after the gather of stage s: Pb^s = MU (the faces'
+// pull-back at the cell) + G at the ghost positions that copy the cell + the
+// sources' cotangent at P^s; then, for s > 0, the recovery +
+// RK adjoint of stage s-1 (whose output is U^s, P^s; flags of that recovery in
 // fprev, coefficients a, b): Ub <- (1 - a) Ub~, Unacc += a Ub~,
 // Rb = b dt Ub~; for s = 0 (fprev null) the step's input cotangent
 // Ub <- Ub + Unacc + (dU/dP)^-T Pb^0.
 template <int KIND>
 __global__ __launch_bounds__(ABLOCK) void k_adj_cell(const double* __restrict__ Pc,
                                                       const double* __restrict__ MU,
+                                                      const double* __restrict__ G0,
+                                                      const double* __restrict__ G1,
+                                                      const double* __restrict__ G2,
                                                       double* __restrict__ Rb, double* __restrict__ Ub,
                                                       double* __restrict__ Unacc,
                                                       const unsigned char* __restrict__ fprev, Dev d, double a,
@@ -484,37 +566,17 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_cell(const double* __restrict__ 
     double pb[9], q[9], rb[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
-        pb[v] = any ? MU[v * d.sv + pc] : 0.0;
+        pb[v] = any ? MU[v * d.N + c] : 0.0;
         q[v] = Pc[v * d.sv + pc];
         rb[v] = Rb[v * d.N + c];
     }
-    const int idx[3] = {i, j, k};
-    const long long stride[3] = {1, d.px, (long long)d.px * d.py};
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (!d.act[ax])
-            continue;
-        const int n = d.n[ax];
-        const long long st = stride[ax];
-        long long o[2];
-        int no = 0;
-        if (d.bc[ax] == 0) {
-            if (idx[ax] < 2)
-                o[no++] = n * st;
-            if (idx[ax] >= n - 2)
-                o[no++] = -n * st;
-        } else if (idx[ax] == 0) {
-            o[no++] = -st;
-            o[no++] = -2 * st;
-        } else if (idx[ax] == n - 1) {
-            o[no++] = st;
-            o[no++] = 2 * st;
-        }
-        for (int e = 0; e < no; ++e)
-#pragma unroll
-            for (int v = 0; v < 9; ++v)
-                pb[v] += MU[v * d.sv + pc + o[e]];
-    }
+    const int ci[3] = {i, j, k};
+    if (d.act[0])
+        fold_ghosts<0>(d, G0, ci, pb);
+    if (d.act[1])
+        fold_ghosts<1>(d, G1, ci, pb);
+    if (d.act[2])
+        fold_ghosts<2>(d, G2, ci, pb);
     const double3 x = centre(d, i, j, k);
     sources_rev<KIND>(d, x.x, x.y, x.z, q, rb, pb);
     double ub[9], ut[9];
@@ -631,30 +693,28 @@ hipError_t launch_adj_rec(int kind, double* Ub, const double* Pn, const unsigned
     return hipGetLastError();
 }
 
-hipError_t launch_adj_gather(int dir, const double* Pc, const double* FB, double* MU, const Dev& d, int first,
+hipError_t launch_adj_gather(const double* Pc, const double* const* FB, double* MU, double* const* G, const Dev& d,
                              hipStream_t s)
 {
-    long long m[3] = {d.n[0], d.n[1], d.n[2]};
-    m[dir] += 4;
-    const unsigned nb = ablocks(m[0] * m[1] * m[2]);
-    if (dir == 0)
-        hipLaunchKernelGGL((k_adj_gather<0>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
-    else if (dir == 1)
-        hipLaunchKernelGGL((k_adj_gather<1>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
-    else
-        hipLaunchKernelGGL((k_adj_gather<2>), dim3(nb), dim3(ABLOCK), 0, s, Pc, FB, MU, d, first);
+    long long total = d.N;
+    for (int a = 0; a < 3; ++a)
+        if (d.act[a])
+            total += 4 * (d.N / d.n[a]);
+    hipLaunchKernelGGL(k_adj_gather, dim3(ablocks(total)), dim3(ABLOCK), 0, s, Pc, FB[0], FB[1], FB[2], MU, G[0],
+                       G[1], G[2], d);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_cell(int kind, const double* Pc, const double* MU, double* Rb, double* Ub, double* Unacc,
-                           const unsigned char* fprev, const Dev& d, double a, double b, double dt, hipStream_t s)
+hipError_t launch_adj_cell(int kind, const double* Pc, const double* MU, const double* const* G, double* Rb,
+                           double* Ub, double* Unacc, const unsigned char* fprev, const Dev& d, double a, double b,
+                           double dt, hipStream_t s)
 {
     if (kind == FLAT)
-        hipLaunchKernelGGL((k_adj_cell<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Ub, Unacc, fprev,
-                           d, a, b, dt);
+        hipLaunchKernelGGL((k_adj_cell<FLAT>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, G[0], G[1], G[2], Rb,
+                           Ub, Unacc, fprev, d, a, b, dt);
     else
-        hipLaunchKernelGGL((k_adj_cell<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, Rb, Ub, Unacc, fprev,
-                           d, a, b, dt);
+        hipLaunchKernelGGL((k_adj_cell<ISO>), dim3(ablocks(d.N)), dim3(ABLOCK), 0, s, Pc, MU, G[0], G[1], G[2], Rb,
+                           Ub, Unacc, fprev, d, a, b, dt);
     return hipGetLastError();
 }
 

@@ -31,7 +31,11 @@ struct Layout {
     // accumulator, the R cotangent, a dense primitive scratch, the ghosted
     // cotangent of the primitives and the face-state cotangents of one axis
     bool adj;
-    size_t off_ac[4], off_aflags, off_aus, off_unacc, off_rb, off_pb, off_mu, off_fb;
+    size_t off_ac[4], off_aflags, off_aus, off_unacc, off_rb, off_pb, off_mu, off_fb[3], off_gmu[3];
+    // tape of recorded steps (FP64): per slot the ns+1 stage caches and the
+    // ns stages' recovery flags
+    int tape = 0;
+    size_t off_tape = 0, tape_slot = 0, tape_flags = 0;
     size_t total;
 };
 
@@ -55,7 +59,7 @@ bool grid_ok(const grmhd_grid* g)
     return true;
 }
 
-Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int ns = 3)
+Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int ns = 3, int tape = 0)
 {
     Layout L{};
     for (int d = 0; d < 3; ++d)
@@ -96,18 +100,27 @@ Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int 
         }
         L.off_aflags = off;
         off = round_up(off + (size_t)ns * L.N, 256);
-        size_t* dense_offs[4] = {&L.off_aus, &L.off_unacc, &L.off_rb, &L.off_pb};
+        size_t* dense_offs[5] = {&L.off_aus, &L.off_unacc, &L.off_rb, &L.off_pb, &L.off_mu};
         for (size_t* o : dense_offs) {
             *o = off;
             off = round_up(off + dense, 256);
         }
-        long long nfmax = 0;
-        for (int d = 0; d < 3; ++d)
-            nfmax = L.nf[d] > nfmax ? L.nf[d] : nfmax;
-        L.off_mu = off;
-        off = round_up(off + cache, 256);
-        L.off_fb = off;
-        off = round_up(off + sizeof(double) * 18 * (size_t)nfmax, 256);
+        // the left/right face-state cotangents of every active axis, and the
+        // primitive cotangents at its ghost positions (4 per line)
+        for (int d = 0; d < 3; ++d) {
+            L.off_fb[d] = off;
+            off = round_up(off + sizeof(double) * 18 * (size_t)L.nf[d], 256);
+            L.off_gmu[d] = off;
+            if (L.nf[d])
+                off = round_up(off + sizeof(double) * 9 * 4 * (size_t)(L.N / g->n[d]), 256);
+        }
+        if (tape > 0) {
+            L.tape = tape;
+            L.tape_flags = round_up(cache, 256) * (size_t)(ns + 1);
+            L.tape_slot = L.tape_flags + round_up((size_t)ns * L.N, 256);
+            L.off_tape = off;
+            off += L.tape_slot * (size_t)tape;
+        }
     }
     L.total = off;
     return L;
@@ -116,6 +129,11 @@ Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int 
 bool wants_adjoint(const grmhd_opts* o)
 {
     return o && o->adjoint && o->precision == GRMHD_FP64;
+}
+
+int tape_slots(const grmhd_opts* o)
+{
+    return wants_adjoint(o) && o->tape_steps > 0 && o->tape_steps <= 4096 ? o->tape_steps : 0;
 }
 
 // bytes of one value of the primitive caches and face buffers
@@ -149,7 +167,11 @@ struct grmhd_ctx {
     bool adj_prepared = false;
     double* Ac[4] = {nullptr, nullptr, nullptr, nullptr};
     unsigned char* Aflags = nullptr;
-    double *Aus = nullptr, *Unacc = nullptr, *Rb = nullptr, *Pb = nullptr, *MU = nullptr, *FB = nullptr;
+    double *Aus = nullptr, *Unacc = nullptr, *Rb = nullptr, *Pb = nullptr, *MU = nullptr;
+    double* FB[3] = {nullptr, nullptr, nullptr};
+    double* GMU[3] = {nullptr, nullptr, nullptr};
+    // recorded steps: dt of each slot (NaN: never recorded)
+    std::vector<double> tape_dt;
     unsigned long long* cnt = nullptr;
     bool prepared = false;
     bool cache_valid = false;
@@ -304,6 +326,12 @@ int rhs_t(grmhd_ctx* c, const double* P, double* R)
     });
 }
 
+// SSP Runge-Kutta stages: U^(s+1) = U^s + a_s (U^n - U^s) + b_s dt R(P^s)
+const double RK3A[3] = {0.0, 0.75, 1.0 / 3.0};
+const double RK3B[3] = {1.0, 0.25, 2.0 / 3.0};
+const double RK2A[2] = {0.0, 0.5};
+const double RK2B[2] = {1.0, 0.5};
+
 // One substep's update launch with the stage-state types TS (read) and TO
 // (written).
 template <typename T, typename TS, typename TO>
@@ -324,13 +352,9 @@ int update_stage(grmhd_ctx* c, bool zmarch, int src, int dst, const double* U, c
 template <typename T>
 int step_t(grmhd_ctx* c, double* U, double dt)
 {
-    static const double rk3a[3] = {0.0, 0.75, 1.0 / 3.0};
-    static const double rk3b[3] = {1.0, 0.25, 2.0 / 3.0};
-    static const double rk2a[2] = {0.0, 0.5};
-    static const double rk2b[2] = {1.0, 0.5};
     const int ns = c->rk_order;
-    const double* A = ns == 3 ? rk3a : rk2a;
-    const double* B = ns == 3 ? rk3b : rk2b;
+    const double* A = ns == 3 ? RK3A : RK2A;
+    const double* B = ns == 3 ? RK3B : RK2B;
     // 3D grids: the z faces are computed inside the fused update kernel, which
     // writes the new primitives to another cache; otherwise the update works
     // in place on the cache with all face fluxes precomputed.  The first stage
@@ -357,6 +381,8 @@ int step_t(grmhd_ctx* c, double* U, double dt)
     return GRMHD_OK;
 }
 
+double* tape_cache(grmhd_ctx* c, int slot, int b);
+
 // Adjoint: first use fills the stage caches with NaN (their never-written
 // edge and corner ghosts included), so that the first recovery of P^0 has no
 // valid guess and takes the bracketed solve.
@@ -370,6 +396,10 @@ int adj_prepare(grmhd_ctx* c)
     for (int b = 0; b <= c->rk_order; ++b)
         if (grmhd::launch_fill(c->Ac[b], 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
+    for (int t = 0; t < c->L.tape; ++t)
+        for (int b = 0; b <= c->rk_order; ++b)
+            if (grmhd::launch_fill(tape_cache(c, t, b), 9 * c->L.sv, std::nan(""), c->stream) != hipSuccess)
+                return GRMHD_ERR_HIP;
     c->adj_prepared = true;
     return GRMHD_OK;
 }
@@ -414,54 +444,138 @@ int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, con
     return GRMHD_OK;
 }
 
-int step_adjoint(grmhd_ctx* c, const double* U, double* Ubar, double dt)
+// Reverse sweep of one step whose stage primitives P^0..P^ns are Ps[] and
+// whose stages' recovery flags are flags[s * N]: Ubar <- (dU^(n+1)/dU^n)^T Ubar.
+int reverse_sweep(grmhd_ctx* c, const double* const* Ps, const unsigned char* flags, double* Ubar, double dt)
 {
-    static const double rk3a[3] = {0.0, 0.75, 1.0 / 3.0};
-    static const double rk3b[3] = {1.0, 0.25, 2.0 / 3.0};
-    static const double rk2a[2] = {0.0, 0.5};
-    static const double rk2b[2] = {1.0, 0.5};
     const int ns = c->rk_order;
-    const double* A = ns == 3 ? rk3a : rk2a;
-    const double* B = ns == 3 ? rk3b : rk2b;
-    int rc = adj_recompute(c, U, dt, A, B);
-    if (rc)
-        return rc;
+    const double* A = ns == 3 ? RK3A : RK2A;
+    const double* B = ns == 3 ? RK3B : RK2B;
     // the last stage's recovery + RK adjoint (its output is the step's)
-    rc = timed(c, GRMHD_K_ADJ_REC, [&] {
-        return grmhd::launch_adj_rec(c->kind, Ubar, c->Ac[ns], c->Aflags + (size_t)(ns - 1) * c->L.N, c->Unacc,
-                                     c->Rb, c->d, A[ns - 1], B[ns - 1], dt, c->stream);
+    int rc = timed(c, GRMHD_K_ADJ_REC, [&] {
+        return grmhd::launch_adj_rec(c->kind, Ubar, Ps[ns], flags + (size_t)(ns - 1) * c->L.N, c->Unacc, c->Rb,
+                                     c->d, A[ns - 1], B[ns - 1], dt, c->stream);
     });
     if (rc)
         return rc;
     for (int s = ns - 1; s >= 0; --s) {
-        const double* Ps = c->Ac[s];
-        int first = 1;
+        bool any = false;
         for (int dir = 0; dir < 3; ++dir) {
             if (!c->d.act[dir])
                 continue;
             rc = timed(c, GRMHD_K_ADJ_FACE, [&] {
-                return grmhd::launch_adj_face(c->kind, dir, Ps, c->Rb, c->FB, c->d, c->stream);
+                return grmhd::launch_adj_face(c->kind, dir, Ps[s], c->Rb, c->FB[dir], c->d, c->stream);
             });
             if (rc)
                 return rc;
+            any = true;
+        }
+        if (any) {
             rc = timed(c, GRMHD_K_ADJ_GATHER, [&] {
-                return grmhd::launch_adj_gather(dir, Ps, c->FB, c->MU, c->d, first, c->stream);
+                return grmhd::launch_adj_gather(Ps[s], c->FB, c->MU, c->GMU, c->d, c->stream);
             });
             if (rc)
                 return rc;
-            first = 0;
         }
         // Pb^s, then the recovery + RK adjoint of stage s-1 (or the step's start)
-        const unsigned char* fprev = s > 0 ? c->Aflags + (size_t)(s - 1) * c->L.N : nullptr;
+        const unsigned char* fprev = s > 0 ? flags + (size_t)(s - 1) * c->L.N : nullptr;
         const double a = s > 0 ? A[s - 1] : 0.0, b = s > 0 ? B[s - 1] : 0.0;
         rc = timed(c, GRMHD_K_ADJ_CELL, [&] {
-            return grmhd::launch_adj_cell(c->kind, Ps, c->MU, c->Rb, Ubar, c->Unacc, fprev, c->d, a, b, dt,
-                                          c->stream);
+            return grmhd::launch_adj_cell(c->kind, Ps[s], c->MU, c->GMU, c->Rb, Ubar, c->Unacc, fprev, c->d, a,
+                                          b, dt, c->stream);
         });
         if (rc)
             return rc;
     }
     return GRMHD_OK;
+}
+
+int step_adjoint(grmhd_ctx* c, const double* U, double* Ubar, double dt)
+{
+    const int ns = c->rk_order;
+    int rc = adj_recompute(c, U, dt, ns == 3 ? RK3A : RK2A, ns == 3 ? RK3B : RK2B);
+    if (rc)
+        return rc;
+    return reverse_sweep(c, c->Ac, c->Aflags, Ubar, dt);
+}
+
+double* tape_cache(grmhd_ctx* c, int slot, int b)
+{
+    const size_t cache = round_up(sizeof(double) * 9 * (size_t)c->L.sv, 256);
+    return (double*)(c->ws + c->L.off_tape + (size_t)slot * c->L.tape_slot + (size_t)b * cache);
+}
+
+unsigned char* tape_flags(grmhd_ctx* c, int slot)
+{
+    return c->ws + c->L.off_tape + (size_t)slot * c->L.tape_slot + c->L.tape_flags;
+}
+
+// One forward step with the kernels, inputs and order of step_t<double> (so
+// U and the primitives come out bitwise the same), the stage primitives
+// written to the caches of tape slot `slot` instead of the rotating caches
+// and the stages' recovery flags kept beside them.  The step's starting
+// primitives are copied into the slot first, its final ones back to the
+// current cache afterwards.
+int step_record(grmhd_ctx* c, double* U, double dt, int slot)
+{
+    const int ns = c->rk_order;
+    const double* A = ns == 3 ? RK3A : RK2A;
+    const double* B = ns == 3 ? RK3B : RK2B;
+    const bool zmarch = c->d.act[2] != 0;
+    const size_t bytes = sizeof(double) * 9 * (size_t)c->L.sv;
+    int rc = GRMHD_OK;
+    if (!c->ghosts_ok[0]) {
+        rc = timed(c, GRMHD_K_BC, [&] { return grmhd::launch_ghosts((double*)c->Pbuf[0], c->d, c->stream); });
+        if (rc)
+            return rc;
+        c->ghosts_ok[0] = true;
+    }
+    if (hipMemcpyAsync(tape_cache(c, slot, 0), c->Pbuf[0], bytes, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+        return GRMHD_ERR_HIP;
+    double* Us = (double*)c->Us;
+    unsigned char* fl = tape_flags(c, slot);
+    for (int s = 0; s < ns; ++s) {
+        const double* Ps = tape_cache(c, slot, s);
+        double* Pn = tape_cache(c, slot, s + 1);
+        for (int dir = 0; dir < (zmarch ? 2 : 3); ++dir) {
+            if (!c->d.act[dir])
+                continue;
+            rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
+                return grmhd::launch_flux(c->kind, dir, Ps, (double*)c->F[dir], c->d, c->stream);
+            });
+            if (rc)
+                return rc;
+        }
+        const double* Uin = s == 0 ? U : Us;
+        double* Uo = s == ns - 1 ? U : Us;
+        unsigned char* f = fl + (size_t)s * c->L.N;
+        rc = timed(c, GRMHD_K_UPDATE, [&] {
+            if (zmarch)
+                return grmhd::launch_update_zmarch(c->kind, (const double*)c->F[0], (const double*)c->F[1], Ps,
+                                                   Pn, U, Uin, Uo, c->d, dt, A[s], B[s], c->cnt, f, c->stream);
+            return grmhd::launch_update(c->kind, (const double*)c->F[0], (const double*)c->F[1],
+                                        (const double*)c->F[2], Ps, Pn, U, Uin, Uo, c->d, dt, A[s], B[s],
+                                        c->cnt, f, c->stream);
+        });
+        if (rc)
+            return rc;
+    }
+    if (hipMemcpyAsync(c->Pbuf[0], tape_cache(c, slot, ns), bytes, hipMemcpyDeviceToDevice, c->stream) !=
+        hipSuccess)
+        return GRMHD_ERR_HIP;
+    c->ghosts_ok[0] = true;
+    c->tape_dt[slot] = dt;
+    return GRMHD_OK;
+}
+
+int step_adjoint_recorded(grmhd_ctx* c, int slot, double* Ubar)
+{
+    const double dt = c->tape_dt[slot];
+    const double* Ps[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int b = 0; b <= c->rk_order; ++b)
+        Ps[b] = tape_cache(c, slot, b);
+    return reverse_sweep(c, Ps, tape_flags(c, slot), Ubar, dt);
 }
 
 }  // namespace
@@ -473,7 +587,7 @@ size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_opts* opts)
     if (!grid_ok(grid))
         return 0;
     const int ns = opts && opts->rk_order == 2 ? 2 : 3;
-    return make_layout(grid, elem_size(opts), wants_adjoint(opts), ns).total;
+    return make_layout(grid, elem_size(opts), wants_adjoint(opts), ns, tape_slots(opts)).total;
 }
 
 int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
@@ -504,7 +618,9 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
         return GRMHD_ERR_ARG;
     if (opts->adjoint && opts->precision != GRMHD_FP64)
         return GRMHD_ERR_ARG;
-    Layout L = make_layout(grid, elem_size(opts), wants_adjoint(opts), opts->rk_order);
+    if (opts->tape_steps < 0 || opts->tape_steps > 4096)
+        return GRMHD_ERR_ARG;
+    Layout L = make_layout(grid, elem_size(opts), wants_adjoint(opts), opts->rk_order, tape_slots(opts));
     if (!opts->workspace || opts->workspace_bytes < L.total)
         return GRMHD_ERR_WORKSPACE;
     if (((uintptr_t)opts->workspace) % 256 != 0)
@@ -567,7 +683,11 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
         c->Rb = (double*)(c->ws + L.off_rb);
         c->Pb = (double*)(c->ws + L.off_pb);
         c->MU = (double*)(c->ws + L.off_mu);
-        c->FB = (double*)(c->ws + L.off_fb);
+        for (int a = 0; a < 3; ++a)
+            c->FB[a] = L.nf[a] ? (double*)(c->ws + L.off_fb[a]) : nullptr;
+        for (int a = 0; a < 3; ++a)
+            c->GMU[a] = L.nf[a] ? (double*)(c->ws + L.off_gmu[a]) : nullptr;
+        c->tape_dt.assign((size_t)L.tape, std::nan(""));
     }
     *out = c;
     return GRMHD_OK;
@@ -621,6 +741,38 @@ int grmhd_step_adjoint(grmhd_ctx* c, const double* U, double* Ubar, double dt)
     if (rc)
         return rc;
     return step_adjoint(c, U, Ubar, dt);
+}
+
+int grmhd_step_record(grmhd_ctx* c, double* U, double dt, int slot)
+{
+    if (!c || !U || !std::isfinite(dt))
+        return GRMHD_ERR_ARG;
+    if (!c->adj)
+        return GRMHD_ERR_NO_ADJOINT;
+    if (slot < 0 || slot >= c->L.tape)
+        return GRMHD_ERR_ARG;
+    if (!c->cache_valid)
+        return GRMHD_ERR_STATE;
+    int rc = adj_prepare(c);
+    if (rc)
+        return rc;
+    return step_record(c, U, dt, slot);
+}
+
+int grmhd_step_adjoint_recorded(grmhd_ctx* c, int slot, double* Ubar)
+{
+    if (!c || !Ubar)
+        return GRMHD_ERR_ARG;
+    if (!c->adj)
+        return GRMHD_ERR_NO_ADJOINT;
+    if (slot < 0 || slot >= c->L.tape)
+        return GRMHD_ERR_ARG;
+    if (!std::isfinite(c->tape_dt[slot]))
+        return GRMHD_ERR_STATE;
+    int rc = adj_prepare(c);
+    if (rc)
+        return rc;
+    return step_adjoint_recorded(c, slot, Ubar);
 }
 
 int grmhd_cons_adjoint(grmhd_ctx* c, const double* P, const double* Ubar, double* Pbar)

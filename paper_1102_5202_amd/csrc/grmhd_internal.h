@@ -84,10 +84,11 @@ hipError_t launch_adj_rec(int kind, double* Ub, const double* Pn, const unsigned
                           double* Rb, const Dev& d, double a, double b, double dt, hipStream_t s);
 hipError_t launch_adj_face(int kind, int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
                            hipStream_t s);
-hipError_t launch_adj_gather(int dir, const double* Pc, const double* FB, double* MU, const Dev& d, int first,
+hipError_t launch_adj_gather(const double* Pc, const double* const* FB, double* MU, double* const* G, const Dev& d,
                              hipStream_t s);
-hipError_t launch_adj_cell(int kind, const double* Pc, const double* MU, double* Rb, double* Ub, double* Unacc,
-                           const unsigned char* fprev, const Dev& d, double a, double b, double dt, hipStream_t s);
+hipError_t launch_adj_cell(int kind, const double* Pc, const double* MU, const double* const* G, double* Rb,
+                           double* Ub, double* Unacc, const unsigned char* fprev, const Dev& d, double a, double b,
+                           double dt, hipStream_t s);
 hipError_t launch_adj_final(int kind, const double* Ub, const double* Pb, const double* P0, const double* Unacc,
                             double* Ubar, const Dev& d, hipStream_t s);
 hipError_t launch_adj_cons(int kind, const double* P, const double* Ubar, double* Pbar, const Dev& d,

@@ -25,7 +25,8 @@ NVAR = 9
 
 # exported symbols of include/grmhd.h
 SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_cons", "grmhd_step",
-           "grmhd_prim", "grmhd_rhs", "grmhd_step_adjoint", "grmhd_cons_adjoint",
+           "grmhd_prim", "grmhd_rhs", "grmhd_step_adjoint", "grmhd_step_record",
+           "grmhd_step_adjoint_recorded", "grmhd_cons_adjoint",
            "grmhd_prim_adjoint", "grmhd_status", "grmhd_timing", "grmhd_free", "grmhd_strerror",
            "grmhd_batch_workspace_bytes", "grmhd_batch_init", "grmhd_batch_set_stream",
            "grmhd_batch_cons", "grmhd_batch_evolve", "grmhd_batch_prim", "grmhd_batch_tune",
@@ -49,7 +50,8 @@ class Opts(C.Structure):
     _fields_ = [("rk_order", C.c_int), ("precision", C.c_int), ("c_h", C.c_double),
                 ("kappa", C.c_double), ("rho_atm", C.c_double), ("p_atm", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("timing", C.c_int),
-                ("adjoint", C.c_int), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("adjoint", C.c_int), ("tape_steps", C.c_int), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
 
 
 class BatchDesc(C.Structure):
@@ -87,6 +89,8 @@ def load(path: str = LIB_PATH):
     L.grmhd_prim.argtypes = [vp, vp, vp]
     L.grmhd_rhs.argtypes = [vp, vp, vp]
     L.grmhd_step_adjoint.argtypes = [vp, vp, vp, C.c_double]
+    L.grmhd_step_record.argtypes = [vp, vp, C.c_double, C.c_int]
+    L.grmhd_step_adjoint_recorded.argtypes = [vp, C.c_int, vp]
     L.grmhd_cons_adjoint.argtypes = [vp, vp, vp, vp]
     L.grmhd_prim_adjoint.argtypes = [vp, vp, vp, vp]
     L.grmhd_status.argtypes = [vp, C.POINTER(Stats), C.c_int]
@@ -129,11 +133,12 @@ def make_grid(n, lo, hi, bc) -> Grid:
 
 
 def workspace_bytes(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0, 0, 0), precision="fp64",
-                    rk_order=3, adjoint=False) -> int:
+                    rk_order=3, adjoint=False, tape_steps=0) -> int:
     o = Opts()
     o.precision = PRECISIONS[precision]
     o.rk_order = int(rk_order)
     o.adjoint = int(bool(adjoint))
+    o.tape_steps = int(tape_steps)
     return int(load().grmhd_workspace_bytes(C.byref(make_grid(n, lo, hi, bc)), C.byref(o)))
 
 
@@ -145,12 +150,13 @@ class Solver:
     device: P = (rho, p, u~x, u~y, u~z, Bx, By, Bz, Phi),
     U = (D, tau, Sx, Sy, Sz, Bdx, Bdy, Bdz, Phi).  precision "fp64" or
     "mixed" (float face physics and caches, double accumulation and recovery).
-    adjoint=True (FP64 only) reserves the workspace of the adjoint calls."""
+    adjoint=True (FP64 only) reserves the workspace of the adjoint calls;
+    tape_steps > 0 (with adjoint) adds that many slots of recorded steps."""
 
     def __init__(self, n, lo, hi, bc, metric=FLAT, M=0.0, soft=SOFT_SQRT, r_min=1.0,
                  gamma=5.0 / 3.0, K=0.0, rk_order=3, c_h=1.0, kappa=1.0, rho_atm=1e-12,
                  p_atm=1e-12, newton_tol=1e-12, newton_maxit=50, timing=False, device="cuda",
-                 stream=None, precision="fp64", adjoint=False):
+                 stream=None, precision="fp64", adjoint=False, tape_steps=0):
         L = load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -165,7 +171,7 @@ class Solver:
         self.precision = precision
         self._opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa),
                           float(rho_atm), float(p_atm), float(newton_tol), int(newton_maxit),
-                          int(bool(timing)), int(bool(adjoint)), None, 0)
+                          int(bool(timing)), int(bool(adjoint)), int(tape_steps), None, 0)
         nbytes = int(L.grmhd_workspace_bytes(C.byref(self._grid), C.byref(self._opts)))
         if nbytes == 0:
             raise ValueError("invalid grid")
@@ -177,6 +183,7 @@ class Solver:
         _check(L.grmhd_init(C.byref(ctx), C.byref(self._metric), C.byref(self._grid),
                             C.byref(self._eos), C.byref(self._opts)), "grmhd_init")
         self._ctx = ctx
+        self.tape_steps = int(tape_steps) if adjoint else 0
         self.set_stream(stream if stream is not None else torch.cuda.current_stream(self.device))
 
     # -- plumbing ------------------------------------------------------------
@@ -224,6 +231,18 @@ class Solver:
         _check(load().grmhd_step_adjoint(self._ctx, C.c_void_p(self._t(U, "U")),
                                          C.c_void_p(self._t(Ubar, "Ubar")), float(dt)),
                "grmhd_step_adjoint")
+        return Ubar
+
+    def step_record(self, U: torch.Tensor, dt: float, slot: int) -> torch.Tensor:
+        """One step of U in place, as step(), keeping its stages in tape slot `slot`."""
+        _check(load().grmhd_step_record(self._ctx, C.c_void_p(self._t(U, "U")), float(dt), int(slot)),
+               "grmhd_step_record")
+        return U
+
+    def step_adjoint_recorded(self, slot: int, Ubar: torch.Tensor) -> torch.Tensor:
+        """Ubar <- (dU^(n+1)/dU^n)^T Ubar for the step recorded in tape slot `slot`."""
+        _check(load().grmhd_step_adjoint_recorded(self._ctx, int(slot), C.c_void_p(self._t(Ubar, "Ubar"))),
+               "grmhd_step_adjoint_recorded")
         return Ubar
 
     def cons_adjoint(self, P: torch.Tensor, Ubar: torch.Tensor, Pbar: torch.Tensor = None) -> torch.Tensor:
@@ -294,7 +313,7 @@ class BatchSolver:
             raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
         self.precision = precision
         self._opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa), float(rho_atm),
-                          float(p_atm), float(newton_tol), int(newton_maxit), 0, 0, None, 0)
+                          float(p_atm), float(newton_tol), int(newton_maxit), 0, 0, 0, None, 0)
         nbytes = int(L.grmhd_batch_workspace_bytes(C.byref(self._desc), C.byref(self._opts)))
         if nbytes == 0:
             raise ValueError("invalid batch description")

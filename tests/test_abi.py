@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 24, names
+    assert len(names) == 26, names
     assert set(names) == set(lib.SYMBOLS)
     L = lib.load()
     for n in names:
@@ -67,13 +67,13 @@ def test_workspace_and_init_validation(lib):
             assert L.grmhd_free(ctx) == 0
         return rc
 
-    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)
+    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)
     assert init(ok) == 0
-    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb - 8)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr + 8), nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, None, nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb - 8)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr + 8), nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, None, nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)) == -1
     assert init(ok, eos=lib.Eos(0, 2.5, 0.0)) == -1
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 0.4)) == -1   # r_min <= M/2
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 1.0)) == 0
@@ -98,8 +98,10 @@ def test_workspace_and_init_validation(lib):
 
 def test_adjoint_workspace(lib):
     """The adjoint part of the workspace: FP64 only, ns+1 ghosted stage caches,
-    stage flags, four dense arrays, a ghosted cotangent and the 18 face-state
-    cotangents of one axis on top of the forward workspace."""
+    stage flags, five dense arrays (stage state, two U cotangents, the
+    right-hand side's cotangent, the pulled-back primitive cotangent), the
+    18 face-state cotangents of every axis and the primitive cotangents at
+    every axis' ghost positions on top of the forward workspace."""
     L = lib.load()
     n = (16, 8, 6)
     g = lib.make_grid(n, (0, 0, 0), (1, 1, 1), (0, 1, 1))
@@ -112,19 +114,63 @@ def test_adjoint_workspace(lib):
         px = ((16 + 4 + 7) // 8) * 8
         sv = px * 12 * 10
         N = 16 * 8 * 6
-        nfmax = max(17 * 8 * 6, 16 * 9 * 6, 16 * 8 * 7)
-        assert adj - fwd >= 8 * 9 * ((rk + 2) * sv + 4 * N) + rk * N + 8 * 18 * nfmax
-        assert adj - fwd <= 8 * 9 * ((rk + 2) * sv + 4 * N) + rk * N + 8 * 18 * nfmax + 256 * 12
+        nf = 17 * 8 * 6 + 16 * 9 * 6 + 16 * 8 * 7
+        ghosts = 4 * (N // 16 + N // 8 + N // 6)   # 4 ghost positions per line and axis
+        want = 8 * 9 * ((rk + 1) * sv + 5 * N + ghosts) + rk * N + 8 * 18 * nf
+        assert want <= adj - fwd <= want + 256 * 16
         o.precision = 1                      # mixed: no adjoint workspace, and init refuses it
         assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) < fwd
     raw, addr = _host_ws(adj)
     m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 1, C.c_void_p(addr), adj)
+    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 1, 0, C.c_void_p(addr), adj)
     ctx = C.c_void_p()
     assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
     o.precision = 0
     assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == 0
+    assert L.grmhd_free(ctx) == 0
+
+
+def test_tape_workspace_and_validation(lib):
+    """Tape slots of recorded steps: (rk+1) ghosted FP64 caches and rk flag
+    bytes per cell per slot; slot and state checks happen on the host."""
+    L = lib.load()
+    n = (16, 8, 6)
+    g = lib.make_grid(n, (0, 0, 0), (1, 1, 1), (0, 1, 1))
+    px = ((16 + 4 + 7) // 8) * 8
+    sv = px * 12 * 10
+    N = 16 * 8 * 6
+    up = lambda x: (x + 255) // 256 * 256
+    for rk in (2, 3):
+        o = lib.Opts()
+        o.rk_order = rk
+        o.adjoint = 1
+        base = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        o.tape_steps = 5
+        taped = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        assert taped - base == 5 * ((rk + 1) * up(8 * 9 * sv) + up(rk * N))
+        o.adjoint = 0                        # the tape belongs to the adjoint workspace
+        assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) < base
+    o = lib.Opts()
+    o.rk_order, o.adjoint, o.tape_steps, o.rho_atm, o.p_atm = 2, 1, 3, 1e-12, 1e-12
+    nb = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+    raw, addr = _host_ws(nb)
+    o.workspace, o.workspace_bytes = C.c_void_p(addr), nb
+    m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
+    e = lib.Eos(0, 5.0 / 3.0, 0.0)
+    ctx = C.c_void_p()
+    for bad in (-1, 4097):
+        o.tape_steps = bad
+        assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
+    o.tape_steps = 3
+    assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == 0
+    dummy = C.c_void_p(addr)                 # never dereferenced: every call below fails its checks
+    assert L.grmhd_step_record(ctx, dummy, 0.1, 3) == -1          # slot out of range
+    assert L.grmhd_step_record(ctx, dummy, 0.1, -1) == -1
+    assert L.grmhd_step_record(ctx, dummy, float("nan"), 0) == -1
+    assert L.grmhd_step_record(ctx, dummy, 0.1, 0) == -4          # no primitives yet (cons/prim first)
+    assert L.grmhd_step_adjoint_recorded(ctx, 0, dummy) == -4     # slot never recorded
+    assert L.grmhd_step_adjoint_recorded(ctx, 3, dummy) == -1
     assert L.grmhd_free(ctx) == 0
 
 
@@ -147,7 +193,7 @@ def test_batch_workspace_and_init_validation(lib):
     o.precision = 0
     raw, addr = _host_ws(nb)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, C.c_void_p(addr), nb)
+    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)
     ctx = C.c_void_p()
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == 0
     assert L.grmhd_batch_evolve(ctx, C.c_void_p(addr), 5) == -4      # before cons

@@ -123,7 +123,8 @@ def test_prim_adjoint(G, orc, AD):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_step_adjoint_matches_oracle(G, orc, AD, name):
-    """One step's vector-Jacobian product, Ubar^n = (dU^(n+1)/dU^n)^T Ubar."""
+    """One step's vector-Jacobian product, Ubar^n = (dU^(n+1)/dU^n)^T Ubar,
+    by grmhd_step_adjoint (twice) and from a recorded step."""
     w = CASES[name]
     pb = orc.Problem(**w.problem_kwargs())
     U0, P0, sto = orc.step(pb, orc.prim2con(pb, w.P), w.P, w.dt, 1)   # a state that has been stepped
@@ -139,6 +140,14 @@ def test_step_adjoint_matches_oracle(G, orc, AD, name):
         s.step_adjoint(Ug, Ub, w.dt)
         gpus.append(Ub.cpu().numpy())
     st = s.status()
+    # the same step recorded by a forward pass and reversed from the tape
+    sr = G.solver_for(w, device=DEV, adjoint=True, tape_steps=1)
+    Ur = _t(U0)
+    sr.prim(Ur)
+    sr.step_record(Ur, w.dt, 0)
+    Ub = _t(Ubar)
+    sr.step_adjoint_recorded(0, Ub)
+    gpus.append(Ub.cpu().numpy())
     U = torch.from_numpy(U0.copy()).requires_grad_(True)
     P = AD.primitives_of(pb, U, torch.from_numpy(P0))
     U1, _ = AD.step(pb, U, P, w.dt, 1)
@@ -159,6 +168,25 @@ def test_step_adjoint_matches_oracle(G, orc, AD, name):
         say(name, "step_adjoint rel-L1", err, st)
         assert np.all(np.isfinite(gpu))
         assert np.all(err <= bar)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_recorded_step_is_the_step(G, name):
+    """grmhd_step_record advances U and the primitives bitwise as grmhd_step
+    does, step after step, and leaves the context ready for a plain step."""
+    w = CASES[name]
+    P0 = _t(w.P)
+    a = G.solver_for(w, device=DEV)
+    b = G.solver_for(w, device=DEV, adjoint=True, tape_steps=2)
+    Ua, Ub = a.cons(P0), b.cons(P0)
+    for k in range(3):
+        a.step(Ua, w.dt)
+        if k < 2:
+            b.step_record(Ub, w.dt, k)
+        else:
+            b.step(Ub, w.dt)
+        assert torch.equal(Ua, Ub), (name, k)
+    assert torch.equal(a.prim(Ua), b.prim(Ub))
 
 
 def _loss_chain(G, w, s, P0, tgt, nsteps):
@@ -242,21 +270,29 @@ def test_loss_gradient_finite_differences(G):
 
 def test_autograd_evolve_with_checkpoints(G):
     """torch.autograd through evolve(): the gradient equals the plain adjoint
-    chain, whatever the checkpoint interval."""
+    chain, whatever the checkpoint interval; with the tape of recorded steps
+    as well, to rounding (the recorded steps linearise
+    around the primitives the forward steps used, the chain around primitives
+    recovered afresh, which differ at rounding level).  Every variable is
+    varied: at a uniform field the MC slopes sit on their kink, where the
+    branch, and so the derivative, follows the rounding of the primitives."""
     from paper_1102_5202_amd.adjoint import evolve
     w = WL.config4(n=16, nsteps=7)
+    w.P = _vary_all(w.P)
     s = G.solver_for(w, device=DEV, adjoint=True)
+    st = G.solver_for(w, device=DEV, adjoint=True, tape_steps=10)
     tgt = _t(w.extra["target"])
     L, g_chain = _loss_chain(G, w, s, _t(w.P), tgt, w.nsteps)
     grads = []
-    for every in (1, 3, 10):
-        P0 = _t(w.P).requires_grad_(True)
-        P = evolve(s, P0, w.dt, w.nsteps, every)
-        loss = ((P[0] - tgt) ** 2).sum()
-        loss.backward()
-        assert abs(loss.item() - L) <= 1e-14 * L
-        grads.append(P0.grad.clone())
-    for g in grads:
+    for solver in (s, st):
+        for every in (1, 3, 10):
+            P0 = _t(w.P).requires_grad_(True)
+            P = evolve(solver, P0, w.dt, w.nsteps, every)
+            loss = ((P[0] - tgt) ** 2).sum()
+            loss.backward()
+            assert abs(loss.item() - L) <= 1e-14 * L
+            grads.append(P0.grad.clone())
+    for e, g in enumerate(grads):
         rel = float((g - g_chain).abs().sum() / g_chain.abs().sum())
-        say("evolve gradient vs chain", rel)
+        say("evolve gradient vs chain", "taped" if e >= 3 else "untaped", rel)
         assert rel <= 1e-12
