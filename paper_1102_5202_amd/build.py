@@ -4,7 +4,12 @@
 
 All device code is compiled with packed-FP32 instruction selection disabled
 (``-packed-fp32-ops``) and without fast-math; FMA contraction is left at the
-compiler default.
+compiler default.  Single-precision division and square root (used only by
+the mixed-precision path's face physics and sources) take the hardware
+reciprocal and square-root instructions instead of the correctly rounded
+sequences (``-fno-hip-fp32-correctly-rounded-divide-sqrt``: a few ulp of
+FP32, far below that path's FP32 rounding of the states; double precision is
+unaffected).
 """
 from __future__ import annotations
 
@@ -21,6 +26,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          "-Wall", "-Wno-unused-function"]
 
 
