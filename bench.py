@@ -306,6 +306,7 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--no-variants", action="store_true", help="skip the scheme-variant legs")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--accuracy-steps", type=int, default=200,
@@ -354,8 +355,8 @@ def main(argv=None) -> int:
     nsub = w.rk_order
     P0 = torch.from_numpy(w.P).to(dev)
 
-    def timed_run(precision):
-        s = grmhd.solver_for(w, device=dev, timing=not args.no_timing, precision=precision)
+    def timed_run(precision, **over):
+        s = grmhd.solver_for(w, device=dev, timing=not args.no_timing, precision=precision, **over)
         U = s.cons(P0)
         for _ in range(args.warmup):
             s.step(U, w.dt)
@@ -428,6 +429,13 @@ def main(argv=None) -> int:
     if not args.no_adjoint and fp64:
         # the adjoint workload (64^3 periodic box, 50 RK2 steps, checkpoints every 10)
         out["adjoint"] = adjoint_cost(grmhd, workloads.config4(n=64, nsteps=50), dev, 50, 10)
+    if not args.no_variants and fp64:
+        # scheme variants on the same workload: the recovery's one-unknown iteration
+        v = timed_run("fp64", recovery="1d")
+        out["variants"] = {"recovery_1d": {
+            "value": v["value"], "ms_per_step": v["ms_per_step"], "recovery": v["recovery"],
+            "finite": v["finite"], "update_avg_ms": v["kernels"].get("update", {}).get("avg_ms"),
+            "vs_2d": round(v["value"] / fp64["value"], 3)}}
     if not args.no_batch and fp64:
         # 256 magnetised 1D Riemann problems of 200..4000 cells, each to t = 0.4
         out["batch"] = batch_throughput(grmhd, workloads.config5(), dev)

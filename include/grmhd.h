@@ -103,6 +103,15 @@ typedef struct {
                        when opts.p_atm < 0 */
 } grmhd_eos;
 
+/* Primitive recovery (section 3.2 names a two-unknown and a one-unknown
+ * scheme of Noble et al. 2006).  Both solve the same equations, warm-started
+ * from the previous primitives, with the same acceptance test and the same
+ * bracketed one-unknown fallback; they differ in the Newton iteration. */
+typedef enum {
+    GRMHD_RECOVERY_2D = 0,  /* Newton on (Wc = rho h W^2, v^2) */
+    GRMHD_RECOVERY_1D = 1   /* Newton on Wc alone, v^2(Wc) eliminated */
+} grmhd_recovery;
+
 /* Scheme options and the caller's workspace. */
 typedef struct {
     int rk_order;          /* 2 (SSP-RK2) or 3 (SSP-RK3, the order of section 3.2) */
@@ -113,6 +122,7 @@ typedef struct {
     double p_atm;          /* atmosphere and floor pressure; < 0: K rho_atm^gamma */
     double newton_tol;     /* relative step tolerance of the recovery (1e-12 if 0) */
     int newton_maxit;      /* iteration cap of the recovery (50 if 0) */
+    int recovery;          /* grmhd_recovery: the primitive recovery's Newton iteration */
     int timing;            /* nonzero: time every kernel launch with HIP events */
     int adjoint;           /* nonzero: reserve the workspace of the adjoint calls (FP64 only) */
     int tape_steps;        /* with adjoint: slots of recorded steps (grmhd_step_record), 0..4096 */

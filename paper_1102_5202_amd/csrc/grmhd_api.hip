@@ -616,6 +616,8 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
         return GRMHD_ERR_ARG;
     if (opts->newton_tol < 0.0 || opts->newton_maxit < 0)
         return GRMHD_ERR_ARG;
+    if (opts->recovery != GRMHD_RECOVERY_2D && opts->recovery != GRMHD_RECOVERY_1D)
+        return GRMHD_ERR_ARG;
     if (opts->adjoint && opts->precision != GRMHD_FP64)
         return GRMHD_ERR_ARG;
     if (opts->tape_steps < 0 || opts->tape_steps > 4096)
@@ -665,6 +667,7 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     d.p_atm = opts->p_atm >= 0.0 ? opts->p_atm : eos->K * std::pow(opts->rho_atm, eos->gamma);
     d.tol = opts->newton_tol > 0.0 ? opts->newton_tol : 1e-12;
     d.maxit = opts->newton_maxit > 0 ? opts->newton_maxit : 50;
+    d.c2p1d = opts->recovery == GRMHD_RECOVERY_1D;
 
     c->ws = (unsigned char*)opts->workspace;
     c->cnt = (unsigned long long*)(c->ws + L.off_cnt);

@@ -176,6 +176,8 @@ int grmhd_batch_init(grmhd_batch** out, const grmhd_batch_desc* desc, const grmh
         return GRMHD_ERR_ARG;
     if (opts->newton_tol < 0.0 || opts->newton_maxit < 0)
         return GRMHD_ERR_ARG;
+    if (opts->recovery != GRMHD_RECOVERY_2D && opts->recovery != GRMHD_RECOVERY_1D)
+        return GRMHD_ERR_ARG;
     const size_t es = esize_of(opts);
     BatchLayout L = batch_layout(desc, es);
     if (!opts->workspace || opts->workspace_bytes < L.total || ((uintptr_t)opts->workspace) % 256 != 0)
@@ -206,6 +208,7 @@ int grmhd_batch_init(grmhd_batch** out, const grmhd_batch_desc* desc, const grmh
     d.p_atm = opts->p_atm >= 0.0 ? opts->p_atm : eos->K * std::pow(opts->rho_atm, eos->gamma);
     d.tol = opts->newton_tol > 0.0 ? opts->newton_tol : 1e-12;
     d.maxit = opts->newton_maxit > 0 ? opts->newton_maxit : 50;
+    d.c2p1d = opts->recovery == GRMHD_RECOVERY_1D;
     b->probs.resize(b->nprob);
     long long off = 0, poff = 0;
     for (int i = 0; i < b->nprob; ++i) {

@@ -31,6 +31,7 @@ struct Dev {
     double c_h, ic_h, c_h2, kappa;
     double rho_atm, p_atm, tol;
     int maxit;
+    int c2p1d;       // recovery: 0 Newton on (Wc, v^2), 1 Newton on Wc alone
 };
 
 // Geometry at one point.
@@ -416,6 +417,48 @@ __device__ __forceinline__ double c2p_f1d(const C2P& c, double gk, double Wc, do
     return -0.5 * c.Bc2 * (1.0 + v2) + 0.5 * c.QB2 * iW * iW - Wc + p - c.Qn;
 }
 
+// Recovery with one unknown: v^2(Wc) eliminated through the momentum
+// equation, Newton on the energy equation's residual in Wc, warm-started from
+// the guess's Wc.  Accepted as the 2D iteration is: the relative step below
+// tol, then one more step, with v^2 in [0, 1) and the residual below 1e-10
+// of its scale.
+__device__ __forceinline__ bool c2p_newton1d(const C2P& c, double gk, double tol, int maxit, double& Wc,
+                                             double& v2, int& iters)
+{
+    int extra = -1;
+    for (int it = 0; it < maxit; ++it) {
+        iters = it + 1;
+        double dv2;
+        c2p_v2(c, Wc, v2, dv2);
+        if (!(v2 >= 0.0 && v2 < 1.0))
+            return false;
+        double df;
+        const double f = c2p_f1d(c, gk, Wc, df);
+        double Wn = Wc - f / df;
+        if (!(Wn > 0.0))
+            Wn = 0.5 * Wc;
+        const double step = fabs(Wn - Wc);
+        Wc = Wn;
+        if (!finite(Wc))
+            return false;
+        if (extra == 0)
+            break;
+        if (step <= tol * Wc)
+            extra = 0;   // converged: one more step puts the error at round-off
+    }
+    if (extra != 0 || !(Wc > 0.0))
+        return false;
+    double dv2;
+    c2p_v2(c, Wc, v2, dv2);
+    if (!(v2 >= 0.0 && v2 < 1.0))
+        return false;
+    double df;
+    const double f = c2p_f1d(c, gk, Wc, df);
+    const double p = gk * (Wc * (1.0 - v2) - c.D * sqrt(1.0 - v2));
+    const double sc = c.Bc2 + Wc + fabs(p) + fabs(c.Qn) + 0.5 * c.QB2 / (Wc * Wc);
+    return fabs(f) <= 1e-10 * sc;
+}
+
 // Bracketed solve in Wc alone (v^2 eliminated): used when the 2D iteration
 // is not accepted.  The bracket starts at the smallest Wc with v^2 < 1 (v^2
 // falls with Wc; f falls with Wc), searched above D when v^2(D) >= 1 and
@@ -561,7 +604,8 @@ __device__ __forceinline__ int recover_cell(const Dev& d, const Geo& g, double* 
         Wc = (qg[0] + d.gfac * qg[1]) * Wg2;
         v2 = uu / Wg2;
         bool guess_ok = finite(Wc) && Wc > 0.0 && finite(v2);
-        bool conv = guess_ok && c2p_newton2d(c, d.gk, d.tol, d.maxit, Wc, v2, iters);
+        bool conv = guess_ok && (d.c2p1d ? c2p_newton1d(c, d.gk, d.tol, d.maxit, Wc, v2, iters)
+                                         : c2p_newton2d(c, d.gk, d.tol, d.maxit, Wc, v2, iters));
         if (!conv) {
             flags |= FLAG_FALLBACK;
             WV r = c2p_bracketed(c.D, c.Qn, c.Qt2, c.Bc2, c.QB2, d.gk);

@@ -67,13 +67,15 @@ def test_workspace_and_init_validation(lib):
             assert L.grmhd_free(ctx) == 0
         return rc
 
-    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)
+    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)
     assert init(ok) == 0
-    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb - 8)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr + 8), nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, None, nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb - 8)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr + 8), nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, None, nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 2, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 1, 0, 0, 0, C.c_void_p(addr), nb)) == 0
     assert init(ok, eos=lib.Eos(0, 2.5, 0.0)) == -1
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 0.4)) == -1   # r_min <= M/2
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 1.0)) == 0
@@ -123,7 +125,7 @@ def test_adjoint_workspace(lib):
     raw, addr = _host_ws(adj)
     m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 1, 0, C.c_void_p(addr), adj)
+    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 1, 0, C.c_void_p(addr), adj)
     ctx = C.c_void_p()
     assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
     o.precision = 0
@@ -193,7 +195,7 @@ def test_batch_workspace_and_init_validation(lib):
     o.precision = 0
     raw, addr = _host_ws(nb)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, C.c_void_p(addr), nb)
+    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)
     ctx = C.c_void_p()
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == 0
     assert L.grmhd_batch_evolve(ctx, C.c_void_p(addr), 5) == -4      # before cons

@@ -68,14 +68,16 @@ def test_cons_matches_oracle(G, orc):
     assert np.all(err <= 1e-14)
 
 
-def test_prim_matches_oracle_from_perturbed_guess(G, orc):
-    """Newton from a guess 5% away, flat and curved, magnetised states."""
+@pytest.mark.parametrize("recovery", ["2d", "1d"])
+def test_prim_matches_oracle_from_perturbed_guess(G, orc, recovery):
+    """Newton from a guess 5% away, flat and curved, magnetised states, with
+    the two-unknown and the one-unknown iteration."""
     for w in (WL.config2(n=24, k=3), WL.config3(n=(26, 22, 20))):
         pb = orc.Problem(**w.problem_kwargs())
         rng = np.random.default_rng(0)
         Pg = w.P * (1.0 + 0.05 * rng.uniform(-1, 1, w.P.shape))
         Ut = orc.prim2con(pb, w.P)
-        s = G.solver_for(w, device=DEV)
+        s = G.solver_for(w, device=DEV, recovery=recovery)
         s.cons(torch.from_numpy(Pg).to(DEV))          # loads the guess into the cache
         P = s.prim(torch.from_numpy(Ut).to(DEV)).cpu().numpy()
         st = s.status()
@@ -144,6 +146,22 @@ def test_curved_blob(G, orc):
     err = rel_l1(U, Ur)
     say("curved blob rel-L1", err, st, sto)
     assert np.all(err <= 1e-10)
+
+
+@pytest.mark.parametrize("case", ["riemann0", "riemann5", "periodic", "curved"])
+def test_one_unknown_recovery_matches_oracle(G, orc, case):
+    """The same runs with the recovery's one-unknown Newton iteration (Wc
+    alone, v^2 eliminated) in place of the two-unknown one: the same root, so
+    the same parity bar."""
+    w, nsteps = {"riemann0": (WL.config1(0), 400), "riemann5": (WL.config1(5), 400),
+                 "periodic": (WL.config2(n=(33, 30, 28), nsteps=30), 30),
+                 "curved": (WL.config3(n=(40, 36, 34), nsteps=20), 20)}[case]
+    U, P, st, _ = gpu_run(G, w, nsteps, recovery="1d")
+    Ur, Pr, sto, _ = oracle_run(orc, w, nsteps)
+    err = rel_l1(U, Ur)
+    say(case, "1d recovery rel-L1", err[:8].max(), st, sto)
+    assert np.all(err[:8] <= 1e-10)
+    assert st["fail"] == sto["fail"]
 
 
 def test_curved_blob_full_size_sampled(G, orc):
