@@ -23,6 +23,7 @@ FLAT, ISO_SCHW = 0, 1
 SOFT_SQRT, SOFT_MAX = 0, 1
 PERIODIC, OUTFLOW = 0, 1
 FLAG_FAIL, FLAG_ATM, FLAG_PFLOOR = 1, 2, 4
+RECON_MC, RECON_PPM = 0, 1
 
 
 class _Metric(C.Structure):
@@ -37,7 +38,7 @@ class _Grid(C.Structure):
 class _Problem(C.Structure):
     _fields_ = [("metric", _Metric), ("grid", _Grid), ("gamma", C.c_double),
                 ("rk_order", C.c_int), ("c_h", C.c_double), ("kappa", C.c_double),
-                ("rho_atm", C.c_double), ("p_atm", C.c_double)]
+                ("rho_atm", C.c_double), ("p_atm", C.c_double), ("recon", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -79,6 +80,8 @@ def lib():
                                           C.c_double, C.c_double, C.c_double, dp, dp, dp]
         L.orc_mc_slope.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_mc_slope.restype = C.c_double
+        L.orc_ppm_edges.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_ppm_edges.restype = None
         _lib = L
     return _lib
 
@@ -113,6 +116,7 @@ class Problem:
     kappa: float = 1.0
     rho_atm: float = 1e-12
     p_atm: float = 1e-12
+    recon: int = RECON_MC
     _c: _Problem = field(default=None, init=False, repr=False)
 
     def c(self) -> _Problem:
@@ -132,6 +136,7 @@ class Problem:
         p.kappa = self.kappa
         p.rho_atm = self.rho_atm
         p.p_atm = self.p_atm
+        p.recon = int(self.recon)
         return p
 
     @property
@@ -255,6 +260,15 @@ def point_face_flux(qL, qR, gamma, dir, c_h=1.0, x=0.0, y=0.0, z=0.0, **mk):
     lib().orc_point_face_flux(C.byref(_m(**mk)), gamma, c_h, dir, x, y, z, _ptr(qL), _ptr(qR),
                               _ptr(F))
     return F
+
+
+def ppm_edges(a) -> tuple:
+    """PPM edge values (left, right) of the middle cell of five cell values."""
+    a = _arr(a)
+    assert a.shape == (5,)
+    l, r = C.c_double(), C.c_double()
+    lib().orc_ppm_edges(_ptr(a), C.byref(l), C.byref(r))
+    return l.value, r.value
 
 
 def mc_slope(qm, q0, qp) -> float:

@@ -586,6 +586,41 @@ double orc_mc_slope(double qm, double q0, double qp)
     return minmod3(2.0 * (q0 - qm), 0.5 * (qp - qm), 2.0 * (qp - q0));
 }
 
+/* PPM (the piecewise parabolic method of Colella & Woodward 1984; section 3.2
+ * offers it beside MC) on cell i from the cells a[0..4] = i-2..i+2:
+ * 1. the value at each of the cell's two interfaces is interpolated from the
+ *    four nearest cells as the mean of its two neighbours minus one sixth of
+ *    the difference of their MC-limited slopes (the fourth-order interface
+ *    value of cell averages while the limiter is inactive);
+ * 2. the parabola through the cell mean and these two edge values is then
+ *    constrained to be monotone: at a local extremum of the cell means the
+ *    reconstruction is flat (both edges = the mean); if the parabola would
+ *    peak inside the cell, the edge nearer the peak is moved so that the
+ *    extremum falls on the opposite edge (the edge becomes 3 a_i - 2 a_other).
+ * No contact steepening and no shock flattening.                            */
+void orc_ppm_edges(const double *a, double *aL, double *aR)
+{
+    double sm = orc_mc_slope(a[0], a[1], a[2]);   /* slope of cell i-1 */
+    double s0 = orc_mc_slope(a[1], a[2], a[3]);   /* slope of cell i   */
+    double sp = orc_mc_slope(a[2], a[3], a[4]);   /* slope of cell i+1 */
+    double l = 0.5 * (a[1] + a[2]) - (s0 - sm) / 6.0;
+    double r = 0.5 * (a[2] + a[3]) - (sp - s0) / 6.0;
+    double q = a[2];
+    if ((r - q) * (q - l) <= 0.0) {
+        l = q;
+        r = q;
+    } else {
+        double dlr = r - l;
+        double m6 = 6.0 * (q - 0.5 * (l + r));
+        if (dlr * m6 > dlr * dlr)
+            l = 3.0 * q - 2.0 * r;
+        else if (-dlr * dlr > dlr * m6)
+            r = 3.0 * q - 2.0 * l;
+    }
+    *aL = l;
+    *aR = r;
+}
+
 /* HLLE flux (Harten, Lax, van Leer, Einfeldt) at one face from the left and
  * right reconstructed primitives.  The normal field and Phi form a linear
  * 2x2 system that is solved exactly first; its state fixes the normal field
@@ -775,17 +810,32 @@ int orc_rhs(const orc_problem *pb, const double *P, double *R)
             for (j = 0; j < nf[1]; j++)
                 for (i = 0; i < nf[0]; i++) {
                     int fi[3] = {i, j, k};
-                    double q[4][9], qL[9], qR[9], F[9], pos[3];
+                    double q[6][9], qL[9], qR[9], F[9], pos[3];
                     geom G;
                     long long fc = ((long long)k * nf[1] + j) * nf[0] + i;
-                    for (s = 0; s < 4; s++) {
+                    /* cells f-3 .. f+2 along d (boundary rule by index mapping) */
+                    for (s = 0; s < 6; s++) {
                         int ci[3] = {i, j, k};
-                        ci[d] = bc_map(fi[d] - 2 + s, g->n[d], g->bc[d]);
+                        ci[d] = bc_map(fi[d] - 3 + s, g->n[d], g->bc[d]);
                         load_prim(g, P, ci[0], ci[1], ci[2], q[s]);
                     }
                     for (v = 0; v < 9; v++) {
-                        qL[v] = q[1][v] + 0.5 * orc_mc_slope(q[0][v], q[1][v], q[2][v]);
-                        qR[v] = q[2][v] - 0.5 * orc_mc_slope(q[1][v], q[2][v], q[3][v]);
+                        if (pb->recon == ORC_RECON_PPM) {
+                            /* left state: right edge of cell f-1; right state:
+                             * left edge of cell f */
+                            double a[5], e0, e1;
+                            for (s = 0; s < 5; s++)
+                                a[s] = q[s][v];
+                            orc_ppm_edges(a, &e0, &qL[v]);
+                            for (s = 0; s < 5; s++)
+                                a[s] = q[s + 1][v];
+                            orc_ppm_edges(a, &qR[v], &e1);
+                            (void)e0;
+                            (void)e1;
+                        } else {
+                            qL[v] = q[2][v] + 0.5 * orc_mc_slope(q[1][v], q[2][v], q[3][v]);
+                            qR[v] = q[3][v] - 0.5 * orc_mc_slope(q[2][v], q[3][v], q[4][v]);
+                        }
                     }
                     for (s = 0; s < 3; s++)
                         pos[s] = (s == d) ? g->lo[s] + fi[s] * dx : centre(g, s, fi[s]);

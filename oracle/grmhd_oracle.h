@@ -12,7 +12,8 @@
  * choices of section 3.2): the finite-volume update of the conserved variables
  *   U = ( sqrt(-g) rho u^t,  -sqrt(-g)(T^t_t + rho u^t),  sqrt(-g) T^t_j,
  *         sqrt(-g) B^j,  Phi )
- * in a fixed static metric, with MC-limited TVD reconstruction of the
+ * in a fixed static metric, with MC-limited TVD reconstruction (or, as the
+ * alternative section 3.2 names, PPM) of the
  * primitives P = (rho, p, u~^x, u~^y, u~^z, B^x, B^y, B^z, Phi), HLLE face
  * fluxes, metric source terms, a bracketed Newton recovery of P from U, and
  * an SSP Runge-Kutta update.  Divergence violations are damped with a
@@ -33,6 +34,7 @@ extern "C" {
 enum { ORC_FLAT = 0, ORC_ISO_SCHW = 1 };
 enum { ORC_SOFT_SQRT = 0, ORC_SOFT_MAX = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
+enum { ORC_RECON_MC = 0, ORC_RECON_PPM = 1 };
 
 /* cell flags produced by the recovery + floor policy */
 enum { ORC_FLAG_FAIL = 1, ORC_FLAG_ATM = 2, ORC_FLAG_PFLOOR = 4 };
@@ -60,6 +62,7 @@ typedef struct {
     double kappa;   /* cleaning damping rate                             */
     double rho_atm; /* atmosphere density                                */
     double p_atm;   /* atmosphere / floor pressure                       */
+    int recon;      /* ORC_RECON_MC or ORC_RECON_PPM                     */
 } orc_problem;
 
 typedef struct {
@@ -101,6 +104,7 @@ void orc_point_face_flux(const orc_metric *m, double gamma, double c_h, int dir,
                          double x, double y, double z, const double *qL,
                          const double *qR, double *F);
 double orc_mc_slope(double qm, double q0, double qp);
+void orc_ppm_edges(const double *a /* cells i-2..i+2 */, double *aL, double *aR);
 
 #ifdef __cplusplus
 }
