@@ -430,12 +430,15 @@ def main(argv=None) -> int:
         # the adjoint workload (64^3 periodic box, 50 RK2 steps, checkpoints every 10)
         out["adjoint"] = adjoint_cost(grmhd, workloads.config4(n=64, nsteps=50), dev, 50, 10)
     if not args.no_variants and fp64:
-        # scheme variants on the same workload: the recovery's one-unknown iteration
-        v = timed_run("fp64", recovery="1d")
-        out["variants"] = {"recovery_1d": {
-            "value": v["value"], "ms_per_step": v["ms_per_step"], "recovery": v["recovery"],
-            "finite": v["finite"], "update_avg_ms": v["kernels"].get("update", {}).get("avg_ms"),
-            "vs_2d": round(v["value"] / fp64["value"], 3)}}
+        # scheme variants on the same workload: the recovery's one-unknown
+        # iteration; PPM reconstruction (three face kernels + the cell update)
+        out["variants"] = {}
+        for name, over in (("recovery_1d", {"recovery": "1d"}), ("ppm", {"reconstruction": "ppm"})):
+            v = timed_run("fp64", **over)
+            out["variants"][name] = {
+                "value": v["value"], "ms_per_step": v["ms_per_step"], "recovery": v["recovery"],
+                "finite": v["finite"], "kernels_avg_ms": {k: x["avg_ms"] for k, x in v["kernels"].items()},
+                "vs_default": round(v["value"] / fp64["value"], 3)}
     if not args.no_batch and fp64:
         # 256 magnetised 1D Riemann problems of 200..4000 cells, each to t = 0.4
         out["batch"] = batch_throughput(grmhd, workloads.config5(), dev)

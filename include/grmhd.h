@@ -112,6 +112,18 @@ typedef enum {
     GRMHD_RECOVERY_1D = 1   /* Newton on Wc alone, v^2(Wc) eliminated */
 } grmhd_recovery;
 
+/* Reconstruction of the primitives at the faces (section 3.2 offers TVD with
+ * the MC limiter and PPM).  PPM here is Colella & Woodward's interface
+ * interpolation with MC-limited slopes and their monotonicity constraints
+ * (no contact steepening, no flattening); it needs 3 cells on every active
+ * axis, has no adjoint and no batched form, and 3D grids with it run the
+ * face kernels of all three axes followed by the cell update (the fused
+ * z-face + update kernel is MC only). */
+typedef enum {
+    GRMHD_RECON_MC = 0,
+    GRMHD_RECON_PPM = 1
+} grmhd_reconstruction;
+
 /* Scheme options and the caller's workspace. */
 typedef struct {
     int rk_order;          /* 2 (SSP-RK2) or 3 (SSP-RK3, the order of section 3.2) */
@@ -123,6 +135,7 @@ typedef struct {
     double newton_tol;     /* relative step tolerance of the recovery (1e-12 if 0) */
     int newton_maxit;      /* iteration cap of the recovery (50 if 0) */
     int recovery;          /* grmhd_recovery: the primitive recovery's Newton iteration */
+    int reconstruction;    /* grmhd_reconstruction: MC (2 ghost layers) or PPM (3) */
     int timing;            /* nonzero: time every kernel launch with HIP events */
     int adjoint;           /* nonzero: reserve the workspace of the adjoint calls (FP64 only) */
     int tape_steps;        /* with adjoint: slots of recorded steps (grmhd_step_record), 0..4096 */

@@ -59,11 +59,12 @@ bool grid_ok(const grmhd_grid* g)
     return true;
 }
 
-Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int ns = 3, int tape = 0)
+Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int ns = 3, int tape = 0,
+                   int ghost = 2)
 {
     Layout L{};
     for (int d = 0; d < 3; ++d)
-        L.g[d] = g->n[d] > 1 ? 2 : 0;
+        L.g[d] = g->n[d] > 1 ? ghost : 0;
     // x pitch rounded to 8 doubles (64 bytes) so rows start aligned
     L.px = (int)round_up((size_t)(g->n[0] + 2 * L.g[0]), 8);
     L.py = g->n[1] + 2 * L.g[1];
@@ -129,6 +130,30 @@ Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int 
 bool wants_adjoint(const grmhd_opts* o)
 {
     return o && o->adjoint && o->precision == GRMHD_FP64;
+}
+
+// Ghost layers of the reconstruction: MC reads 2 cells beside a face, PPM 3.
+int ghost_width(const grmhd_opts* o)
+{
+    return o && o->reconstruction == GRMHD_RECON_PPM ? 3 : 2;
+}
+
+// Options that fit the grid: PPM needs 3 cells on every active axis (the
+// periodic images of the ghost layers) and has no adjoint.
+bool opts_fit(const grmhd_grid* g, const grmhd_opts* o)
+{
+    if (!o)
+        return true;   // defaults: MC
+    if (o->reconstruction != GRMHD_RECON_MC && o->reconstruction != GRMHD_RECON_PPM)
+        return false;
+    if (o->reconstruction == GRMHD_RECON_PPM) {
+        if (o->adjoint)
+            return false;
+        for (int d = 0; d < 3; ++d)
+            if (g->n[d] > 1 && g->n[d] < 3)
+                return false;
+    }
+    return true;
 }
 
 int tape_slots(const grmhd_opts* o)
@@ -355,12 +380,13 @@ int step_t(grmhd_ctx* c, double* U, double dt)
     const int ns = c->rk_order;
     const double* A = ns == 3 ? RK3A : RK2A;
     const double* B = ns == 3 ? RK3B : RK2B;
-    // 3D grids: the z faces are computed inside the fused update kernel, which
-    // writes the new primitives to another cache; otherwise the update works
-    // in place on the cache with all face fluxes precomputed.  The first stage
+    // 3D grids with MC: the z faces are computed inside the fused update
+    // kernel, which writes the new primitives to another cache; otherwise (1D,
+    // 2D, PPM) the update works in place on the cache with all face fluxes
+    // precomputed.  The first stage
     // reads U^n as its stage state; the intermediate stage state has the cache
     // type (float in the mixed path); the last stage writes U.
-    const bool zmarch = c->d.act[2] != 0;
+    const bool zmarch = c->d.act[2] && !c->d.ppm;
     T* Us = (T*)c->Us;
     for (int s = 0; s < ns; ++s) {
         const int src = zmarch ? s : 0;
@@ -410,7 +436,7 @@ int adj_prepare(grmhd_ctx* c)
 int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, const double* B)
 {
     const int ns = c->rk_order;
-    const bool zmarch = c->d.act[2] != 0;
+    const bool zmarch = c->d.act[2] && !c->d.ppm;
     int rc = timed(c, GRMHD_K_PRIM, [&] {
         return grmhd::launch_prim(c->kind, U, c->Pb, c->Ac[0], c->d, c->cnt, c->stream);
     });
@@ -521,7 +547,7 @@ int step_record(grmhd_ctx* c, double* U, double dt, int slot)
     const int ns = c->rk_order;
     const double* A = ns == 3 ? RK3A : RK2A;
     const double* B = ns == 3 ? RK3B : RK2B;
-    const bool zmarch = c->d.act[2] != 0;
+    const bool zmarch = c->d.act[2] && !c->d.ppm;
     const size_t bytes = sizeof(double) * 9 * (size_t)c->L.sv;
     int rc = GRMHD_OK;
     if (!c->ghosts_ok[0]) {
@@ -587,7 +613,9 @@ size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_opts* opts)
     if (!grid_ok(grid))
         return 0;
     const int ns = opts && opts->rk_order == 2 ? 2 : 3;
-    return make_layout(grid, elem_size(opts), wants_adjoint(opts), ns, tape_slots(opts)).total;
+    if (!opts_fit(grid, opts))
+        return 0;
+    return make_layout(grid, elem_size(opts), wants_adjoint(opts), ns, tape_slots(opts), ghost_width(opts)).total;
 }
 
 int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
@@ -622,7 +650,10 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
         return GRMHD_ERR_ARG;
     if (opts->tape_steps < 0 || opts->tape_steps > 4096)
         return GRMHD_ERR_ARG;
-    Layout L = make_layout(grid, elem_size(opts), wants_adjoint(opts), opts->rk_order, tape_slots(opts));
+    if (!opts_fit(grid, opts))
+        return GRMHD_ERR_ARG;
+    Layout L = make_layout(grid, elem_size(opts), wants_adjoint(opts), opts->rk_order, tape_slots(opts),
+                           ghost_width(opts));
     if (!opts->workspace || opts->workspace_bytes < L.total)
         return GRMHD_ERR_WORKSPACE;
     if (((uintptr_t)opts->workspace) % 256 != 0)
@@ -668,6 +699,7 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     d.tol = opts->newton_tol > 0.0 ? opts->newton_tol : 1e-12;
     d.maxit = opts->newton_maxit > 0 ? opts->newton_maxit : 50;
     d.c2p1d = opts->recovery == GRMHD_RECOVERY_1D;
+    d.ppm = opts->reconstruction == GRMHD_RECON_PPM;
 
     c->ws = (unsigned char*)opts->workspace;
     c->cnt = (unsigned long long*)(c->ws + L.off_cnt);

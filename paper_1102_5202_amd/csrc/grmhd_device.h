@@ -15,7 +15,7 @@ enum { FLAT = 0, ISO = 1 };
 // Per-launch constants (passed by value as a kernel argument).
 struct Dev {
     int n[3];        // interior cells
-    int g[3];        // ghost width per axis (2 on active axes, 0 otherwise)
+    int g[3];        // ghost width per axis (2, or 3 with PPM, on active axes; 0 otherwise)
     int act[3];      // axis active (n > 1)
     int bc[3];       // 0 periodic, 1 outflow
     int px, py, pz;  // dimensions of the ghosted primitive cache (px is the pitch)
@@ -32,6 +32,7 @@ struct Dev {
     double rho_atm, p_atm, tol;
     int maxit;
     int c2p1d;       // recovery: 0 Newton on (Wc, v^2), 1 Newton on Wc alone
+    int ppm;         // reconstruction: 0 MC (2 ghosts), 1 PPM (3 ghosts)
 };
 
 // Geometry at one point.
@@ -232,6 +233,31 @@ __device__ __forceinline__ T mc_slope(T qm, T q0, T qp)
     return (dl * dr > T(0)) ? copysign(s, dc) : T(0);
 }
 
+// PPM edge values (Colella & Woodward's piecewise parabolic method, the
+// alternative reconstruction of section 3.2) of the middle cell of a0..a4:
+// interface values from the four nearest cells with MC-limited slopes, then
+// the monotonicity constraints (flat at a local extremum; an edge moved to
+// 3 q - 2 other where the parabola would peak inside the cell).
+template <typename T>
+__device__ __forceinline__ void ppm_edges(T a0, T a1, T a2, T a3, T a4, T& aL, T& aR)
+{
+    const T sm = mc_slope(a0, a1, a2), s0 = mc_slope(a1, a2, a3), sp = mc_slope(a2, a3, a4);
+    T l = T(0.5) * (a1 + a2) - (s0 - sm) / T(6);
+    T r = T(0.5) * (a2 + a3) - (sp - s0) / T(6);
+    if ((r - a2) * (a2 - l) <= T(0)) {
+        l = a2;
+        r = a2;
+    } else {
+        const T dlr = r - l, m6 = T(6) * (a2 - T(0.5) * (l + r));
+        if (dlr * m6 > dlr * dlr)
+            l = T(3) * a2 - T(2) * r;
+        else if (-dlr * dlr > dlr * m6)
+            r = T(3) * a2 - T(2) * l;
+    }
+    aL = l;
+    aR = r;
+}
+
 // A class test, not arithmetic: with FMA contraction "x - x" may be evaluated
 // as fma(a, b, -x) for x = a*b, which is the rounding error of the product.
 __device__ __forceinline__ bool finite(double x)
@@ -338,9 +364,11 @@ __device__ __forceinline__ double c2p_press(const C2P& c, double gk, double Wc, 
 }
 
 // Newton-Raphson on the two residuals, warm-started.  Converged when the
-// relative step in Wc falls below tol, after one more step; the final point
-// must then satisfy both equations to 1e-10 of their scales with v^2 inside
-// (0, 1) unclamped.  Returns true on acceptance; iters counts the iterations.
+// relative step in Wc falls below tol, after one more step (which takes the
+// iterate to its rounding limit, so that the root does not depend on the
+// guess in its last bits); the final point must then satisfy both equations
+// to 1e-10 of their scales with v^2 inside (0, 1) unclamped.  Returns true
+// on acceptance; iters counts the iterations.
 __device__ __forceinline__ bool c2p_newton2d(const C2P& c, double gk, double tol, int maxit,
                                              double& Wc, double& v2, int& iters)
 {
@@ -362,9 +390,9 @@ __device__ __forceinline__ bool c2p_newton2d(const C2P& c, double gk, double tol
         double a12 = bw * bw;
         double a21 = -c.QB2 * iW2 * iW - 1.0 + gk * (1.0 - v2);
         double a22 = -0.5 * c.Bc2 + gk * (-Wc + 0.5 * c.D / s);
-        double det = a11 * a22 - a12 * a21;
-        double dW = (r1 * a22 - a12 * r2) / det;
-        double dv = (a11 * r2 - a21 * r1) / det;
+        double idet = 1.0 / (a11 * a22 - a12 * a21);
+        double dW = (r1 * a22 - a12 * r2) * idet;
+        double dv = (a11 * r2 - a21 * r1) * idet;
         double Wn = Wc - dW;
         double vn = v2 - dv;
         if (!(Wn > 0.0))
@@ -379,7 +407,7 @@ __device__ __forceinline__ bool c2p_newton2d(const C2P& c, double gk, double tol
         if (extra == 0)
             break;
         if (step <= tol * Wc)
-            extra = 0;   // converged: one more step puts the error at round-off
+            extra = 0;   // converged: one more step takes the iterate to its rounding limit
     }
     if (extra != 0 || clamped || !(Wc > 0.0))
         return false;
@@ -444,7 +472,7 @@ __device__ __forceinline__ bool c2p_newton1d(const C2P& c, double gk, double tol
         if (extra == 0)
             break;
         if (step <= tol * Wc)
-            extra = 0;   // converged: one more step puts the error at round-off
+            extra = 0;   // converged: one more step takes the iterate to its rounding limit
     }
     if (extra != 0 || !(Wc > 0.0))
         return false;

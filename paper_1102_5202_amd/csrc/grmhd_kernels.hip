@@ -89,6 +89,11 @@ __global__ __launch_bounds__(BLOCK) void k_ghosts(T* __restrict__ Pc, Dev d, lon
         Pc[v * d.sv + dst] = Pc[v * d.sv + sp];
 }
 
+__device__ __forceinline__ long long cache_index(const Dev& d, int i, int j, int k)
+{
+    return ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + (i + d.g[0]);
+}
+
 template <int D, int KIND, typename T>
 __device__ __forceinline__ void face_store(T* qL, T* qR, double x, double y, double z, const Dev& d,
                                            T* __restrict__ F, long long NF, long long f)
@@ -195,6 +200,43 @@ __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, 
     }
 }
 
+// Faces along D with PPM reconstruction: one thread per face, the six cells
+// f-3 .. f+2 along D; the left state is the right edge of cell f-1, the
+// right state the left edge of cell f.  Needs 3 ghost layers.
+template <int D, int KIND, typename T>
+__global__ __launch_bounds__(BLOCK) void k_flux_ppm(const T* __restrict__ Pc, T* __restrict__ F, Dev d)
+{
+    const long long NF = d.nf[D];
+    const long long f = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (f >= NF)
+        return;
+    int m[3] = {d.n[0], d.n[1], d.n[2]};
+    m[D] += 1;
+    int fi[3];
+    fi[0] = (int)(f % m[0]);
+    const long long t = f / m[0];
+    fi[1] = (int)(t % m[1]);
+    fi[2] = (int)(t / m[1]);
+    int ci[3] = {fi[0], fi[1], fi[2]};
+    ci[D] -= 3;
+    const long long base = cache_index(d, ci[0], ci[1], ci[2]);
+    const long long st = D == 0 ? 1 : (D == 1 ? (long long)d.px : (long long)d.px * d.py);
+    T qL[9], qR[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        const T* p = Pc + v * d.sv + base;
+        const T a0 = p[0], a1 = p[st], a2 = p[2 * st], a3 = p[3 * st], a4 = p[4 * st], a5 = p[5 * st];
+        T e;
+        ppm_edges(a0, a1, a2, a3, a4, e, qL[v]);
+        ppm_edges(a1, a2, a3, a4, a5, qR[v], e);
+    }
+    double pos[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        pos[e] = e == D ? d.lo[e] + fi[e] * d.dx[e] : d.lo[e] + (fi[e] + 0.5) * d.dx[e];
+    face_store<D, KIND>(qL, qR, pos[0], pos[1], pos[2], d, F, NF, f);
+}
+
 // Flux differences + sources for cell c (i,j,k); q are its primitives.
 template <int KIND, typename T>
 __device__ __forceinline__ void rhs_cell(const Dev& d, const T* __restrict__ Fx, const T* __restrict__ Fy,
@@ -224,11 +266,6 @@ __device__ __forceinline__ void rhs_cell(const Dev& d, const T* __restrict__ Fx,
     }
     add_sources<KIND>(d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
                       d.lo[2] + (k + 0.5) * d.dx[2], q, g, R);
-}
-
-__device__ __forceinline__ long long cache_index(const Dev& d, int i, int j, int k)
-{
-    return ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + (i + d.g[0]);
 }
 
 // Per-thread counts reduced over the wave, one atomic per wave and counter
@@ -274,7 +311,7 @@ __device__ __forceinline__ void tally(int flags, int iters, int& nf, int& na, in
 // ghosts: every stencil is 1D).  Periodic: the cell is the image of ghost
 // idx + n when idx < g and of ghost idx - n when idx >= n - g.  Outflow
 // (zero gradient): the first and last cells fill both ghost layers beside
-// them.  Active axes have n >= 2 = g, so these are all the images.
+// them.  Active axes have n >= g, so these are all the images.
 template <typename T>
 __device__ __forceinline__ void store_prim(const Dev& d, T* __restrict__ P, long long pc, int i, int j,
                                            int k, const double* p)
@@ -288,26 +325,25 @@ __device__ __forceinline__ void store_prim(const Dev& d, T* __restrict__ P, long
     for (int a = 0; a < 3; ++a) {
         if (!d.act[a])
             continue;
-        const int n = d.n[a];
+        const int n = d.n[a], g = d.g[a];
         const long long st = stride[a];
         if (d.bc[a] == 0) {
-            if (idx[a] < 2) {
+            if (idx[a] < g) {
 #pragma unroll
                 for (int v = 0; v < 9; ++v)
                     P[v * d.sv + pc + n * st] = (T)p[v];
             }
-            if (idx[a] >= n - 2) {
+            if (idx[a] >= n - g) {
 #pragma unroll
                 for (int v = 0; v < 9; ++v)
                     P[v * d.sv + pc - n * st] = (T)p[v];
             }
         } else if (idx[a] == 0 || idx[a] == n - 1) {
             const long long s1 = idx[a] == 0 ? -st : st;
+            for (int e = 1; e <= g; ++e)
 #pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                P[v * d.sv + pc + s1] = (T)p[v];
-                P[v * d.sv + pc + 2 * s1] = (T)p[v];
-            }
+                for (int v = 0; v < 9; ++v)
+                    P[v * d.sv + pc + e * s1] = (T)p[v];
         }
     }
 }
@@ -840,6 +876,16 @@ hipError_t launch_ghosts(T* Pc, const Dev& d, hipStream_t s)
 template <int KIND, typename T>
 static hipError_t launch_flux_k(int dir, const T* Pc, T* F, const Dev& d, hipStream_t s)
 {
+    if (d.ppm) {
+        const unsigned nb = blocks_for(d.nf[dir]);
+        if (dir == 0)
+            hipLaunchKernelGGL((k_flux_ppm<0, KIND, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+        else if (dir == 1)
+            hipLaunchKernelGGL((k_flux_ppm<1, KIND, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+        else
+            hipLaunchKernelGGL((k_flux_ppm<2, KIND, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+        return hipGetLastError();
+    }
     if (dir == 0) {
         hipLaunchKernelGGL((k_flux_x<KIND, T>), dim3(blocks_for(d.nf[0])), dim3(BLOCK), 0, s, Pc, F, d);
     } else {

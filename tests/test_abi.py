@@ -67,15 +67,15 @@ def test_workspace_and_init_validation(lib):
             assert L.grmhd_free(ctx) == 0
         return rc
 
-    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)
+    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)
     assert init(ok) == 0
-    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb - 8)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr + 8), nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, None, nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 2, 0, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 1, 0, 0, 0, C.c_void_p(addr), nb)) == 0
+    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb - 8)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr + 8), nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, None, nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 2, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 1, 0, 0, 0, 0, C.c_void_p(addr), nb)) == 0
     assert init(ok, eos=lib.Eos(0, 2.5, 0.0)) == -1
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 0.4)) == -1   # r_min <= M/2
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 1.0)) == 0
@@ -125,7 +125,7 @@ def test_adjoint_workspace(lib):
     raw, addr = _host_ws(adj)
     m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 1, 0, C.c_void_p(addr), adj)
+    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 1, 0, C.c_void_p(addr), adj)
     ctx = C.c_void_p()
     assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
     o.precision = 0
@@ -176,6 +176,39 @@ def test_tape_workspace_and_validation(lib):
     assert L.grmhd_free(ctx) == 0
 
 
+def test_ppm_layout_and_validation(lib):
+    """PPM widens the ghost layers of the primitive caches from 2 to 3, needs
+    3 cells on every active axis and has no adjoint."""
+    L = lib.load()
+    g = lib.make_grid((16, 8, 6), (0, 0, 0), (1, 1, 1), (0, 1, 1))
+    o = lib.Opts()
+    o.rk_order = 3
+    mc = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+    o.reconstruction = 1
+    ppm = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+    sv_mc, sv_ppm = 24 * 12 * 10, 24 * 14 * 12        # x pitch rounded to 8 elements
+    assert ppm - mc == 3 * 8 * 9 * (sv_ppm - sv_mc)      # three caches
+    o.reconstruction = 2
+    assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) == 0
+    o.reconstruction = 1
+    assert L.grmhd_workspace_bytes(C.byref(lib.make_grid((16, 2, 6), (0, 0, 0), (1, 1, 1), (0, 0, 0))),
+                                   C.byref(o)) == 0
+    assert L.grmhd_workspace_bytes(C.byref(lib.make_grid((16, 1, 1), (0, 0, 0), (1, 1, 1), (0, 0, 0))),
+                                   C.byref(o)) > 0
+    o.adjoint = 1
+    assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) == 0
+    o.adjoint = 0
+    raw, addr = _host_ws(ppm)
+    o.workspace, o.workspace_bytes, o.rho_atm, o.p_atm = C.c_void_p(addr), ppm, 1e-12, 1e-12
+    m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
+    e = lib.Eos(0, 5.0 / 3.0, 0.0)
+    ctx = C.c_void_p()
+    assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == 0
+    assert L.grmhd_free(ctx) == 0
+    o.adjoint = 1
+    assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
+
+
 def test_batch_workspace_and_init_validation(lib):
     L = lib.load()
     n = [20, 35, 7]
@@ -195,7 +228,7 @@ def test_batch_workspace_and_init_validation(lib):
     o.precision = 0
     raw, addr = _host_ws(nb)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, C.c_void_p(addr), nb)
+    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)
     ctx = C.c_void_p()
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == 0
     assert L.grmhd_batch_evolve(ctx, C.c_void_p(addr), 5) == -4      # before cons

@@ -132,3 +132,17 @@ def test_batch_full_size_sampled(G, orc):
     # distance grows with the number of cells and steps; the median problem
     # holds the 1e-5 bar
     assert np.median(worst) <= 1e-5 and np.percentile(worst, 90) <= 1e-4
+
+
+def test_batch_one_unknown_recovery(G, orc):
+    """The ensemble with the recovery's one-unknown iteration: the same root,
+    the same bar against the oracle."""
+    e = WL.config5(nprob=6, nmin=20, nmax=150, k=3)
+    s = G.batch_for(e, device=DEV, recovery="1d")
+    U = s.cons(s.pack(e.P))
+    s.evolve(U)
+    Us = s.unpack(U.cpu())
+    for b in range(len(e.n)):
+        Ur, _ = _oracle_problem(orc, e, b)
+        err = orc.parity_error(Us[b].numpy(), Ur)
+        assert np.all(err[:8] <= 1e-10), (b, err)
