@@ -380,7 +380,8 @@ __device__ __forceinline__ bool c2p_newton2d(const C2P& c, double gk, double tol
         double bw = c.Bc2 + Wc;
         double iW = 1.0 / Wc;
         double iW2 = iW * iW;
-        double s = sqrt(1.0 - v2);
+        double is = rsqrt(1.0 - v2);          // 1 / sqrt(1 - v^2) = W
+        double s = (1.0 - v2) * is;
         // residuals
         double r1 = v2 * bw * bw - c.QB2 * (c.Bc2 + 2.0 * Wc) * iW2 - c.Qt2;
         double p = gk * (Wc * (1.0 - v2) - c.D * s);
@@ -389,7 +390,7 @@ __device__ __forceinline__ bool c2p_newton2d(const C2P& c, double gk, double tol
         double a11 = 2.0 * v2 * bw + 2.0 * c.QB2 * bw * iW2 * iW;
         double a12 = bw * bw;
         double a21 = -c.QB2 * iW2 * iW - 1.0 + gk * (1.0 - v2);
-        double a22 = -0.5 * c.Bc2 + gk * (-Wc + 0.5 * c.D / s);
+        double a22 = -0.5 * c.Bc2 + gk * (-Wc + 0.5 * c.D * is);
         double idet = 1.0 / (a11 * a22 - a12 * a21);
         double dW = (r1 * a22 - a12 * r2) * idet;
         double dv = (a11 * r2 - a21 * r1) * idet;
@@ -611,7 +612,7 @@ __device__ __forceinline__ int recover_cell(const Dev& d, const Geo& g, double* 
     ok = ok && u[0] > 0.0;
     double Bc[3], Q[3];
     C2P c;
-    double isg = 1.0 / g.sqrtg;
+    double isg = g.alpha * g.isqrtmg;   // 1 / sqrt(gamma) = alpha / sqrt(-g)
     c.D = u[0] * isg;
     c.Qn = -(u[1] + u[0]) * g.isqrtmg;
 #pragma unroll
@@ -643,12 +644,13 @@ __device__ __forceinline__ int recover_cell(const Dev& d, const Geo& g, double* 
         }
     }
     if (ok) {
-        double s = sqrt(1.0 - v2);
-        double W = 1.0 / s;
+        double W = rsqrt(1.0 - v2);
+        double s = (1.0 - v2) * W;
         p[0] = c.D * s;
         p[1] = d.gk * (Wc * (1.0 - v2) - c.D * s);
-        double f = W / (Wc + c.Bc2);
-        double fq = QB / Wc;
+        double iq = 1.0 / (Wc * (Wc + c.Bc2));
+        double f = W * Wc * iq;                 // W / (Wc + B^2)
+        double fq = QB * (Wc + c.Bc2) * iq;     // (Q.B) / Wc
 #pragma unroll
         for (int i = 0; i < 3; ++i)
             p[2 + i] = f * (g.ipsi4 * Q[i] + fq * Bc[i]);
