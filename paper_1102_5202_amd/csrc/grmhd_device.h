@@ -40,41 +40,50 @@ struct Geo {
     double alpha, psi4, ipsi4, sqrtg, sqrtmg, isqrtmg;
 };
 
-// h = M/(2 r_s) and r_s at a point; returns false where the softened radius is
+// 1/r_s at a point (r_s the softened radius); varying is false where r_s is
 // constant (MAX softening inside r_min: derivatives vanish).
-__device__ __forceinline__ double soft_radius(const Dev& d, double r2, bool& varying)
+__device__ __forceinline__ double soft_iradius(const Dev& d, double r2, bool& varying)
 {
     if (d.soft == 0) {
         varying = true;
-        return sqrt(r2 + d.rmin2);
+        return rsqrt(r2 + d.rmin2);
     }
-    double r = sqrt(r2);
-    varying = r > d.rmin;
-    return varying ? r : d.rmin;
+    varying = r2 > d.rmin2;
+    return rsqrt(varying ? r2 : d.rmin2);
+}
+
+// The isotropic metric from h = M / (2 r_s) < 1: alpha = (1-h)/(1+h),
+// psi = 1 + h, with one division for 1/(1+h) and 1/(1-h).
+__device__ __forceinline__ Geo geo_from_h(double h, double& i1h)
+{
+    Geo g;
+    const double q = 1.0 / ((1.0 - h) * (1.0 + h));
+    i1h = (1.0 - h) * q;                  // 1 / (1 + h)
+    const double im1h = (1.0 + h) * q;    // 1 / (1 - h)
+    const double psi = 1.0 + h;
+    const double psi2 = psi * psi;
+    const double i2 = i1h * i1h;
+    g.alpha = (1.0 - h) * i1h;
+    g.psi4 = psi2 * psi2;
+    g.ipsi4 = i2 * i2;
+    g.sqrtg = g.psi4 * psi2;
+    g.sqrtmg = g.alpha * g.sqrtg;
+    g.isqrtmg = im1h * i1h * g.ipsi4;     // 1 / ((1 - h) (1 + h)^5)
+    return g;
 }
 
 template <int KIND>
 __device__ __forceinline__ Geo geo_at(const Dev& d, double x, double y, double z)
 {
-    Geo g;
     if (KIND == FLAT) {
+        Geo g;
         g.alpha = g.psi4 = g.ipsi4 = g.sqrtg = g.sqrtmg = g.isqrtmg = 1.0;
-    } else {
-        bool vary;
-        double rs = soft_radius(d, x * x + y * y + z * z, vary);
-        double h = 0.5 * d.M / rs;
-        double i1h = 1.0 / (1.0 + h);
-        double psi = 1.0 + h;
-        double psi2 = psi * psi;
-        double i2 = i1h * i1h;
-        g.alpha = (1.0 - h) * i1h;
-        g.psi4 = psi2 * psi2;
-        g.ipsi4 = i2 * i2;
-        g.sqrtg = g.psi4 * psi2;
-        g.sqrtmg = g.alpha * g.sqrtg;
-        g.isqrtmg = 1.0 / g.sqrtmg;
+        return g;
     }
-    return g;
+    bool vary;
+    const double irs = soft_iradius(d, x * x + y * y + z * z, vary);
+    double i1h;
+    return geo_from_h(0.5 * d.M * irs, i1h);
 }
 
 // Geometry plus the radial derivative factors at a cell centre:
@@ -83,30 +92,22 @@ template <int KIND>
 __device__ __forceinline__ Geo geo_deriv(const Dev& d, double x, double y, double z, double& ka,
                                          double& kp)
 {
-    Geo g;
     if (KIND == FLAT) {
+        Geo g;
         g.alpha = g.psi4 = g.ipsi4 = g.sqrtg = g.sqrtmg = g.isqrtmg = 1.0;
         ka = kp = 0.0;
-    } else {
-        bool vary;
-        double rs = soft_radius(d, x * x + y * y + z * z, vary);
-        double irs = 1.0 / rs;
-        double h = 0.5 * d.M * irs;
-        double i1h = 1.0 / (1.0 + h);
-        double psi = 1.0 + h;
-        double psi2 = psi * psi;
-        double i2 = i1h * i1h;
-        g.alpha = (1.0 - h) * i1h;
-        g.psi4 = psi2 * psi2;
-        g.ipsi4 = i2 * i2;
-        g.sqrtg = g.psi4 * psi2;
-        g.sqrtmg = g.alpha * g.sqrtg;
-        g.isqrtmg = 1.0 / g.sqrtmg;
-        double hr2 = vary ? h * irs * irs : 0.0;
-        // d alpha/d r_s = 2 h / (r_s (1+h)^2), d psi^4/d r_s = -4 psi^3 h / r_s, d r_s/d x_j = x_j / r_s
-        ka = 2.0 * hr2 * i2;
-        kp = -4.0 * psi2 * psi * hr2;
+        return g;
     }
+    bool vary;
+    const double irs = soft_iradius(d, x * x + y * y + z * z, vary);
+    const double h = 0.5 * d.M * irs;
+    double i1h;
+    const Geo g = geo_from_h(h, i1h);
+    const double psi = 1.0 + h;
+    const double hr2 = vary ? h * irs * irs : 0.0;
+    // d alpha/d r_s = 2 h / (r_s (1+h)^2), d psi^4/d r_s = -4 psi^3 h / r_s, d r_s/d x_j = x_j / r_s
+    ka = 2.0 * hr2 * i1h * i1h;
+    kp = -4.0 * psi * psi * psi * hr2;
     return g;
 }
 
