@@ -38,7 +38,8 @@ class _Grid(C.Structure):
 class _Problem(C.Structure):
     _fields_ = [("metric", _Metric), ("grid", _Grid), ("gamma", C.c_double),
                 ("rk_order", C.c_int), ("c_h", C.c_double), ("kappa", C.c_double),
-                ("rho_atm", C.c_double), ("p_atm", C.c_double), ("recon", C.c_int)]
+                ("rho_atm", C.c_double), ("p_atm", C.c_double), ("recon", C.c_int),
+                ("ct", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -117,6 +118,7 @@ class Problem:
     rho_atm: float = 1e-12
     p_atm: float = 1e-12
     recon: int = RECON_MC
+    ct: int = 0
     _c: _Problem = field(default=None, init=False, repr=False)
 
     def c(self) -> _Problem:
@@ -137,6 +139,7 @@ class Problem:
         p.rho_atm = self.rho_atm
         p.p_atm = self.p_atm
         p.recon = int(self.recon)
+        p.ct = int(self.ct)
         return p
 
     @property

@@ -625,7 +625,7 @@ void orc_ppm_edges(const double *a, double *aL, double *aR)
  * right reconstructed primitives.  The normal field and Phi form a linear
  * 2x2 system that is solved exactly first; its state fixes the normal field
  * seen by both sides.                                                       */
-static void face_flux(const geom *G, double gamma, double c_h, int dir, const double *qL_in,
+static void face_flux(const geom *G, double gamma, double c_h, int ct, int dir, const double *qL_in,
                       const double *qR_in, double *F)
 {
     double qL[9], qR[9], FL[9], FR[9], UL[9], UR[9];
@@ -637,7 +637,9 @@ static void face_flux(const geom *G, double gamma, double c_h, int dir, const do
     memcpy(qR, qR_in, sizeof qR);
     BnL = G->sqrtmg * qL[5 + dir];
     BnR = G->sqrtmg * qR[5 + dir];
-    Bs = 0.5 * (BnL + BnR) - (qR[8] - qL[8]) / (2.0 * c_h);
+    /* with constrained transport Phi plays no part: the normal field is the
+     * mean of the two reconstructed ones (its flux is replaced later) */
+    Bs = ct ? 0.5 * (BnL + BnR) : 0.5 * (BnL + BnR) - (qR[8] - qL[8]) / (2.0 * c_h);
     phis = 0.5 * (qL[8] + qR[8]) - 0.5 * c_h * (BnR - BnL);
     qL[5 + dir] = qR[5 + dir] = Bs / G->sqrtmg;
 
@@ -780,13 +782,118 @@ int orc_con2prim(const orc_problem *pb, double *U, const double *Pguess, double 
     return con2prim_grid(pb, U, Pguess, P, flags, st);
 }
 
+/* Face index of direction dir at face/cell indices (i, j, k). */
+static long long fidx(const orc_grid *g, int dir, int i, int j, int k)
+{
+    int nf0 = g->n[0] + (dir == 0), nf1 = g->n[1] + (dir == 1);
+    return ((long long)k * nf1 + j) * nf0 + i;
+}
+
+/* Flux-CT (Toth 2000, the constrained-transport alternative to the cleaning
+ * of section 3.2): for every pair (a, b) of active axes, the edge value
+ *   W_ab = 1/4 [F^b(Bd^a) at the two b-faces beside the edge
+ *               - F^a(Bd^b) at the two a-faces beside it]
+ * (the electric field along the third axis, up to sign), from the original
+ * fluxes; then F^a(Bd^b) = -1/2 (W_ab at the two edges of the a-face) and
+ * F^b(Bd^a) = +1/2 (W_ab at the two edges of the b-face); the normal-field
+ * and Phi fluxes vanish.  Face neighbours across a boundary map like cells.
+ * The update then keeps the corner-centred divergence of Bd unchanged.   */
+static int flux_ct(const orc_grid *g, double **F)
+{
+    int act[3], a, b;
+    double *W[3][3] = {{NULL}};
+    for (a = 0; a < 3; a++)
+        act[a] = g->n[a] > 1;
+    /* edge values from the original fluxes */
+    for (a = 0; a < 3; a++)
+        for (b = a + 1; b < 3; b++) {
+            int e = 3 - a - b, fa, fb, ce;
+            int na = g->n[a], nb = g->n[b], ne = g->n[e];
+            long long NFa, NFb;
+            if (!act[a] || !act[b])
+                continue;
+            NFa = (long long)(g->n[0] + (a == 0)) * (g->n[1] + (a == 1)) * (g->n[2] + (a == 2));
+            NFb = (long long)(g->n[0] + (b == 0)) * (g->n[1] + (b == 1)) * (g->n[2] + (b == 2));
+            W[a][b] = (double *)malloc(sizeof(double) * (size_t)(na + 1) * (nb + 1) * ne);
+            if (!W[a][b])
+                return -1;
+            for (ce = 0; ce < ne; ce++)
+                for (fb = 0; fb <= nb; fb++)
+                    for (fa = 0; fa <= na; fa++) {
+                        double s = 0.0;
+                        int t;
+                        for (t = 0; t < 2; t++) {
+                            int ix[3], cb = bc_map(fb - 1 + t, nb, g->bc[b]), ca = bc_map(fa - 1 + t, na, g->bc[a]);
+                            /* F^a(Bd^b) at a-face fa, cell cb along b */
+                            ix[a] = fa;
+                            ix[b] = cb;
+                            ix[e] = ce;
+                            s -= F[a][(5 + b) * NFa + fidx(g, a, ix[0], ix[1], ix[2])];
+                            /* F^b(Bd^a) at b-face fb, cell ca along a */
+                            ix[a] = ca;
+                            ix[b] = fb;
+                            s += F[b][(5 + a) * NFb + fidx(g, b, ix[0], ix[1], ix[2])];
+                        }
+                        W[a][b][((long long)ce * (nb + 1) + fb) * (na + 1) + fa] = 0.25 * s;
+                    }
+        }
+    /* corrected fluxes */
+    for (a = 0; a < 3; a++) {
+        long long NFa, f;
+        int i, j, k;
+        if (!act[a])
+            continue;
+        NFa = (long long)(g->n[0] + (a == 0)) * (g->n[1] + (a == 1)) * (g->n[2] + (a == 2));
+        for (k = 0; k < g->n[2] + (a == 2); k++)
+            for (j = 0; j < g->n[1] + (a == 1); j++)
+                for (i = 0; i < g->n[0] + (a == 0); i++) {
+                    int ix[3] = {i, j, k}, b;
+                    f = fidx(g, a, i, j, k);
+                    F[a][(5 + a) * NFa + f] = 0.0;
+                    F[a][8 * NFa + f] = 0.0;
+                    for (b = 0; b < 3; b++) {
+                        int lo = a < b ? a : b, hi = a < b ? b : a, e = 3 - a - b;
+                        int nl = g->n[lo], nh = g->n[hi];
+                        long long w0, w1;
+                        double sign;
+                        if (b == a || !act[b])
+                            continue;
+                        /* the face's two edges: the face index along a is fixed,
+                         * the cell index along b gives edges b and b+1 */
+                        {
+                            int el[3], eh[3];
+                            el[0] = ix[0];
+                            el[1] = ix[1];
+                            el[2] = ix[2];
+                            eh[0] = ix[0];
+                            eh[1] = ix[1];
+                            eh[2] = ix[2];
+                            eh[b] += 1;
+                            w0 = ((long long)el[e] * (nh + 1) + el[hi]) * (nl + 1) + el[lo];
+                            w1 = ((long long)eh[e] * (nh + 1) + eh[hi]) * (nl + 1) + eh[lo];
+                        }
+                        /* W is defined for (lo, hi) = (a, b) with sign +; for a > b
+                         * the face is a b-face of the pair and takes +1/2 */
+                        sign = a < b ? -0.5 : 0.5;
+                        F[a][(5 + b) * NFa + f] = sign * (W[lo][hi][w0] + W[lo][hi][w1]);
+                    }
+                }
+    }
+    for (a = 0; a < 3; a++)
+        for (b = 0; b < 3; b++)
+            free(W[a][b]);
+    return 0;
+}
+
 int orc_rhs(const orc_problem *pb, const double *P, double *R)
 {
     const orc_grid *g = &pb->grid;
     long long N = ncell(g);
+    double *Fall[3] = {NULL, NULL, NULL};
     int d;
     memset(R, 0, sizeof(double) * 9 * N);
 
+    /* face fluxes of every active axis */
     for (d = 0; d < 3; d++) {
         int nf[3], k;
         long long NF;
@@ -800,8 +907,12 @@ int orc_rhs(const orc_problem *pb, const double *P, double *R)
         nf[d] += 1;
         NF = (long long)nf[0] * nf[1] * nf[2];
         Fd = (double *)malloc(sizeof(double) * 9 * NF);
-        if (!Fd)
+        if (!Fd) {
+            for (k = 0; k < 3; k++)
+                free(Fall[k]);
             return -1;
+        }
+        Fall[d] = Fd;
 
         /* face fluxes: face index f along d sits between cells f-1 and f */
 #pragma omp parallel for num_threads(g_threads) schedule(static)
@@ -840,13 +951,33 @@ int orc_rhs(const orc_problem *pb, const double *P, double *R)
                     for (s = 0; s < 3; s++)
                         pos[s] = (s == d) ? g->lo[s] + fi[s] * dx : centre(g, s, fi[s]);
                     geom_at(&pb->metric, pos[0], pos[1], pos[2], &G);
-                    face_flux(&G, pb->gamma, pb->c_h, d, qL, qR, F);
+                    face_flux(&G, pb->gamma, pb->c_h, pb->ct, d, qL, qR, F);
                     for (v = 0; v < 9; v++)
                         Fd[v * NF + fc] = F[v];
                 }
         }
 
-        /* flux differences */
+    }
+
+    if (pb->ct && flux_ct(g, Fall) != 0) {
+        for (d = 0; d < 3; d++)
+            free(Fall[d]);
+        return -1;
+    }
+
+    /* flux differences */
+    for (d = 0; d < 3; d++) {
+        int nf[3], k;
+        long long NF;
+        const double *Fd = Fall[d];
+        double dx = dxof(g, d);
+        if (g->n[d] == 1)
+            continue;
+        nf[0] = g->n[0];
+        nf[1] = g->n[1];
+        nf[2] = g->n[2];
+        nf[d] += 1;
+        NF = (long long)nf[0] * nf[1] * nf[2];
 #pragma omp parallel for num_threads(g_threads) schedule(static)
         for (k = 0; k < g->n[2]; k++) {
             int i, j, v;
@@ -861,8 +992,9 @@ int orc_rhs(const orc_problem *pb, const double *P, double *R)
                         R[v * N + c] -= (Fd[v * NF + fh] - Fd[v * NF + fl]) / dx;
                 }
         }
-        free(Fd);
     }
+    for (d = 0; d < 3; d++)
+        free(Fall[d]);
 
     /* cell-centred sources */
     {
@@ -880,6 +1012,8 @@ int orc_rhs(const orc_problem *pb, const double *P, double *R)
                     load_prim(g, P, i, j, k, q);
                     state_from_prim(&G, pb->gamma, q, &s);
                     source_from_state(&G, &s, pb->kappa, S);
+                    if (pb->ct)
+                        S[8] = 0.0;   /* constrained transport: Phi is carried unchanged */
                     for (v = 0; v < 9; v++)
                         R[v * N + c] += S[v];
                 }
@@ -1030,5 +1164,5 @@ void orc_point_face_flux(const orc_metric *m, double gamma, double c_h, int dir,
 {
     geom G;
     geom_at(m, x, y, z, &G);
-    face_flux(&G, gamma, c_h, dir, qL, qR, F);
+    face_flux(&G, gamma, c_h, 0, dir, qL, qR, F);
 }

@@ -63,6 +63,7 @@ typedef struct {
     double rho_atm; /* atmosphere density                                */
     double p_atm;   /* atmosphere / floor pressure                       */
     int recon;      /* ORC_RECON_MC or ORC_RECON_PPM                     */
+    int ct;         /* 0: hyperbolic cleaning; 1: flux-CT (Phi carried)  */
 } orc_problem;
 
 typedef struct {
