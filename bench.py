@@ -431,9 +431,11 @@ def main(argv=None) -> int:
         out["adjoint"] = adjoint_cost(grmhd, workloads.config4(n=64, nsteps=50), dev, 50, 10)
     if not args.no_variants and fp64:
         # scheme variants on the same workload: the recovery's one-unknown
-        # iteration; PPM reconstruction (three face kernels + the cell update)
+        # iteration; PPM reconstruction and flux-CT (three face kernels, for
+        # flux-CT the edge and face corrections, then the cell update)
         out["variants"] = {}
-        for name, over in (("recovery_1d", {"recovery": "1d"}), ("ppm", {"reconstruction": "ppm"})):
+        for name, over in (("recovery_1d", {"recovery": "1d"}), ("ppm", {"reconstruction": "ppm"}),
+                           ("fluxct", {"divergence": "fluxct"})):
             v = timed_run("fp64", **over)
             out["variants"][name] = {
                 "value": v["value"], "ms_per_step": v["ms_per_step"], "recovery": v["recovery"],

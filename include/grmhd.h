@@ -124,6 +124,21 @@ typedef enum {
     GRMHD_RECON_PPM = 1
 } grmhd_reconstruction;
 
+/* Control of the divergence of the densitised field (section 3.2 names a
+ * hyperbolic cleaning scheme): GLM-type cleaning with the scalar Phi, or
+ * flux-CT (Toth 2000: every field flux replaced by the average of the edge
+ * values -- the electric field -- built from the cleaning-free Godunov
+ * fluxes of both face directions), which keeps the corner-centred
+ * divergence sum_i d_i Bd^i unchanged to round-off in 3D.  With flux-CT Phi
+ * is carried unchanged (no flux, no damping), the normal field at a face is
+ * the mean of the two reconstructed ones, 3D grids run the face kernels of
+ * all axes and the cell update (the fused kernel is cleaning only), and
+ * there is no adjoint and no batched form. */
+typedef enum {
+    GRMHD_DIV_CLEANING = 0,
+    GRMHD_DIV_FLUXCT = 1
+} grmhd_divergence;
+
 /* Scheme options and the caller's workspace. */
 typedef struct {
     int rk_order;          /* 2 (SSP-RK2) or 3 (SSP-RK3, the order of section 3.2) */
@@ -136,6 +151,7 @@ typedef struct {
     int newton_maxit;      /* iteration cap of the recovery (50 if 0) */
     int recovery;          /* grmhd_recovery: the primitive recovery's Newton iteration */
     int reconstruction;    /* grmhd_reconstruction: MC (2 ghost layers) or PPM (3) */
+    int divergence;        /* grmhd_divergence: hyperbolic cleaning or flux-CT */
     int timing;            /* nonzero: time every kernel launch with HIP events */
     int adjoint;           /* nonzero: reserve the workspace of the adjoint calls (FP64 only) */
     int tape_steps;        /* with adjoint: slots of recorded steps (grmhd_step_record), 0..4096 */
@@ -166,7 +182,8 @@ typedef enum {
     GRMHD_K_ADJ_FACE = 9, /* adjoint: face solver, one axis                  */
     GRMHD_K_ADJ_GATHER = 10, /* adjoint: reconstruction of all axes + ghost fold */
     GRMHD_K_ADJ_CELL = 11,   /* adjoint: sources + the next recovery + RK adjoint */
-    GRMHD_K_COUNT = 12
+    GRMHD_K_CT = 12,      /* flux-CT: edge values and the corrected field fluxes */
+    GRMHD_K_COUNT = 13
 } grmhd_kernel;
 
 typedef struct grmhd_ctx grmhd_ctx;

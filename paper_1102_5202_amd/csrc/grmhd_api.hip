@@ -26,6 +26,9 @@ struct Layout {
     int g[3], px, py, pz;
     long long sv, N, nf[3];
     size_t off_cnt, off_pc[3], off_us, off_f[3];
+    // flux-CT: edge values of the axis pairs (x,y), (x,z), (y,z)
+    bool ct = false;
+    size_t off_w[3] = {0, 0, 0};
     // adjoint part (FP64): stage primitive caches P^0..P^ns, the stages'
     // recovery flags, the recomputed stage state, the U^n cotangent
     // accumulator, the R cotangent, a dense primitive scratch, the ghosted
@@ -60,7 +63,7 @@ bool grid_ok(const grmhd_grid* g)
 }
 
 Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int ns = 3, int tape = 0,
-                   int ghost = 2)
+                   int ghost = 2, bool ct = false)
 {
     Layout L{};
     for (int d = 0; d < 3; ++d)
@@ -90,6 +93,15 @@ Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int 
     for (int d = 0; d < 3; ++d) {
         L.off_f[d] = off;
         off = round_up(off + esize * 9 * (size_t)L.nf[d], 256);
+    }
+    L.ct = ct;
+    if (ct) {
+        for (int p = 0; p < 3; ++p) {
+            const int x = p == 2 ? 1 : 0, y = p == 0 ? 1 : 2, z = 3 - x - y;
+            L.off_w[p] = off;
+            if (g->n[x] > 1 && g->n[y] > 1)
+                off = round_up(off + esize * (size_t)(g->n[x] + 1) * (g->n[y] + 1) * g->n[z], 256);
+        }
     }
     L.adj = adjoint;
     if (adjoint) {
@@ -146,6 +158,10 @@ bool opts_fit(const grmhd_grid* g, const grmhd_opts* o)
         return true;   // defaults: MC
     if (o->reconstruction != GRMHD_RECON_MC && o->reconstruction != GRMHD_RECON_PPM)
         return false;
+    if (o->divergence != GRMHD_DIV_CLEANING && o->divergence != GRMHD_DIV_FLUXCT)
+        return false;
+    if (o->divergence == GRMHD_DIV_FLUXCT && o->adjoint)
+        return false;
     if (o->reconstruction == GRMHD_RECON_PPM) {
         if (o->adjoint)
             return false;
@@ -183,6 +199,7 @@ struct grmhd_ctx {
     void* Pbuf[3] = {nullptr, nullptr, nullptr};
     void* Us = nullptr;                     // intermediate stage state (cache type)
     void* F[3] = {nullptr, nullptr, nullptr};
+    void* W[3] = {nullptr, nullptr, nullptr};   // flux-CT edge values
     // cache b has its ghost slabs filled: every kernel that writes a cache
     // (cons, prim, the updates) writes the ghost images of its cells as well
     bool ghosts_ok[3] = {false, false, false};
@@ -296,6 +313,13 @@ int fluxes(grmhd_ctx* c, int b, int ndir)
         if (rc)
             return rc;
     }
+    if (c->d.ct && ndir == 3) {
+        T* F[3] = {faces<T>(c, 0), faces<T>(c, 1), faces<T>(c, 2)};
+        T* W[3] = {(T*)c->W[0], (T*)c->W[1], (T*)c->W[2]};
+        rc = timed(c, GRMHD_K_CT, [&] { return grmhd::launch_ct(F, W, c->d, c->stream); });
+        if (rc)
+            return rc;
+    }
     return GRMHD_OK;
 }
 
@@ -380,13 +404,13 @@ int step_t(grmhd_ctx* c, double* U, double dt)
     const int ns = c->rk_order;
     const double* A = ns == 3 ? RK3A : RK2A;
     const double* B = ns == 3 ? RK3B : RK2B;
-    // 3D grids with MC: the z faces are computed inside the fused update
-    // kernel, which writes the new primitives to another cache; otherwise (1D,
-    // 2D, PPM) the update works in place on the cache with all face fluxes
-    // precomputed.  The first stage
+    // 3D grids with MC and cleaning: the z faces are computed inside the fused
+    // update kernel, which writes the new primitives to another cache;
+    // otherwise (1D, 2D, PPM, flux-CT) the update works in place on the cache
+    // with all face fluxes precomputed (and, for flux-CT, corrected).  The first stage
     // reads U^n as its stage state; the intermediate stage state has the cache
     // type (float in the mixed path); the last stage writes U.
-    const bool zmarch = c->d.act[2] && !c->d.ppm;
+    const bool zmarch = c->d.act[2] && !c->d.ppm && !c->d.ct;
     T* Us = (T*)c->Us;
     for (int s = 0; s < ns; ++s) {
         const int src = zmarch ? s : 0;
@@ -436,7 +460,7 @@ int adj_prepare(grmhd_ctx* c)
 int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, const double* B)
 {
     const int ns = c->rk_order;
-    const bool zmarch = c->d.act[2] && !c->d.ppm;
+    const bool zmarch = c->d.act[2] && !c->d.ppm && !c->d.ct;
     int rc = timed(c, GRMHD_K_PRIM, [&] {
         return grmhd::launch_prim(c->kind, U, c->Pb, c->Ac[0], c->d, c->cnt, c->stream);
     });
@@ -547,7 +571,7 @@ int step_record(grmhd_ctx* c, double* U, double dt, int slot)
     const int ns = c->rk_order;
     const double* A = ns == 3 ? RK3A : RK2A;
     const double* B = ns == 3 ? RK3B : RK2B;
-    const bool zmarch = c->d.act[2] && !c->d.ppm;
+    const bool zmarch = c->d.act[2] && !c->d.ppm && !c->d.ct;
     const size_t bytes = sizeof(double) * 9 * (size_t)c->L.sv;
     int rc = GRMHD_OK;
     if (!c->ghosts_ok[0]) {
@@ -615,7 +639,9 @@ size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_opts* opts)
     const int ns = opts && opts->rk_order == 2 ? 2 : 3;
     if (!opts_fit(grid, opts))
         return 0;
-    return make_layout(grid, elem_size(opts), wants_adjoint(opts), ns, tape_slots(opts), ghost_width(opts)).total;
+    return make_layout(grid, elem_size(opts), wants_adjoint(opts), ns, tape_slots(opts), ghost_width(opts),
+                       opts && opts->divergence == GRMHD_DIV_FLUXCT)
+        .total;
 }
 
 int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
@@ -653,7 +679,7 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     if (!opts_fit(grid, opts))
         return GRMHD_ERR_ARG;
     Layout L = make_layout(grid, elem_size(opts), wants_adjoint(opts), opts->rk_order, tape_slots(opts),
-                           ghost_width(opts));
+                           ghost_width(opts), opts->divergence == GRMHD_DIV_FLUXCT);
     if (!opts->workspace || opts->workspace_bytes < L.total)
         return GRMHD_ERR_WORKSPACE;
     if (((uintptr_t)opts->workspace) % 256 != 0)
@@ -700,6 +726,7 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     d.maxit = opts->newton_maxit > 0 ? opts->newton_maxit : 50;
     d.c2p1d = opts->recovery == GRMHD_RECOVERY_1D;
     d.ppm = opts->reconstruction == GRMHD_RECON_PPM;
+    d.ct = opts->divergence == GRMHD_DIV_FLUXCT;
 
     c->ws = (unsigned char*)opts->workspace;
     c->cnt = (unsigned long long*)(c->ws + L.off_cnt);
@@ -708,6 +735,8 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     c->Us = (void*)(c->ws + L.off_us);
     for (int a = 0; a < 3; ++a)
         c->F[a] = L.nf[a] ? (void*)(c->ws + L.off_f[a]) : nullptr;
+    for (int p = 0; p < 3; ++p)
+        c->W[p] = L.ct ? (void*)(c->ws + L.off_w[p]) : nullptr;
     if (L.adj) {
         c->adj = true;
         for (int b = 0; b <= c->rk_order; ++b)

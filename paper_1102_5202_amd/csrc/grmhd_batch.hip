@@ -180,6 +180,8 @@ int grmhd_batch_init(grmhd_batch** out, const grmhd_batch_desc* desc, const grmh
         return GRMHD_ERR_ARG;
     if (opts->reconstruction != GRMHD_RECON_MC)
         return GRMHD_ERR_ARG;   // the batched rows carry two ghost cells: MC only
+    if (opts->divergence != GRMHD_DIV_CLEANING)
+        return GRMHD_ERR_ARG;
     const size_t es = esize_of(opts);
     BatchLayout L = batch_layout(desc, es);
     if (!opts->workspace || opts->workspace_bytes < L.total || ((uintptr_t)opts->workspace) % 256 != 0)

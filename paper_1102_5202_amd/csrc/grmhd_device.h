@@ -33,6 +33,7 @@ struct Dev {
     int maxit;
     int c2p1d;       // recovery: 0 Newton on (Wc, v^2), 1 Newton on Wc alone
     int ppm;         // reconstruction: 0 MC (2 ghosts), 1 PPM (3 ghosts)
+    int ct;          // divergence control: 0 cleaning (Phi), 1 flux-CT (Phi carried)
 };
 
 // Geometry at one point.
@@ -279,7 +280,9 @@ __device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, doub
 
     // cleaning pair: exact solution of the linear (Bd^n, Phi) Riemann problem
     T BnL = g.sqrtmg * qL[5 + D], BnR = g.sqrtmg * qR[5 + D];
-    T Bs = half * (BnL + BnR) - half * ich * (qR[8] - qL[8]);
+    // with flux-CT Phi plays no part: the mean of the reconstructed normal
+    // fields (its flux and Phi's are replaced after all faces are known)
+    T Bs = d.ct ? half * (BnL + BnR) : half * (BnL + BnR) - half * ich * (qR[8] - qL[8]);
     T phs = half * (qL[8] + qR[8]) - half * ch * (BnR - BnL);
     qL[5 + D] = qR[5 + D] = Bs * g.isqrtmg;
 
@@ -347,7 +350,8 @@ __device__ __forceinline__ void add_sources(const Dev& d, double x, double y, do
         R[3] += (double)(K * (T)y);
         R[4] += (double)(K * (T)z);
     }
-    R[8] -= d.kappa * (double)q[8];
+    if (!d.ct)
+        R[8] -= d.kappa * (double)q[8];   // flux-CT carries Phi unchanged
 }
 
 // ---------------------------------------------------------------------------

@@ -25,6 +25,10 @@ template <typename T>
 hipError_t launch_ghosts(T* Pc, const Dev& d, hipStream_t s);
 template <typename T>
 hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipStream_t s);
+// Flux-CT: the field fluxes of all active axes (F[3]) replaced from the edge
+// values W[3] of the axis pairs (x,y), (x,z), (y,z).
+template <typename T>
+hipError_t launch_ct(T* const* F, T* const* W, const Dev& d, hipStream_t s);
 // TS / TO: types of the stage state read (U^s) and written (U^(s+1)); double,
 // or float for the intermediate stages of the mixed-precision path.  U^n is
 // always double.  The update kernels read the primitives from Pc and write

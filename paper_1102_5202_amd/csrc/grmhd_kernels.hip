@@ -237,6 +237,106 @@ __global__ __launch_bounds__(BLOCK) void k_flux_ppm(const T* __restrict__ Pc, T*
     face_store<D, KIND>(qL, qR, pos[0], pos[1], pos[2], d, F, NF, f);
 }
 
+// ---------------------------------------------------------------------------
+// Flux-CT (Toth 2000).  For every pair (a, b) of active axes (a < b; e the
+// third), the edge value at a-face fa, b-face fb, cell ce along e:
+//   W_ab = 1/4 [F^b(Bd^a) at the two b-faces beside the edge
+//               - F^a(Bd^b) at the two a-faces beside it],
+// face neighbours across a boundary mapped like cells (periodic wrap,
+// outflow clamp); edge arrays [ce][fb][fa].  Then every face of an active
+// axis a gets, for each active partner b, F^a(Bd^b) = -1/2 (W_ab at its two
+// edges) when a < b and +1/2 when a > b; its normal-field and Phi fluxes
+// vanish.  The cell update keeps the corner-centred divergence of Bd.
+
+__device__ __forceinline__ int ct_map(int c, int n, int bc)
+{
+    return c < 0 ? (bc == 0 ? c + n : 0) : (c >= n ? (bc == 0 ? c - n : n - 1) : c);
+}
+
+__device__ __forceinline__ long long face_index(const Dev& d, int dir, int i, int j, int k)
+{
+    const long long nf0 = d.n[0] + (dir == 0), nf1 = d.n[1] + (dir == 1);
+    return ((long long)k * nf1 + j) * nf0 + i;
+}
+
+template <typename T>
+struct CtArgs {
+    T* F[3];          // face fluxes of the three axes ([9][nf])
+    T* W[3];          // edge values of the pairs (x,y), (x,z), (y,z)
+    long long nW[3];  // edges per pair (0: a partner inactive)
+};
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_ct_edges(CtArgs<T> A, Dev d)
+{
+    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    int p = 0;
+    while (p < 3 && t >= A.nW[p]) {
+        t -= A.nW[p];
+        ++p;
+    }
+    if (p == 3)
+        return;
+    const int a = p == 2 ? 1 : 0, b = p == 0 ? 1 : 2, e = 3 - a - b;
+    const int na = d.n[a], nb = d.n[b];
+    const int fa = (int)(t % (na + 1));
+    const long long r = t / (na + 1);
+    const int fb = (int)(r % (nb + 1));
+    const int ce = (int)(r / (nb + 1));
+    const long long NFa = d.nf[a], NFb = d.nf[b];
+    T s = T(0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        int ix[3];
+        ix[a] = fa;
+        ix[b] = ct_map(fb - 1 + q, nb, d.bc[b]);
+        ix[e] = ce;
+        s -= A.F[a][(5 + b) * NFa + face_index(d, a, ix[0], ix[1], ix[2])];
+        ix[a] = ct_map(fa - 1 + q, na, d.bc[a]);
+        ix[b] = fb;
+        s += A.F[b][(5 + a) * NFb + face_index(d, b, ix[0], ix[1], ix[2])];
+    }
+    A.W[p][t] = T(0.25) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_ct_faces(CtArgs<T> A, Dev d)
+{
+    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    int a = 0;
+    while (a < 3 && (!d.act[a] || t >= d.nf[a])) {
+        if (d.act[a])
+            t -= d.nf[a];
+        ++a;
+    }
+    if (a == 3)
+        return;
+    const long long NF = d.nf[a];
+    const int m0 = d.n[0] + (a == 0), m1 = d.n[1] + (a == 1);
+    int ix[3];
+    ix[0] = (int)(t % m0);
+    const long long r = t / m0;
+    ix[1] = (int)(r % m1);
+    ix[2] = (int)(r / m1);
+    T* F = A.F[a];
+    F[(5 + a) * NF + t] = T(0);
+    F[8 * NF + t] = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (b == a || !d.act[b])
+            continue;
+        const int lo = a < b ? a : b, hi = a < b ? b : a, e = 3 - a - b;
+        const int p = lo == 0 ? (hi == 1 ? 0 : 1) : 2;
+        const long long nl = d.n[lo], nh = d.n[hi];
+        int eh[3] = {ix[0], ix[1], ix[2]};
+        eh[b] += 1;
+        const long long w0 = ((long long)ix[e] * (nh + 1) + ix[hi]) * (nl + 1) + ix[lo];
+        const long long w1 = ((long long)eh[e] * (nh + 1) + eh[hi]) * (nl + 1) + eh[lo];
+        const T sign = a < b ? T(-0.5) : T(0.5);
+        F[(5 + b) * NF + t] = sign * (A.W[p][w0] + A.W[p][w1]);
+    }
+}
+
 // Flux differences + sources for cell c (i,j,k); q are its primitives.
 template <int KIND, typename T>
 __device__ __forceinline__ void rhs_cell(const Dev& d, const T* __restrict__ Fx, const T* __restrict__ Fy,
@@ -901,6 +1001,26 @@ static hipError_t launch_flux_k(int dir, const T* Pc, T* F, const Dev& d, hipStr
 }
 
 template <typename T>
+hipError_t launch_ct(T* const* F, T* const* W, const Dev& d, hipStream_t s)
+{
+    CtArgs<T> A;
+    long long edges = 0, faces = 0;
+    for (int p = 0; p < 3; ++p) {
+        const int a = p == 2 ? 1 : 0, b = p == 0 ? 1 : 2, e = 3 - a - b;
+        A.F[p] = F[p];
+        A.W[p] = W[p];
+        A.nW[p] = d.act[a] && d.act[b] ? (long long)(d.n[a] + 1) * (d.n[b] + 1) * d.n[e] : 0;
+        edges += A.nW[p];
+        faces += d.act[p] ? d.nf[p] : 0;
+    }
+    if (edges > 0)
+        hipLaunchKernelGGL(k_ct_edges<T>, dim3(blocks_for(edges)), dim3(BLOCK), 0, s, A, d);
+    if (faces > 0)
+        hipLaunchKernelGGL(k_ct_faces<T>, dim3(blocks_for(faces)), dim3(BLOCK), 0, s, A, d);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipStream_t s)
 {
     return kind == FLAT ? launch_flux_k<FLAT>(dir, Pc, F, d, s) : launch_flux_k<ISO>(dir, Pc, F, d, s);
@@ -1056,6 +1176,7 @@ GRMHD_INSTANTIATE_UPDATE(float, float, double)
     template hipError_t launch_fill<T>(T*, long long, double, hipStream_t);                             \
     template hipError_t launch_ghosts<T>(T*, const Dev&, hipStream_t);                                  \
     template hipError_t launch_flux<T>(int, int, const T*, T*, const Dev&, hipStream_t);               \
+    template hipError_t launch_ct<T>(T* const*, T* const*, const Dev&, hipStream_t);                   \
     template hipError_t launch_rhs<T>(int, const T*, const T*, const T*, const T*, double*, const Dev&,  \
                                       hipStream_t);                                                     \
     template hipError_t launch_cons<T>(int, const double*, double*, T*, const Dev&, hipStream_t);      \

@@ -21,8 +21,9 @@ FP64, MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 RECOVERY = {"2d": 0, "1d": 1}
 RECONSTRUCTION = {"mc": 0, "ppm": 1}
+DIVERGENCE = {"cleaning": 0, "fluxct": 1}
 KERNELS = ("bc", "flux_x", "flux_y", "flux_z", "update", "cons", "prim", "rhs", "adj_rec",
-           "adj_face", "adj_gather", "adj_cell")
+           "adj_face", "adj_gather", "adj_cell", "ct")
 NVAR = 9
 
 # exported symbols of include/grmhd.h
@@ -52,7 +53,7 @@ class Opts(C.Structure):
     _fields_ = [("rk_order", C.c_int), ("precision", C.c_int), ("c_h", C.c_double),
                 ("kappa", C.c_double), ("rho_atm", C.c_double), ("p_atm", C.c_double),
                 ("newton_tol", C.c_double), ("newton_maxit", C.c_int), ("recovery", C.c_int),
-                ("reconstruction", C.c_int), ("timing", C.c_int),
+                ("reconstruction", C.c_int), ("divergence", C.c_int), ("timing", C.c_int),
                 ("adjoint", C.c_int), ("tape_steps", C.c_int), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t)]
 
@@ -154,7 +155,7 @@ class Solver:
     U = (D, tau, Sx, Sy, Sz, Bdx, Bdy, Bdz, Phi).  precision "fp64" or
     "mixed" (float face physics and caches, double accumulation and recovery).
     recovery "2d" (Newton on (Wc, v^2)) or "1d" (Newton on Wc alone);
-    reconstruction "mc" or "ppm".
+    reconstruction "mc" or "ppm"; divergence "cleaning" (GLM, Phi) or "fluxct".
     adjoint=True (FP64 only) reserves the workspace of the adjoint calls;
     tape_steps > 0 (with adjoint) adds that many slots of recorded steps."""
 
@@ -162,7 +163,7 @@ class Solver:
                  gamma=5.0 / 3.0, K=0.0, rk_order=3, c_h=1.0, kappa=1.0, rho_atm=1e-12,
                  p_atm=1e-12, newton_tol=1e-12, newton_maxit=50, timing=False, device="cuda",
                  stream=None, precision="fp64", adjoint=False, tape_steps=0, recovery="2d",
-                 reconstruction="mc"):
+                 reconstruction="mc", divergence="cleaning"):
         L = load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -178,11 +179,13 @@ class Solver:
             raise ValueError("recovery must be one of %s" % sorted(RECOVERY))
         if reconstruction not in RECONSTRUCTION:
             raise ValueError("reconstruction must be one of %s" % sorted(RECONSTRUCTION))
+        if divergence not in DIVERGENCE:
+            raise ValueError("divergence must be one of %s" % sorted(DIVERGENCE))
         self.precision = precision
         self._opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa),
                           float(rho_atm), float(p_atm), float(newton_tol), int(newton_maxit),
-                          RECOVERY[recovery], RECONSTRUCTION[reconstruction], int(bool(timing)),
-                          int(bool(adjoint)), int(tape_steps), None, 0)
+                          RECOVERY[recovery], RECONSTRUCTION[reconstruction], DIVERGENCE[divergence],
+                          int(bool(timing)), int(bool(adjoint)), int(tape_steps), None, 0)
         nbytes = int(L.grmhd_workspace_bytes(C.byref(self._grid), C.byref(self._opts)))
         if nbytes == 0:
             raise ValueError("invalid grid")
@@ -327,7 +330,7 @@ class BatchSolver:
         self.precision = precision
         self._opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa), float(rho_atm),
                           float(p_atm), float(newton_tol), int(newton_maxit), RECOVERY[recovery], 0, 0, 0, 0,
-                          None, 0)
+                          0, None, 0)
         nbytes = int(L.grmhd_batch_workspace_bytes(C.byref(self._desc), C.byref(self._opts)))
         if nbytes == 0:
             raise ValueError("invalid batch description")

@@ -67,15 +67,15 @@ def test_workspace_and_init_validation(lib):
             assert L.grmhd_free(ctx) == 0
         return rc
 
-    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)
+    ok = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)
     assert init(ok) == 0
-    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb - 8)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr + 8), nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, None, nb)) == -2
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 2, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
-    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 1, 0, 0, 0, 0, C.c_void_p(addr), nb)) == 0
+    assert init(lib.Opts(4, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, 0, C.c_void_p(addr), nb - 8)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, 0, C.c_void_p(addr + 8), nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, 0, None, nb)) == -2
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 0.0, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 2, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == -1
+    assert init(lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 1, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)) == 0
     assert init(ok, eos=lib.Eos(0, 2.5, 0.0)) == -1
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 0.4)) == -1   # r_min <= M/2
     assert init(ok, metric=lib.Metric(lib.ISO_SCHW, 0, 1.0, 1.0)) == 0
@@ -125,7 +125,7 @@ def test_adjoint_workspace(lib):
     raw, addr = _host_ws(adj)
     m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 1, 0, C.c_void_p(addr), adj)
+    o = lib.Opts(3, 1, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 1, 0, C.c_void_p(addr), adj)
     ctx = C.c_void_p()
     assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
     o.precision = 0
@@ -209,6 +209,26 @@ def test_ppm_layout_and_validation(lib):
     assert L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o)) == -1
 
 
+def test_fluxct_layout_and_validation(lib):
+    """Flux-CT adds the edge values of every pair of active axes to the
+    workspace and has no adjoint."""
+    L = lib.load()
+    for n, pairs in (((16, 8, 6), [(17 * 9 * 6), (17 * 7 * 8), (9 * 7 * 16)]), ((16, 8, 1), [17 * 9]),
+                     ((16, 1, 1), [])):
+        g = lib.make_grid(n, (0, 0, 0), (1, 1, 1), (0, 1, 1))
+        o = lib.Opts()
+        o.rk_order = 3
+        base = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        o.divergence = 1
+        ct = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        want = sum(8 * p for p in pairs)
+        assert want <= ct - base <= want + 256 * 3, (n, ct - base, want)
+        o.divergence = 2
+        assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) == 0
+        o.divergence, o.adjoint = 1, 1
+        assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) == 0
+
+
 def test_batch_workspace_and_init_validation(lib):
     L = lib.load()
     n = [20, 35, 7]
@@ -228,7 +248,7 @@ def test_batch_workspace_and_init_validation(lib):
     o.precision = 0
     raw, addr = _host_ws(nb)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
-    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)
+    o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 0, 0, C.c_void_p(addr), nb)
     ctx = C.c_void_p()
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == 0
     assert L.grmhd_batch_evolve(ctx, C.c_void_p(addr), 5) == -4      # before cons
