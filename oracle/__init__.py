@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-FLAT, ISO_SCHW = 0, 1
+FLAT, ISO_SCHW, STORED = 0, 1, 2
 SOFT_SQRT, SOFT_MAX = 0, 1
 PERIODIC, OUTFLOW = 0, 1
 FLAG_FAIL, FLAG_ATM, FLAG_PFLOOR = 1, 2, 4
@@ -27,7 +27,8 @@ RECON_MC, RECON_PPM = 0, 1
 
 
 class _Metric(C.Structure):
-    _fields_ = [("kind", C.c_int), ("soft", C.c_int), ("M", C.c_double), ("r_min", C.c_double)]
+    _fields_ = [("kind", C.c_int), ("soft", C.c_int), ("M", C.c_double), ("r_min", C.c_double),
+                ("alpha_grid", C.POINTER(C.c_double)), ("psi4_grid", C.POINTER(C.c_double))]
 
 
 class _Grid(C.Structure):
@@ -119,6 +120,10 @@ class Problem:
     p_atm: float = 1e-12
     recon: int = RECON_MC
     ct: int = 0
+    # metric STORED: lapse and psi^4 at the cell centres with 2 ghost layers
+    # on every active axis, arrays [z][y][x]
+    alpha_grid: np.ndarray = None
+    psi4_grid: np.ndarray = None
     _c: _Problem = field(default=None, init=False, repr=False)
 
     def c(self) -> _Problem:
@@ -140,6 +145,15 @@ class Problem:
         p.p_atm = self.p_atm
         p.recon = int(self.recon)
         p.ct = int(self.ct)
+        if self.metric == STORED:
+            shape = tuple(self.n[d] + (4 if self.n[d] > 1 else 0) for d in (2, 1, 0))
+            self._keep = [np.ascontiguousarray(self.alpha_grid, dtype=np.float64),
+                          np.ascontiguousarray(self.psi4_grid, dtype=np.float64)]
+            for a in self._keep:
+                if a.shape != shape:
+                    raise ValueError("stored metric arrays must have shape %s" % (shape,))
+            p.metric.alpha_grid = _ptr(self._keep[0])
+            p.metric.psi4_grid = _ptr(self._keep[1])
         return p
 
     @property

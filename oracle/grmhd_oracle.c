@@ -89,13 +89,14 @@ static void inv3(const double a[3][3], double r[3][3])
     r[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / d;
 }
 
+static void geom_build(double alpha, double psi4, const double *dalpha, const double *dpsi4, geom *G);
+
 static void geom_at(const orc_metric *m, double x, double y, double z, geom *G)
 {
     double alpha = 1.0, psi4 = 1.0;
     double dalpha[3] = {0.0, 0.0, 0.0}, dpsi4[3] = {0.0, 0.0, 0.0};
-    int i, j, mu, nu;
+    int i;
 
-    memset(G, 0, sizeof *G);
     if (m->kind == ORC_ISO_SCHW) {
         double xs[3] = {x, y, z};
         double r = sqrt(x * x + y * y + z * z);
@@ -128,6 +129,15 @@ static void geom_at(const orc_metric *m, double x, double y, double z, geom *G)
         }
     }
 
+    geom_build(alpha, psi4, dalpha, dpsi4, G);
+}
+
+/* The static metric with zero shift, lapse alpha and spatial metric
+ * psi4 delta_ij, with the spatial derivatives of alpha and psi4. */
+static void geom_build(double alpha, double psi4, const double *dalpha, const double *dpsi4, geom *G)
+{
+    int i, j, mu, nu;
+    memset(G, 0, sizeof *G);
     G->alpha = alpha;
     for (i = 0; i < 3; i++)
         G->beta[i] = 0.0;
@@ -175,6 +185,77 @@ static void geom_at(const orc_metric *m, double x, double y, double z, geom *G)
         for (j = 0; j < 3; j++)
             G->dg[i + 1][j + 1][j + 1] = dpsi4[i];
     }
+}
+
+/* A stored metric (ORC_STORED): the value of a ghosted centre array at cell
+ * (i, j, k) of the grid (indices down to -2 on active axes). */
+static double stored_at(const orc_grid *g, const double *a, int i, int j, int k)
+{
+    int gx = g->n[0] > 1 ? 2 : 0, gy = g->n[1] > 1 ? 2 : 0, gz = g->n[2] > 1 ? 2 : 0;
+    long long px = g->n[0] + 2 * gx, py = g->n[1] + 2 * gy;
+    return a[((long long)(k + gz) * py + (j + gy)) * px + (i + gx)];
+}
+
+/* Along axis d from cell (i, j, k): the value s cells away. */
+static double stored_off(const orc_grid *g, const double *a, int d, int i, int j, int k, int s)
+{
+    int ix[3] = {i, j, k};
+    ix[d] += s;
+    return stored_at(g, a, ix[0], ix[1], ix[2]);
+}
+
+/* Metric at the centre of cell (i, j, k): analytic, or for a stored metric
+ * the stored values with fourth-order central differences
+ * (a_{i-2} - 8 a_{i-1} + 8 a_{i+1} - a_{i+2}) / (12 dx) for the derivatives
+ * (zero along an inactive axis). */
+static void geom_cell(const orc_problem *pb, int i, int j, int k, geom *G)
+{
+    const orc_grid *g = &pb->grid;
+    const orc_metric *m = &pb->metric;
+    double da[3], dp[3];
+    int d;
+    if (m->kind != ORC_STORED) {
+        /* the cell centres, evaluated as everywhere else in this file */
+        geom_at(m, g->lo[0] + (i + 0.5) * ((g->hi[0] - g->lo[0]) / g->n[0]),
+                g->lo[1] + (j + 0.5) * ((g->hi[1] - g->lo[1]) / g->n[1]),
+                g->lo[2] + (k + 0.5) * ((g->hi[2] - g->lo[2]) / g->n[2]), G);
+        return;
+    }
+    for (d = 0; d < 3; d++) {
+        double dx = (g->hi[d] - g->lo[d]) / g->n[d];
+        da[d] = dp[d] = 0.0;
+        if (g->n[d] == 1)
+            continue;
+        da[d] = (stored_off(g, m->alpha_grid, d, i, j, k, -2) - 8.0 * stored_off(g, m->alpha_grid, d, i, j, k, -1)
+                 + 8.0 * stored_off(g, m->alpha_grid, d, i, j, k, 1) - stored_off(g, m->alpha_grid, d, i, j, k, 2))
+                / (12.0 * dx);
+        dp[d] = (stored_off(g, m->psi4_grid, d, i, j, k, -2) - 8.0 * stored_off(g, m->psi4_grid, d, i, j, k, -1)
+                 + 8.0 * stored_off(g, m->psi4_grid, d, i, j, k, 1) - stored_off(g, m->psi4_grid, d, i, j, k, 2))
+                / (12.0 * dx);
+    }
+    geom_build(stored_at(g, m->alpha_grid, i, j, k), stored_at(g, m->psi4_grid, i, j, k), da, dp, G);
+}
+
+/* Metric at face fi[d] along d (between cells fi[d]-1 and fi[d]; position
+ * pos): analytic, or for a stored metric the fourth-order interpolation
+ * (-a_{f-2} + 9 a_{f-1} + 9 a_f - a_{f+1}) / 16 of the stored values. */
+static void geom_face(const orc_problem *pb, int d, const int *fi, const double *pos, geom *G)
+{
+    const orc_grid *g = &pb->grid;
+    const orc_metric *m = &pb->metric;
+    static const double zero[3] = {0.0, 0.0, 0.0};
+    double a, p;
+    if (m->kind != ORC_STORED) {
+        geom_at(m, pos[0], pos[1], pos[2], G);
+        return;
+    }
+    a = (-stored_off(g, m->alpha_grid, d, fi[0], fi[1], fi[2], -2) + 9.0 * stored_off(g, m->alpha_grid, d, fi[0], fi[1], fi[2], -1)
+         + 9.0 * stored_off(g, m->alpha_grid, d, fi[0], fi[1], fi[2], 0) - stored_off(g, m->alpha_grid, d, fi[0], fi[1], fi[2], 1))
+        / 16.0;
+    p = (-stored_off(g, m->psi4_grid, d, fi[0], fi[1], fi[2], -2) + 9.0 * stored_off(g, m->psi4_grid, d, fi[0], fi[1], fi[2], -1)
+         + 9.0 * stored_off(g, m->psi4_grid, d, fi[0], fi[1], fi[2], 0) - stored_off(g, m->psi4_grid, d, fi[0], fi[1], fi[2], 1))
+        / 16.0;
+    geom_build(a, p, zero, zero, G);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -725,7 +806,7 @@ int orc_prim2con(const orc_problem *pb, const double *P, double *U)
                 state s;
                 double q[9], u[9];
                 long long c = cidx(g, i, j, k);
-                geom_at(&pb->metric, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k), &G);
+                geom_cell(pb, i, j, k, &G);
                 load_prim(g, P, i, j, k, q);
                 state_from_prim(&G, pb->gamma, q, &s);
                 cons_from_state(&G, &s, u);
@@ -751,7 +832,7 @@ static int con2prim_grid(const orc_problem *pb, double *U, const double *Pg, dou
                 geom G;
                 double u[9], pg[9], p[9];
                 long long c = cidx(g, i, j, k);
-                geom_at(&pb->metric, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k), &G);
+                geom_cell(pb, i, j, k, &G);
                 for (v = 0; v < 9; v++) {
                     u[v] = U[v * N + c];
                     pg[v] = Pg[v * N + c];
@@ -950,7 +1031,7 @@ int orc_rhs(const orc_problem *pb, const double *P, double *R)
                     }
                     for (s = 0; s < 3; s++)
                         pos[s] = (s == d) ? g->lo[s] + fi[s] * dx : centre(g, s, fi[s]);
-                    geom_at(&pb->metric, pos[0], pos[1], pos[2], &G);
+                    geom_face(pb, d, fi, pos, &G);
                     face_flux(&G, pb->gamma, pb->c_h, pb->ct, d, qL, qR, F);
                     for (v = 0; v < 9; v++)
                         Fd[v * NF + fc] = F[v];
@@ -1008,7 +1089,7 @@ int orc_rhs(const orc_problem *pb, const double *P, double *R)
                     state s;
                     double q[9], S[9];
                     long long c = cidx(g, i, j, k);
-                    geom_at(&pb->metric, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k), &G);
+                    geom_cell(pb, i, j, k, &G);
                     load_prim(g, P, i, j, k, q);
                     state_from_prim(&G, pb->gamma, q, &s);
                     source_from_state(&G, &s, pb->kappa, S);

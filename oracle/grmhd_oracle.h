@@ -31,7 +31,7 @@ extern "C" {
 
 #define ORC_NVAR 9
 
-enum { ORC_FLAT = 0, ORC_ISO_SCHW = 1 };
+enum { ORC_FLAT = 0, ORC_ISO_SCHW = 1, ORC_STORED = 2 };
 enum { ORC_SOFT_SQRT = 0, ORC_SOFT_MAX = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
 enum { ORC_RECON_MC = 0, ORC_RECON_PPM = 1 };
@@ -40,10 +40,16 @@ enum { ORC_RECON_MC = 0, ORC_RECON_PPM = 1 };
 enum { ORC_FLAG_FAIL = 1, ORC_FLAG_ATM = 2, ORC_FLAG_PFLOOR = 4 };
 
 typedef struct {
-    int kind;       /* ORC_FLAT or ORC_ISO_SCHW                         */
+    int kind;       /* ORC_FLAT, ORC_ISO_SCHW or ORC_STORED (grids only) */
     int soft;       /* radius softening: ORC_SOFT_SQRT or ORC_SOFT_MAX   */
     double M;       /* mass parameter (G = c = 1)                        */
     double r_min;   /* softening radius                                  */
+    /* ORC_STORED: a static, conformally flat metric with zero shift given
+     * by its lapse and conformal factor psi^4 at the cell centres of the
+     * grid and of 2 ghost layers on every active axis ([z][y][x], x
+     * fastest, n + 4 per active axis, n otherwise).                      */
+    const double *alpha_grid;
+    const double *psi4_grid;
 } orc_metric;
 
 typedef struct {

@@ -419,3 +419,49 @@ def direction(w: Workload, i: int, k: int = 0) -> np.ndarray:
     scale = np.abs(flat).max(axis=1)
     scale[flat.max(axis=1) == flat.min(axis=1)] = 0.0
     return rng.standard_normal(w.P.shape) * scale.reshape(9, 1, 1, 1)
+
+
+def ghosted_centres(n, lo, hi):
+    """Cell-centre coordinates including 2 ghost layers on every active axis
+    (z, y, x order broadcastable to [nz+4, ny+4, nx+4] for a 3D grid)."""
+    xs = []
+    for d in range(3):
+        g = 2 if n[d] > 1 else 0
+        xs.append(lo[d] + (np.arange(-g, n[d] + g) + 0.5) * (hi[d] - lo[d]) / n[d])
+    return (xs[0][None, None, :], xs[1][None, :, None], xs[2][:, None, None])
+
+
+def stored_metric(n, lo, hi, k: int = 0, bc=(OUTFLOW, OUTFLOW, OUTFLOW)):
+    """A smooth static, conformally flat metric given on the grid (the input of
+    the stored-metric form): lapse alpha = 1 - a exp(-s^2 / w^2) and conformal
+    factor psi^4 = (1 + b exp(-s^2 / w^2))^4 with seeded a in [0.05, 0.2],
+    b in [0.02, 0.1], a centre c inside the box and width w a third of the
+    box; s is the distance to c, measured along a periodic axis of length L as
+    (L / pi) sin(pi (x - c) / L) so that the metric is periodic there.  Sampled
+    at the cell centres and 2 ghost layers on every active axis; the ghost
+    layers of a periodic axis are copies of the opposite interior cells.
+    Arrays [z][y][x]."""
+    rng = rng_for(60, k)
+    a, b = rng.uniform(0.05, 0.2), rng.uniform(0.02, 0.1)
+    c = [lo[d] + rng.uniform(0.3, 0.7) * (hi[d] - lo[d]) for d in range(3)]
+    w = max(hi[d] - lo[d] for d in range(3) if n[d] > 1) / 3.0
+    X = ghosted_centres(n, lo, hi)
+    r2 = 0.0
+    for d in range(3):
+        if n[d] <= 1:
+            continue
+        L = hi[d] - lo[d]
+        s = (L / np.pi) * np.sin(np.pi * (X[d] - c[d]) / L) if bc[d] == PERIODIC else X[d] - c[d]
+        r2 = r2 + s * s
+    bump = np.exp(-r2 / (w * w))
+    shape = tuple(n[d] + (4 if n[d] > 1 else 0) for d in (2, 1, 0))
+    out = []
+    for f in (1.0 - a * bump, (1.0 + b * bump) ** 4):
+        f = np.broadcast_to(f, shape).copy()
+        for d in range(3):
+            if n[d] > 1 and bc[d] == PERIODIC:
+                ax = 2 - d
+                idx = (np.arange(-2, n[d] + 2) % n[d]) + 2
+                f = np.take(f, idx, axis=ax)
+        out.append(np.ascontiguousarray(f))
+    return out[0], out[1]

@@ -1,0 +1,88 @@
+"""Pins of the oracle's stored-array metric (the metric of section 2.1 given
+on the grid instead of in closed form: lapse and psi^4 at the cell centres
+with two ghost layers; face values by fourth-order interpolation, centre
+derivatives by fourth-order central differences), each against something
+other than the oracle: a flat stored metric reproduces the flat spacetime
+bitwise; the isotropic metric of the curved workload, sampled on the grid
+by a formula written here, converges to the closed-form metric at fourth
+order; mass, energy and field totals are conserved in a periodic box; a
+static fluid has exactly zero mass and energy right-hand sides."""
+import numpy as np
+import pytest
+
+from paper_1102_5202_amd import workloads as WL
+
+
+def _problem(orc, w, alpha=None, psi4=None, **over):
+    kw = w.problem_kwargs()
+    kw.update(over)
+    if alpha is not None:
+        kw.update(metric=orc.STORED, alpha_grid=alpha, psi4_grid=psi4)
+    return orc.Problem(**kw)
+
+
+def _flat(n):
+    shape = tuple(n[d] + (4 if n[d] > 1 else 0) for d in (2, 1, 0))
+    return np.ones(shape), np.ones(shape)
+
+
+@pytest.mark.parametrize("w", [WL.config2(n=(10, 9, 8), nsteps=3), WL.config1(2, n=120)],
+                         ids=["periodic3d", "riemann1d"])
+def test_flat_stored_metric_is_flat_bitwise(orc, w):
+    a, p = _flat(w.n)
+    ref = orc.step(_problem(orc, w), orc.prim2con(_problem(orc, w), w.P), w.P, w.dt, 3)
+    pb = _problem(orc, w, a, p)
+    got = orc.step(pb, orc.prim2con(pb, w.P), w.P, w.dt, 3)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def _iso_sampled(n, lo, hi, M=1.0, r_min=1.0):
+    """The isotropic Schwarzschild metric with softened radius sqrt(r^2 + r_min^2)
+    (the curved workload's) at the ghosted cell centres."""
+    X = WL.ghosted_centres(n, lo, hi)
+    rs = np.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2 + r_min ** 2)
+    h = M / (2.0 * rs)
+    shape = tuple(n[d] + (4 if n[d] > 1 else 0) for d in (2, 1, 0))
+    return (np.broadcast_to((1 - h) / (1 + h), shape).copy(),
+            np.broadcast_to((1 + h) ** 4, shape).copy())
+
+
+def test_sampled_isotropic_metric_converges_at_fourth_order(orc):
+    """Smooth data off the origin in the curved metric: the right-hand side with
+    the metric sampled on the grid approaches the closed-form one at fourth
+    order (interpolation to faces and differences for the sources)."""
+    errs = []
+    for n in (8, 16, 32):
+        w = WL.smooth_box(n=(n, n, n), metric=WL.ISO_SCHW)
+        ref = orc.rhs(_problem(orc, w), w.P)
+        a, p = _iso_sampled(w.n, w.lo, w.hi, w.M, w.r_min)
+        got = orc.rhs(_problem(orc, w, a, p), w.P)
+        errs.append(np.abs(got[:8] - ref[:8]).sum() / np.abs(ref[:8]).sum())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 3.5), (errs, orders)
+
+
+def test_conservation_in_a_periodic_box(orc):
+    """Mass, energy and the densitised field have no source in a static metric:
+    their totals are conserved to round-off under a stored metric too."""
+    w = WL.config2(n=(10, 9, 8), nsteps=3)
+    a, p = WL.stored_metric(w.n, w.lo, w.hi, k=1, bc=w.bc)
+    pb = _problem(orc, w, a, p)
+    U0 = orc.prim2con(pb, w.P)
+    U, P, st = orc.step(pb, U0, w.P, w.dt, w.nsteps)
+    assert st["fail"] == 0
+    for v in (0, 1, 5, 6, 7):
+        scale = np.abs(U0[v]).sum()
+        assert abs(U[v].sum() - U0[v].sum()) <= 2e-14 * scale * w.nsteps, v
+    ref = orc.step(_problem(orc, w), orc.prim2con(_problem(orc, w), w.P), w.P, w.dt, w.nsteps)[0]
+    assert np.abs(U[2:5] - ref[2:5]).max() > 1e-6          # the metric did act on the momenta
+
+
+def test_static_fluid_has_zero_mass_and_energy_rhs(orc):
+    w = WL.config2(n=(10, 9, 8), nsteps=1)
+    P = np.zeros_like(w.P)
+    P[0], P[1] = 1.0, 0.1                                # uniform, at rest, no field
+    a, p = WL.stored_metric(w.n, w.lo, w.hi, k=2, bc=w.bc)
+    R = orc.rhs(_problem(orc, w, a, p), P)
+    assert np.all(R[0] == 0.0) and np.all(R[1] == 0.0)
+    assert np.abs(R[2:5]).max() > 0.0                     # gravity acts on the momenta
