@@ -355,8 +355,10 @@ def main(argv=None) -> int:
     nsub = w.rk_order
     P0 = torch.from_numpy(w.P).to(dev)
 
-    def timed_run(precision, **over):
+    def timed_run(precision, stored=None, **over):
         s = grmhd.solver_for(w, device=dev, timing=not args.no_timing, precision=precision, **over)
+        if stored is not None:
+            s.set_metric(*stored)
         U = s.cons(P0)
         for _ in range(args.warmup):
             s.step(U, w.dt)
@@ -432,10 +434,14 @@ def main(argv=None) -> int:
     if not args.no_variants and fp64:
         # scheme variants on the same workload: the recovery's one-unknown
         # iteration; PPM reconstruction and flux-CT (three face kernels, for
-        # flux-CT the edge and face corrections, then the cell update)
+        # flux-CT the edge and face corrections, then the cell update); the
+        # same spacetime given on the grid (stored metric)
         out["variants"] = {}
+        alpha, psi4 = workloads.sampled_isotropic_metric(w.n, w.lo, w.hi, w.M, w.r_min)
+        stored = (torch.from_numpy(alpha).to(dev), torch.from_numpy(psi4).to(dev))
         for name, over in (("recovery_1d", {"recovery": "1d"}), ("ppm", {"reconstruction": "ppm"}),
-                           ("fluxct", {"divergence": "fluxct"})):
+                           ("fluxct", {"divergence": "fluxct"}),
+                           ("stored_metric", {"metric": grmhd.STORED, "stored": stored})):
             v = timed_run("fp64", **over)
             out["variants"][name] = {
                 "value": v["value"], "ms_per_step": v["ms_per_step"], "recovery": v["recovery"],

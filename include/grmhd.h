@@ -60,7 +60,7 @@ typedef enum {
     GRMHD_ERR_NO_ADJOINT = -5  /* adjoint call on a context made without opts.adjoint (FP64) */
 } grmhd_error;
 
-typedef enum { GRMHD_METRIC_FLAT = 0, GRMHD_METRIC_ISO_SCHW = 1 } grmhd_metric_kind;
+typedef enum { GRMHD_METRIC_FLAT = 0, GRMHD_METRIC_ISO_SCHW = 1, GRMHD_METRIC_STORED = 2 } grmhd_metric_kind;
 typedef enum { GRMHD_SOFT_SQRT = 0, GRMHD_SOFT_MAX = 1 } grmhd_soft_kind;
 typedef enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1 } grmhd_bc_kind;
 typedef enum { GRMHD_EOS_IDEAL = 0 } grmhd_eos_kind;
@@ -77,7 +77,10 @@ typedef enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 } grmhd_precision;
  * without shift: alpha = (1 - M/(2 r_s))/(1 + M/(2 r_s)), gamma_ij = psi^4
  * delta_ij, psi = 1 + M/(2 r_s), with the radius softened near the origin:
  * r_s = sqrt(r^2 + r_min^2) (SQRT) or max(r, r_min) (MAX).  Requires
- * r_min > M/2 so that alpha > 0 everywhere. */
+ * r_min > M/2 so that alpha > 0 everywhere.  STORED is any static,
+ * conformally flat metric with zero shift given on the grid: its lapse and
+ * psi^4 at the cell centres, set with grmhd_set_metric() (M, soft and r_min
+ * are ignored). */
 typedef struct {
     int kind;       /* grmhd_metric_kind */
     int soft;       /* grmhd_soft_kind   */
@@ -216,6 +219,24 @@ int grmhd_cons(grmhd_ctx *ctx, const double *P, double *U);
  * primitives of U must be in the context's cache (set by grmhd_cons,
  * grmhd_prim or the previous grmhd_step).  Asynchronous; graph-capturable. */
 int grmhd_step(grmhd_ctx *ctx, double *U, double dt);
+
+/* The metric of a STORED context (section 2.1: the spacetime is given).
+ * alpha and psi4 (device, double, read during the call only) hold the lapse
+ * and the conformal factor psi^4 (gamma_ij = psi^4 delta_ij, zero shift) at
+ * the cell centres of the grid and of 2 ghost layers on every active axis:
+ * dense [nz+2gz][ny+2gy][nx+2gx], x fastest, g = 2 on an axis with n > 1
+ * and 0 otherwise; both must be positive (on a periodic axis the ghost
+ * layers must repeat the opposite interior cells).  The library writes the
+ * centre values, their fourth-order central differences along every active
+ * axis (for the metric sources) and their fourth-order interpolation to
+ * every face (for the fluxes) into buf, a caller-owned device buffer of
+ * grmhd_metric_bytes(grid) bytes, 256-byte aligned, that must stay alive
+ * while the context is used.  Must precede grmhd_cons, grmhd_prim,
+ * grmhd_rhs and grmhd_step on a STORED context (GRMHD_ERR_STATE otherwise);
+ * GRMHD_ERR_ARG on any other context, GRMHD_ERR_WORKSPACE for a buffer too
+ * small or misaligned.  Asynchronous on the context's stream. */
+size_t grmhd_metric_bytes(const grmhd_grid *grid);
+int grmhd_set_metric(grmhd_ctx *ctx, const double *alpha, const double *psi4, void *buf, size_t buf_bytes);
 
 /* Primitives from conserved variables by Newton-Raphson (section 2.2: the
  * inversion is not algebraic), followed by the atmosphere and floor policy.

@@ -139,6 +139,26 @@ Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int 
     return L;
 }
 
+// The stored-metric buffer: centre values [8][N], then face values [2][nf]
+// of every active axis, each part 256-byte aligned.
+size_t metric_layout(const grmhd_grid* g, size_t off_mf[3])
+{
+    long long N = (long long)g->n[0] * g->n[1] * g->n[2];
+    size_t off = round_up(sizeof(double) * 8 * (size_t)N, 256);
+    for (int d = 0; d < 3; ++d) {
+        long long nf = 0;
+        if (g->n[d] > 1) {
+            nf = 1;
+            for (int e = 0; e < 3; ++e)
+                nf *= g->n[e] + (e == d ? 1 : 0);
+        }
+        if (off_mf)
+            off_mf[d] = off;
+        off = round_up(off + sizeof(double) * 2 * (size_t)nf, 256);
+    }
+    return off;
+}
+
 bool wants_adjoint(const grmhd_opts* o)
 {
     return o && o->adjoint && o->precision == GRMHD_FP64;
@@ -200,6 +220,9 @@ struct grmhd_ctx {
     void* Us = nullptr;                     // intermediate stage state (cache type)
     void* F[3] = {nullptr, nullptr, nullptr};
     void* W[3] = {nullptr, nullptr, nullptr};   // flux-CT edge values
+    // stored metric: set by grmhd_set_metric (kernels read d.mc, d.mf)
+    bool metric_ok = true;
+    grmhd_grid grid{};
     // cache b has its ghost slabs filled: every kernel that writes a cache
     // (cons, prim, the updates) writes the ghost images of its cells as well
     bool ghosts_ok[3] = {false, false, false};
@@ -652,8 +675,11 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     *out = nullptr;
     if (!grid_ok(grid))
         return GRMHD_ERR_ARG;
-    if (metric->kind != GRMHD_METRIC_FLAT && metric->kind != GRMHD_METRIC_ISO_SCHW)
+    if (metric->kind != GRMHD_METRIC_FLAT && metric->kind != GRMHD_METRIC_ISO_SCHW &&
+        metric->kind != GRMHD_METRIC_STORED)
         return GRMHD_ERR_ARG;
+    if (metric->kind == GRMHD_METRIC_STORED && opts->adjoint)
+        return GRMHD_ERR_ARG;   // the adjoint kernels take the closed-form metrics
     if (metric->kind == GRMHD_METRIC_ISO_SCHW) {
         if (metric->soft != GRMHD_SOFT_SQRT && metric->soft != GRMHD_SOFT_MAX)
             return GRMHD_ERR_ARG;
@@ -689,7 +715,10 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     if (!c)
         return GRMHD_ERR_ARG;
     c->L = L;
-    c->kind = metric->kind == GRMHD_METRIC_FLAT ? grmhd::FLAT : grmhd::ISO;
+    c->kind = metric->kind == GRMHD_METRIC_FLAT ? grmhd::FLAT
+              : (metric->kind == GRMHD_METRIC_ISO_SCHW ? grmhd::ISO : grmhd::STORED);
+    c->metric_ok = c->kind != grmhd::STORED;
+    c->grid = *grid;
     c->rk_order = opts->rk_order;
     c->timing = opts->timing;
     c->mixed = opts->precision == GRMHD_MIXED;
@@ -769,6 +798,8 @@ int grmhd_cons(grmhd_ctx* c, const double* P, double* U)
 {
     if (!c || !P || !U)
         return GRMHD_ERR_ARG;
+    if (!c->metric_ok)
+        return GRMHD_ERR_STATE;
     return c->mixed ? cons_t<float>(c, P, U) : cons_t<double>(c, P, U);
 }
 
@@ -776,13 +807,46 @@ int grmhd_prim(grmhd_ctx* c, const double* U, double* P)
 {
     if (!c || !U || !P)
         return GRMHD_ERR_ARG;
+    if (!c->metric_ok)
+        return GRMHD_ERR_STATE;
     return c->mixed ? prim_t<float>(c, U, P) : prim_t<double>(c, U, P);
+}
+
+size_t grmhd_metric_bytes(const grmhd_grid* grid)
+{
+    if (!grid_ok(grid))
+        return 0;
+    return metric_layout(grid, nullptr);
+}
+
+int grmhd_set_metric(grmhd_ctx* c, const double* alpha, const double* psi4, void* buf, size_t buf_bytes)
+{
+    if (!c || !alpha || !psi4 || !buf)
+        return GRMHD_ERR_ARG;
+    if (c->kind != grmhd::STORED)
+        return GRMHD_ERR_ARG;
+    size_t off_mf[3];
+    if (buf_bytes < metric_layout(&c->grid, off_mf) || ((uintptr_t)buf) % 256 != 0)
+        return GRMHD_ERR_WORKSPACE;
+    unsigned char* b = (unsigned char*)buf;
+    c->d.mc = (const double*)b;
+    double* mf[3];
+    for (int d = 0; d < 3; ++d) {
+        mf[d] = c->d.nf[d] ? (double*)(b + off_mf[d]) : nullptr;
+        c->d.mf[d] = mf[d];
+    }
+    if (grmhd::launch_metric(alpha, psi4, (double*)b, mf, c->d, c->stream) != hipSuccess)
+        return GRMHD_ERR_HIP;
+    c->metric_ok = true;
+    return GRMHD_OK;
 }
 
 int grmhd_rhs(grmhd_ctx* c, const double* P, double* R)
 {
     if (!c || !P || !R)
         return GRMHD_ERR_ARG;
+    if (!c->metric_ok)
+        return GRMHD_ERR_STATE;
     return c->mixed ? rhs_t<float>(c, P, R) : rhs_t<double>(c, P, R);
 }
 

@@ -10,7 +10,7 @@
 
 namespace grmhd {
 
-enum { FLAT = 0, ISO = 1 };
+enum { FLAT = 0, ISO = 1, STORED = 2 };
 
 // Per-launch constants (passed by value as a kernel argument).
 struct Dev {
@@ -34,6 +34,10 @@ struct Dev {
     int c2p1d;       // recovery: 0 Newton on (Wc, v^2), 1 Newton on Wc alone
     int ppm;         // reconstruction: 0 MC (2 ghosts), 1 PPM (3 ghosts)
     int ct;          // divergence control: 0 cleaning (Phi), 1 flux-CT (Phi carried)
+    // stored metric: at cell centres [8][N] (alpha, psi^4, d_x,y,z alpha,
+    // d_x,y,z psi^4), at the faces of axis a [2][nf[a]] (alpha, psi^4)
+    const double* mc;
+    const double* mf[3];
 };
 
 // Geometry at one point.
@@ -70,6 +74,19 @@ __device__ __forceinline__ Geo geo_from_h(double h, double& i1h)
     g.sqrtg = g.psi4 * psi2;
     g.sqrtmg = g.alpha * g.sqrtg;
     g.isqrtmg = im1h * i1h * g.ipsi4;     // 1 / ((1 - h) (1 + h)^5)
+    return g;
+}
+
+// The geometry of a static, conformally flat metric from its lapse and psi^4.
+__device__ __forceinline__ Geo geo_from_ap(double alpha, double psi4)
+{
+    Geo g;
+    g.alpha = alpha;
+    g.psi4 = psi4;
+    g.ipsi4 = 1.0 / psi4;
+    g.sqrtg = psi4 * sqrt(psi4);
+    g.sqrtmg = alpha * g.sqrtg;
+    g.isqrtmg = 1.0 / g.sqrtmg;
     return g;
 }
 
@@ -110,6 +127,24 @@ __device__ __forceinline__ Geo geo_deriv(const Dev& d, double x, double y, doubl
     ka = 2.0 * hr2 * i1h * i1h;
     kp = -4.0 * psi * psi * psi * hr2;
     return g;
+}
+
+// Geometry at face f of axis D (position x, y, z) and at the centre of cell c
+// (position x, y, z): closed form, or the stored values.
+template <int D, int KIND>
+__device__ __forceinline__ Geo face_geo(const Dev& d, double x, double y, double z, long long f)
+{
+    if (KIND == STORED)
+        return geo_from_ap(d.mf[D][f], d.mf[D][d.nf[D] + f]);
+    return geo_at<KIND>(d, x, y, z);
+}
+
+template <int KIND>
+__device__ __forceinline__ Geo cell_geo(const Dev& d, double x, double y, double z, long long c)
+{
+    if (KIND == STORED)
+        return geo_from_ap(d.mc[c], d.mc[d.N + c]);
+    return geo_at<KIND>(d, x, y, z);
 }
 
 // The face physics below is written for a scalar type T: double for the FP64
@@ -272,10 +307,10 @@ __device__ __forceinline__ bool finite(double x)
 // (positions x, y, z), the 9 components Fo of the numerical flux: exact
 // (Bd^n, Phi) cleaning pair, then HLLE on the rest.
 template <int D, int KIND, typename T>
-__device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, double z, const Dev& d,
-                                          T* Fo)
+__device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, double z, long long f,
+                                          const Dev& d, T* Fo)
 {
-    const GeoT<T> g = geo_cast<T>(geo_at<KIND>(d, x, y, z));
+    const GeoT<T> g = geo_cast<T>(face_geo<D, KIND>(d, x, y, z, f));
     const T half = T(0.5), ch = (T)d.c_h, ich = (T)d.ic_h;
 
     // cleaning pair: exact solution of the linear (Bd^n, Phi) Riemann problem
@@ -332,9 +367,28 @@ __device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, doub
 // the cleaning scalar.  The source is evaluated in T; the centre geometry is
 // returned in g (double, for the recovery).
 template <int KIND, typename T>
-__device__ __forceinline__ void add_sources(const Dev& d, double x, double y, double z, const T* q,
-                                            Geo& g, double* R)
+__device__ __forceinline__ void add_sources(const Dev& d, double x, double y, double z, long long c,
+                                            const T* q, Geo& g, double* R)
 {
+    if (KIND == STORED) {
+        // the stored derivatives d_j alpha, d_j psi^4 along each axis
+        g = geo_from_ap(d.mc[c], d.mc[d.N + c]);
+        const GeoT<T> gt = geo_cast<T>(g);
+        Kin<T> kk = kinematics(q, gt, (T)d.gfac);
+        T ia2 = T(1) / (gt.alpha * gt.alpha);
+        T Ttt = (kk.wtot * kk.W * kk.W - kk.ptot) * ia2 - kk.bt * kk.bt;
+        T uu = q[2] * q[2] + q[3] * q[3] + q[4] * q[4];
+        T bb = kk.b[0] * kk.b[0] + kk.b[1] * kk.b[1] + kk.b[2] * kk.b[2];
+        T Tkk = kk.wtot * uu + T(3) * kk.ptot * gt.ipsi4 - bb;
+        T h = T(0.5) * gt.sqrtmg;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            R[2 + j] += (double)(h * (-T(2) * gt.alpha * Ttt * (T)d.mc[(2 + j) * d.N + c]
+                                      + Tkk * (T)d.mc[(5 + j) * d.N + c]));
+        if (!d.ct)
+            R[8] -= d.kappa * (double)q[8];
+        return;
+    }
     double ka, kp;
     g = geo_deriv<KIND>(d, x, y, z, ka, kp);
     if (KIND != FLAT) {

@@ -25,6 +25,10 @@ template <typename T>
 hipError_t launch_ghosts(T* Pc, const Dev& d, hipStream_t s);
 template <typename T>
 hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipStream_t s);
+// Stored metric: the caller's ghosted centre arrays to the centre [8][N] and
+// face [2][nf] values the kernels read.
+hipError_t launch_metric(const double* alpha, const double* psi4, double* mc, double* const* mf, const Dev& d,
+                         hipStream_t s);
 // Flux-CT: the field fluxes of all active axes (F[3]) replaced from the edge
 // values W[3] of the axis pairs (x,y), (x,z), (y,z).
 template <typename T>

@@ -99,7 +99,7 @@ __device__ __forceinline__ void face_store(T* qL, T* qR, double x, double y, dou
                                            T* __restrict__ F, long long NF, long long f)
 {
     T Fo[9];
-    face_flux<D, KIND>(qL, qR, x, y, z, d, Fo);
+    face_flux<D, KIND>(qL, qR, x, y, z, f, d, Fo);
 #pragma unroll
     for (int v = 0; v < 9; ++v)
         F[v * NF + f] = Fo[v];
@@ -365,7 +365,7 @@ __device__ __forceinline__ void rhs_cell(const Dev& d, const T* __restrict__ Fx,
             R[v] -= ((double)Fz[v * d.nf[2] + c + nxy] - (double)Fz[v * d.nf[2] + c]) * d.idx[2];
     }
     add_sources<KIND>(d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
-                      d.lo[2] + (k + 0.5) * d.dx[2], q, g, R);
+                      d.lo[2] + (k + 0.5) * d.dx[2], c, q, g, R);
 }
 
 // Per-thread counts reduced over the wave, one atomic per wave and counter
@@ -562,7 +562,8 @@ __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
                 qb[v] = qc[v];
                 qc[v] = qd;
             }
-            face_flux<2, KIND>(qL, qR, x, y, d.lo[2] + k0 * d.dx[2], d, Fp);
+            face_flux<2, KIND>(qL, qR, x, y, d.lo[2] + k0 * d.dx[2],
+                               i + (long long)d.n[0] * (j + (long long)d.n[1] * k0), d, Fp);
         }
         // window now: qb = q_k0, qc = q_{k0+1}, sc = slope of cell k0
         for (int k = k0; k < k1; ++k) {
@@ -580,7 +581,8 @@ __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
                 qc[v] = qd;
             }
             const double z = d.lo[2] + (k + 0.5) * d.dx[2];
-            face_flux<2, KIND>(qL, qR, x, y, z + 0.5 * d.dx[2], d, Fc);
+            face_flux<2, KIND>(qL, qR, x, y, z + 0.5 * d.dx[2],
+                               i + (long long)d.n[0] * (j + (long long)d.n[1] * (k + 1)), d, Fc);
             const long long c = i + (long long)d.n[0] * (j + (long long)d.n[1] * k);
             double R[9];
 #pragma unroll
@@ -602,7 +604,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
                             d.idx[1];
             }
             Geo g;
-            add_sources<KIND>(d, x, y, z, q, g, R);
+            add_sources<KIND>(d, x, y, z, c, q, g, R);
             int iters = 0;
             const long long pc = col + (long long)(k + d.g[2]) * st;
             int flags = stage_cell(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
@@ -656,8 +658,8 @@ __global__ __launch_bounds__(BLOCK) void k_cons(const double* __restrict__ P, do
         q[v] = P[v * d.N + c];
     store_prim(d, Pc, pc, i, j, k, q);
     if (U) {
-        const GeoT<double> g = geo_cast<double>(geo_at<KIND>(
-            d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1], d.lo[2] + (k + 0.5) * d.dx[2]));
+        const GeoT<double> g = geo_cast<double>(cell_geo<KIND>(
+            d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1], d.lo[2] + (k + 0.5) * d.dx[2], c));
         Kin<double> kk = kinematics(q, g, d.gfac);
 #pragma unroll
         for (int v = 0; v < 8; ++v)
@@ -686,8 +688,8 @@ __global__ __launch_bounds__(BLOCK) void k_prim(const double* __restrict__ U, do
             q[v] = (double)Pc[v * d.sv + pc];
             u[v] = U[v * d.N + c];
         }
-        Geo g = geo_at<KIND>(d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
-                             d.lo[2] + (k + 0.5) * d.dx[2]);
+        Geo g = cell_geo<KIND>(d, d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
+                               d.lo[2] + (k + 0.5) * d.dx[2], c);
         int iters = 0;
         int flags = recover_cell(d, g, u, q, p, iters);
 #pragma unroll
@@ -856,7 +858,7 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
                     qL[v] = q1 + half * mc_slope(q0, q1, q2);
                     qR[v] = q2 - half * mc_slope(q1, q2, q3);
                 }
-                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, d, Fp);
+                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fp);
             }
             for (int c = c0; c < c1; ++c) {
                 T qL[9], qR[9], Fc[9], q[9];
@@ -868,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
                     qL[v] = q1 + half * mc_slope(q0, q1, q2);
                     qR[v] = q2 - half * mc_slope(q1, q2, q3);
                 }
-                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, d, Fc);
+                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
                 double R[9];
 #pragma unroll
                 for (int v = 0; v < 9; ++v) {
@@ -1000,6 +1002,74 @@ static hipError_t launch_flux_k(int dir, const T* Pc, T* F, const Dev& d, hipStr
     return hipGetLastError();
 }
 
+// Stored metric: the caller's lapse and psi^4 at the cell centres with 2
+// ghost layers on every active axis (dense [z][y][x]) to the values the
+// kernels read: at cell centres the values and the fourth-order central
+// differences (a_{i-2} - 8 a_{i-1} + 8 a_{i+1} - a_{i+2}) / (12 dx) (zero
+// along an inactive axis); at the faces of every active axis the
+// fourth-order interpolation (-a_{f-2} + 9 a_{f-1} + 9 a_f - a_{f+1}) / 16.
+__global__ __launch_bounds__(BLOCK) void k_metric(const double* __restrict__ A, const double* __restrict__ Pq,
+                                                  double* __restrict__ mc, double* __restrict__ mf0,
+                                                  double* __restrict__ mf1, double* __restrict__ mf2, Dev d)
+{
+    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    const int g[3] = {d.act[0] ? 2 : 0, d.act[1] ? 2 : 0, d.act[2] ? 2 : 0};
+    const long long sx = 1, sy = d.n[0] + 2 * g[0], sz = sy * (d.n[1] + 2 * g[1]);
+    const long long st[3] = {sx, sy, sz};
+    auto at = [&](int i, int j, int k) { return (long long)(k + g[2]) * sz + (long long)(j + g[1]) * sy + (i + g[0]); };
+    if (t < d.N) {
+        const int i = (int)(t % d.n[0]);
+        const long long r = t / d.n[0];
+        const int j = (int)(r % d.n[1]);
+        const int k = (int)(r / d.n[1]);
+        const long long c = at(i, j, k);
+        mc[t] = A[c];
+        mc[d.N + t] = Pq[c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double da = 0.0, dp = 0.0;
+            if (d.act[a]) {
+                const long long s = st[a];
+                da = (A[c - 2 * s] - 8.0 * A[c - s] + 8.0 * A[c + s] - A[c + 2 * s]) / (12.0 * d.dx[a]);
+                dp = (Pq[c - 2 * s] - 8.0 * Pq[c - s] + 8.0 * Pq[c + s] - Pq[c + 2 * s]) / (12.0 * d.dx[a]);
+            }
+            mc[(2 + a) * d.N + t] = da;
+            mc[(5 + a) * d.N + t] = dp;
+        }
+        return;
+    }
+    t -= d.N;
+    double* mf[3] = {mf0, mf1, mf2};
+    for (int a = 0; a < 3; ++a) {
+        if (!d.act[a])
+            continue;
+        if (t >= d.nf[a]) {
+            t -= d.nf[a];
+            continue;
+        }
+        const int m0 = d.n[0] + (a == 0), m1 = d.n[1] + (a == 1);
+        int ix[3];
+        ix[0] = (int)(t % m0);
+        const long long r = t / m0;
+        ix[1] = (int)(r % m1);
+        ix[2] = (int)(r / m1);
+        const long long c = at(ix[0], ix[1], ix[2]);   // cell f along a
+        const long long s = st[a];
+        mf[a][t] = (-A[c - 2 * s] + 9.0 * A[c - s] + 9.0 * A[c] - A[c + s]) / 16.0;
+        mf[a][d.nf[a] + t] = (-Pq[c - 2 * s] + 9.0 * Pq[c - s] + 9.0 * Pq[c] - Pq[c + s]) / 16.0;
+        return;
+    }
+}
+
+hipError_t launch_metric(const double* alpha, const double* psi4, double* mc, double* const* mf, const Dev& d,
+                         hipStream_t s)
+{
+    const long long total = d.N + d.nf[0] + d.nf[1] + d.nf[2];
+    hipLaunchKernelGGL(k_metric, dim3(blocks_for(total)), dim3(BLOCK), 0, s, alpha, psi4, mc, mf[0], mf[1], mf[2],
+                       d);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_ct(T* const* F, T* const* W, const Dev& d, hipStream_t s)
 {
@@ -1023,7 +1093,9 @@ hipError_t launch_ct(T* const* F, T* const* W, const Dev& d, hipStream_t s)
 template <typename T>
 hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipStream_t s)
 {
-    return kind == FLAT ? launch_flux_k<FLAT>(dir, Pc, F, d, s) : launch_flux_k<ISO>(dir, Pc, F, d, s);
+    if (kind == FLAT)
+        return launch_flux_k<FLAT>(dir, Pc, F, d, s);
+    return kind == ISO ? launch_flux_k<ISO>(dir, Pc, F, d, s) : launch_flux_k<STORED>(dir, Pc, F, d, s);
 }
 
 template <typename T, typename TS, typename TO>
@@ -1035,9 +1107,12 @@ hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, const 
     if (kind == FLAT)
         hipLaunchKernelGGL((k_update<FLAT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
                            Uout, d, dt, a, b, cnt, fout);
-    else
+    else if (kind == ISO)
         hipLaunchKernelGGL((k_update<ISO, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
                            Uout, d, dt, a, b, cnt, fout);
+    else
+        hipLaunchKernelGGL((k_update<STORED, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un,
+                           Us, Uout, d, dt, a, b, cnt, fout);
     return hipGetLastError();
 }
 
@@ -1051,9 +1126,12 @@ hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc,
     if (kind == FLAT)
         hipLaunchKernelGGL((k_update_zmarch<FLAT, MARCH_SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy,
                            Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
-    else
+    else if (kind == ISO)
         hipLaunchKernelGGL((k_update_zmarch<ISO, MARCH_SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy,
                            Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
+    else
+        hipLaunchKernelGGL((k_update_zmarch<STORED, MARCH_SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx,
+                           Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
     return hipGetLastError();
 }
 
@@ -1064,8 +1142,10 @@ hipError_t launch_rhs(int kind, const T* Fx, const T* Fy, const T* Fz, const T* 
     unsigned nb = blocks_for(d.N);
     if (kind == FLAT)
         hipLaunchKernelGGL((k_rhs<FLAT, T>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, R, d);
-    else
+    else if (kind == ISO)
         hipLaunchKernelGGL((k_rhs<ISO, T>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, R, d);
+    else
+        hipLaunchKernelGGL((k_rhs<STORED, T>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, R, d);
     return hipGetLastError();
 }
 
@@ -1075,8 +1155,10 @@ hipError_t launch_cons(int kind, const double* P, double* U, T* Pc, const Dev& d
     unsigned nb = blocks_for(d.N);
     if (kind == FLAT)
         hipLaunchKernelGGL((k_cons<FLAT, T>), dim3(nb), dim3(BLOCK), 0, s, P, U, Pc, d);
-    else
+    else if (kind == ISO)
         hipLaunchKernelGGL((k_cons<ISO, T>), dim3(nb), dim3(BLOCK), 0, s, P, U, Pc, d);
+    else
+        hipLaunchKernelGGL((k_cons<STORED, T>), dim3(nb), dim3(BLOCK), 0, s, P, U, Pc, d);
     return hipGetLastError();
 }
 
@@ -1087,8 +1169,10 @@ hipError_t launch_prim(int kind, const double* U, double* P, T* Pc, const Dev& d
     unsigned nb = blocks_for(d.N);
     if (kind == FLAT)
         hipLaunchKernelGGL((k_prim<FLAT, T>), dim3(nb), dim3(BLOCK), 0, s, U, P, Pc, d, cnt);
-    else
+    else if (kind == ISO)
         hipLaunchKernelGGL((k_prim<ISO, T>), dim3(nb), dim3(BLOCK), 0, s, U, P, Pc, d, cnt);
+    else
+        hipLaunchKernelGGL((k_prim<STORED, T>), dim3(nb), dim3(BLOCK), 0, s, U, P, Pc, d, cnt);
     return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgrmhd.so")
 
-FLAT, ISO_SCHW = 0, 1
+FLAT, ISO_SCHW, STORED = 0, 1, 2
 SOFT_SQRT, SOFT_MAX = 0, 1
 PERIODIC, OUTFLOW = 0, 1
 FP64, MIXED = 0, 1
@@ -28,7 +28,8 @@ NVAR = 9
 
 # exported symbols of include/grmhd.h
 SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_cons", "grmhd_step",
-           "grmhd_prim", "grmhd_rhs", "grmhd_step_adjoint", "grmhd_step_record",
+           "grmhd_prim", "grmhd_rhs", "grmhd_metric_bytes", "grmhd_set_metric",
+           "grmhd_step_adjoint", "grmhd_step_record",
            "grmhd_step_adjoint_recorded", "grmhd_cons_adjoint",
            "grmhd_prim_adjoint", "grmhd_status", "grmhd_timing", "grmhd_free", "grmhd_strerror",
            "grmhd_batch_workspace_bytes", "grmhd_batch_init", "grmhd_batch_set_stream",
@@ -92,6 +93,9 @@ def load(path: str = LIB_PATH):
     L.grmhd_step.argtypes = [vp, vp, C.c_double]
     L.grmhd_prim.argtypes = [vp, vp, vp]
     L.grmhd_rhs.argtypes = [vp, vp, vp]
+    L.grmhd_metric_bytes.argtypes = [C.POINTER(Grid)]
+    L.grmhd_metric_bytes.restype = C.c_size_t
+    L.grmhd_set_metric.argtypes = [vp, vp, vp, vp, C.c_size_t]
     L.grmhd_step_adjoint.argtypes = [vp, vp, vp, C.c_double]
     L.grmhd_step_record.argtypes = [vp, vp, C.c_double, C.c_int]
     L.grmhd_step_adjoint_recorded.argtypes = [vp, C.c_int, vp]
@@ -114,7 +118,8 @@ def load(path: str = LIB_PATH):
     L.grmhd_strerror.argtypes = [C.c_int]
     L.grmhd_strerror.restype = C.c_char_p
     for name in SYMBOLS:
-        if name not in ("grmhd_workspace_bytes", "grmhd_strerror", "grmhd_batch_workspace_bytes"):
+        if name not in ("grmhd_workspace_bytes", "grmhd_strerror", "grmhd_batch_workspace_bytes",
+                        "grmhd_metric_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -238,6 +243,23 @@ class Solver:
         _check(load().grmhd_rhs(self._ctx, C.c_void_p(self._t(P, "P")), C.c_void_p(self._t(R, "R"))),
                "grmhd_rhs")
         return R
+
+    def set_metric(self, alpha: torch.Tensor, psi4: torch.Tensor) -> None:
+        """The metric of a STORED solver: lapse and psi^4 at the cell centres with
+        2 ghost layers on every active axis, float64 device tensors of shape
+        (nz+2gz, ny+2gy, nx+2gx).  The derived values live in a buffer owned
+        by the solver."""
+        shape = tuple(self.n[d] + (4 if self.n[d] > 1 else 0) for d in (2, 1, 0))
+        for x, name in ((alpha, "alpha"), (psi4, "psi4")):
+            if (not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_contiguous()
+                    or x.device != self.device or tuple(x.shape) != shape):
+                raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s"
+                                 % (name, shape, self.device))
+        L = load()
+        nb = int(L.grmhd_metric_bytes(C.byref(self._grid)))
+        self.metric_buffer = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        _check(L.grmhd_set_metric(self._ctx, C.c_void_p(alpha.data_ptr()), C.c_void_p(psi4.data_ptr()),
+                                  C.c_void_p(self.metric_buffer.data_ptr()), nb), "grmhd_set_metric")
 
     # -- adjoint (vector-Jacobian products) ----------------------------------
     def step_adjoint(self, U: torch.Tensor, Ubar: torch.Tensor, dt: float) -> torch.Tensor:

@@ -465,3 +465,13 @@ def stored_metric(n, lo, hi, k: int = 0, bc=(OUTFLOW, OUTFLOW, OUTFLOW)):
                 f = np.take(f, idx, axis=ax)
         out.append(np.ascontiguousarray(f))
     return out[0], out[1]
+
+
+def sampled_isotropic_metric(n, lo, hi, M: float = 1.0, r_min: float = 1.0, soft: int = SOFT_SQRT):
+    """The workload's isotropic Schwarzschild metric given on the grid (the
+    stored-metric form of the same spacetime): lapse and psi^4 at the cell
+    centres and 2 ghost layers on every active axis, arrays [z][y][x]."""
+    X = ghosted_centres(n, lo, hi)
+    shape = tuple(n[d] + (4 if n[d] > 1 else 0) for d in (2, 1, 0))
+    alpha, psi4 = _iso_schw(X, M, r_min, soft)
+    return np.broadcast_to(alpha, shape).copy(), np.broadcast_to(psi4, shape).copy()

@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 26, names
+    assert len(names) == 28, names
     assert set(names) == set(lib.SYMBOLS)
     L = lib.load()
     for n in names:
@@ -227,6 +227,45 @@ def test_fluxct_layout_and_validation(lib):
         assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) == 0
         o.divergence, o.adjoint = 1, 1
         assert L.grmhd_workspace_bytes(C.byref(g), C.byref(o)) == 0
+
+
+def test_stored_metric_buffer_and_validation(lib):
+    """The stored-metric buffer: 8 centre values per cell and 2 values per face
+    of every active axis; host-side checks of grmhd_set_metric and the state
+    rule (no cons before the metric is set)."""
+    L = lib.load()
+    up = lambda x: (x + 255) // 256 * 256
+    g = lib.make_grid((16, 8, 6), (0, 0, 0), (1, 1, 1), (0, 1, 1))
+    N = 16 * 8 * 6
+    want = up(8 * 8 * N) + up(8 * 2 * 17 * 8 * 6) + up(8 * 2 * 16 * 9 * 6) + up(8 * 2 * 16 * 8 * 7)
+    assert L.grmhd_metric_bytes(C.byref(g)) == want
+    g1 = lib.make_grid((16, 1, 1), (0, 0, 0), (1, 1, 1), (0, 0, 0))
+    assert L.grmhd_metric_bytes(C.byref(g1)) == up(8 * 8 * 16) + up(8 * 2 * 17) + 0 + 0
+    o = lib.Opts()
+    o.rk_order, o.rho_atm, o.p_atm = 3, 1e-12, 1e-12
+    nb = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+    raw, addr = _host_ws(nb)
+    o.workspace, o.workspace_bytes = C.c_void_p(addr), nb
+    e = lib.Eos(0, 5.0 / 3.0, 0.0)
+    dummy = C.c_void_p(addr)                 # never dereferenced: every call below fails its checks
+    ctx = C.c_void_p()
+    assert L.grmhd_init(C.byref(ctx), C.byref(lib.Metric(lib.FLAT, 0, 0.0, 1.0)), C.byref(g), C.byref(e),
+                        C.byref(o)) == 0
+    assert L.grmhd_set_metric(ctx, dummy, dummy, dummy, 1 << 30) == -1   # not a STORED context
+    assert L.grmhd_free(ctx) == 0
+    assert L.grmhd_init(C.byref(ctx), C.byref(lib.Metric(lib.STORED, 0, 0.0, 1.0)), C.byref(g), C.byref(e),
+                        C.byref(o)) == 0
+    assert L.grmhd_cons(ctx, dummy, dummy) == -4                          # metric not set yet
+    assert L.grmhd_prim(ctx, dummy, dummy) == -4
+    assert L.grmhd_set_metric(ctx, dummy, dummy, dummy, want - 8) == -2   # buffer too small
+    assert L.grmhd_set_metric(ctx, dummy, dummy, C.c_void_p(addr + 8), want) == -2
+    assert L.grmhd_free(ctx) == 0
+    o.adjoint = 1
+    nb = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+    raw2, addr2 = _host_ws(nb)
+    o.workspace, o.workspace_bytes = C.c_void_p(addr2), nb
+    assert L.grmhd_init(C.byref(ctx), C.byref(lib.Metric(lib.STORED, 0, 0.0, 1.0)), C.byref(g), C.byref(e),
+                        C.byref(o)) == -1                                  # no adjoint with a stored metric
 
 
 def test_batch_workspace_and_init_validation(lib):

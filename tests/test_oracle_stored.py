@@ -38,13 +38,23 @@ def test_flat_stored_metric_is_flat_bitwise(orc, w):
 
 def _iso_sampled(n, lo, hi, M=1.0, r_min=1.0):
     """The isotropic Schwarzschild metric with softened radius sqrt(r^2 + r_min^2)
-    (the curved workload's) at the ghosted cell centres."""
+    (the curved workload's) at the ghosted cell centres, written out here."""
     X = WL.ghosted_centres(n, lo, hi)
     rs = np.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2 + r_min ** 2)
     h = M / (2.0 * rs)
     shape = tuple(n[d] + (4 if n[d] > 1 else 0) for d in (2, 1, 0))
     return (np.broadcast_to((1 - h) / (1 + h), shape).copy(),
             np.broadcast_to((1 + h) ** 4, shape).copy())
+
+
+def test_sampled_metric_input_is_the_closed_form(orc):
+    """The input generator's sampled isotropic metric is the formula above."""
+    for n in ((8, 7, 6), (12, 1, 1)):
+        lo, hi = (-3.0, -2.0, -1.0), (2.0, 3.0, 4.0)
+        a, p = WL.sampled_isotropic_metric(n, lo, hi)
+        ra, rp = _iso_sampled(n, lo, hi)
+        np.testing.assert_allclose(a, ra, rtol=1e-15)
+        np.testing.assert_allclose(p, rp, rtol=1e-15)
 
 
 def test_sampled_isotropic_metric_converges_at_fourth_order(orc):
