@@ -316,7 +316,7 @@ __device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, doub
     // cleaning pair: exact solution of the linear (Bd^n, Phi) Riemann problem
     T BnL = g.sqrtmg * qL[5 + D], BnR = g.sqrtmg * qR[5 + D];
     // with flux-CT Phi plays no part: the mean of the reconstructed normal
-    // fields (its flux and Phi's are replaced after all faces are known)
+    // fields
     T Bs = d.ct ? half * (BnL + BnR) : half * (BnL + BnR) - half * ich * (qR[8] - qL[8]);
     T phs = half * (qL[8] + qR[8]) - half * ch * (BnR - BnL);
     qL[5 + D] = qR[5 + D] = Bs * g.isqrtmg;
@@ -355,8 +355,10 @@ __device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, doub
             o += cU * (cons_comp(v, qR, kR, g) - cons_comp(v, qL, kL, g));
         Fo[v] = o;
     }
-    Fo[5 + D] = phs;
-    Fo[8] = (T)d.c_h2 * Bs;
+    // flux-CT: no normal-field flux and no Phi flux (the transverse field
+    // fluxes are replaced once the edge values are known)
+    Fo[5 + D] = d.ct ? T(0) : phs;
+    Fo[8] = d.ct ? T(0) : (T)d.c_h2 * Bs;
 }
 
 

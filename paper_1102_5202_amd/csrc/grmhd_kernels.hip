@@ -259,6 +259,15 @@ __device__ __forceinline__ long long face_index(const Dev& d, int dir, int i, in
     return ((long long)k * nf1 + j) * nf0 + i;
 }
 
+// Edge values of the pair p = (a, b) sit at (face a, face b, cell e): extents
+// n + 1 along a and b, n along e.  Every pair is stored x fastest, so that a
+// wave of consecutive edges or faces reads and writes consecutive addresses.
+__device__ __forceinline__ long long edge_index(const Dev& d, int a, int b, int i, int j, int k)
+{
+    const long long e0 = d.n[0] + (a == 0 || b == 0), e1 = d.n[1] + (a == 1 || b == 1);
+    return ((long long)k * e1 + j) * e0 + i;
+}
+
 template <typename T>
 struct CtArgs {
     T* F[3];          // face fluxes of the three axes ([9][nf])
@@ -277,20 +286,21 @@ __global__ __launch_bounds__(BLOCK) void k_ct_edges(CtArgs<T> A, Dev d)
     }
     if (p == 3)
         return;
-    const int a = p == 2 ? 1 : 0, b = p == 0 ? 1 : 2, e = 3 - a - b;
+    const int a = p == 2 ? 1 : 0, b = p == 0 ? 1 : 2;
     const int na = d.n[a], nb = d.n[b];
-    const int fa = (int)(t % (na + 1));
-    const long long r = t / (na + 1);
-    const int fb = (int)(r % (nb + 1));
-    const int ce = (int)(r / (nb + 1));
+    const int e0 = d.n[0] + (a == 0), e1 = d.n[1] + (a == 1 || b == 1);
+    int ix[3];
+    ix[0] = (int)(t % e0);
+    const long long r = t / e0;
+    ix[1] = (int)(r % e1);
+    ix[2] = (int)(r / e1);
+    const int fa = ix[a], fb = ix[b];
     const long long NFa = d.nf[a], NFb = d.nf[b];
     T s = T(0);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        int ix[3];
         ix[a] = fa;
         ix[b] = ct_map(fb - 1 + q, nb, d.bc[b]);
-        ix[e] = ce;
         s -= A.F[a][(5 + b) * NFa + face_index(d, a, ix[0], ix[1], ix[2])];
         ix[a] = ct_map(fa - 1 + q, na, d.bc[a]);
         ix[b] = fb;
@@ -299,6 +309,8 @@ __global__ __launch_bounds__(BLOCK) void k_ct_edges(CtArgs<T> A, Dev d)
     A.W[p][t] = T(0.25) * s;
 }
 
+// The normal-field and Phi rows of every face flux are zero under flux-CT
+// (the face kernels write them so); this kernel replaces the transverse rows.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_ct_faces(CtArgs<T> A, Dev d)
 {
@@ -319,19 +331,16 @@ __global__ __launch_bounds__(BLOCK) void k_ct_faces(CtArgs<T> A, Dev d)
     ix[1] = (int)(r % m1);
     ix[2] = (int)(r / m1);
     T* F = A.F[a];
-    F[(5 + a) * NF + t] = T(0);
-    F[8 * NF + t] = T(0);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         if (b == a || !d.act[b])
             continue;
-        const int lo = a < b ? a : b, hi = a < b ? b : a, e = 3 - a - b;
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
         const int p = lo == 0 ? (hi == 1 ? 0 : 1) : 2;
-        const long long nl = d.n[lo], nh = d.n[hi];
         int eh[3] = {ix[0], ix[1], ix[2]};
         eh[b] += 1;
-        const long long w0 = ((long long)ix[e] * (nh + 1) + ix[hi]) * (nl + 1) + ix[lo];
-        const long long w1 = ((long long)eh[e] * (nh + 1) + eh[hi]) * (nl + 1) + eh[lo];
+        const long long w0 = edge_index(d, lo, hi, ix[0], ix[1], ix[2]);
+        const long long w1 = edge_index(d, lo, hi, eh[0], eh[1], eh[2]);
         const T sign = a < b ? T(-0.5) : T(0.5);
         F[(5 + b) * NF + t] = sign * (A.W[p][w0] + A.W[p][w1]);
     }
@@ -1083,10 +1092,10 @@ hipError_t launch_ct(T* const* F, T* const* W, const Dev& d, hipStream_t s)
         edges += A.nW[p];
         faces += d.act[p] ? d.nf[p] : 0;
     }
-    if (edges > 0)
-        hipLaunchKernelGGL(k_ct_edges<T>, dim3(blocks_for(edges)), dim3(BLOCK), 0, s, A, d);
-    if (faces > 0)
-        hipLaunchKernelGGL(k_ct_faces<T>, dim3(blocks_for(faces)), dim3(BLOCK), 0, s, A, d);
+    if (edges == 0)
+        return hipSuccess;   // one active axis: no transverse flux to replace
+    hipLaunchKernelGGL(k_ct_edges<T>, dim3(blocks_for(edges)), dim3(BLOCK), 0, s, A, d);
+    hipLaunchKernelGGL(k_ct_faces<T>, dim3(blocks_for(faces)), dim3(BLOCK), 0, s, A, d);
     return hipGetLastError();
 }
 
