@@ -203,6 +203,59 @@ def test_curved_blob_full_size_sampled(G, orc):
     assert np.all(worst <= 1e-12)
 
 
+def test_periodic_box_full_size_sampled(G, orc):
+    """Config 2 at its full 128^3 size, one SSP-RK2 step on the GPU.  Sampled
+    cells are recomputed by the oracle on the 13^3 box around each, cut from
+    the periodic grid with wrapped indices and given zero-gradient boundaries:
+    one RK2 step depends on cells at most 4 away (2 per substep), and the
+    boundary's influence reaches at most 4 cells in, so the box centre is
+    exact."""
+    w = WL.config2(n=128, nsteps=1)
+    s = G.solver_for(w, device=DEV)
+    U = s.cons(torch.from_numpy(w.P).to(DEV))
+    s.step(U, w.dt)
+    torch.cuda.synchronize()
+    U = U.cpu().numpy()
+    say("GPU 128^3 step done", s.status())
+    n, R = 128, 6
+    rng = np.random.default_rng(12)
+    picks = [tuple(rng.integers(0, n, 3)) for _ in range(80)]
+    picks += [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 5), (127, 0, 64), (1, 126, 2)]
+    scale = np.abs(U).reshape(9, -1).max(axis=1)
+    worst = np.zeros(9)
+    for (i, j, k) in picks:
+        idx = [np.arange(c - R, c + R + 1) % n for c in (i, j, k)]
+        sub = np.ascontiguousarray(w.P[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]])
+        kw = w.problem_kwargs()
+        kw["n"] = (2 * R + 1,) * 3
+        kw["lo"] = (0.0,) * 3
+        kw["hi"] = ((2 * R + 1) / n,) * 3
+        kw["bc"] = (WL.OUTFLOW,) * 3
+        pb = orc.Problem(**kw)
+        Ur, _, _ = orc.step(pb, orc.prim2con(pb, sub), sub, w.dt, 1)
+        worst = np.maximum(worst, np.abs(U[:, k, j, i] - Ur[:, R, R, R]) / np.maximum(scale, 1e-300))
+    say("128^3 periodic sampled max err / scale", worst)
+    assert np.all(worst <= 1e-12)
+
+
+@pytest.mark.parametrize("case", ["xy_periodic", "xz_curved", "yz_curved"])
+def test_two_dimensional_runs(G, orc, case):
+    """2D grids (one unit axis) take the unfused path: a face kernel per active
+    axis, the ghost pass and the in-place cell update."""
+    if case == "xy_periodic":
+        w = WL.config2(n=(37, 29, 1), nsteps=40)
+    elif case == "xz_curved":
+        w = WL.config3(n=(34, 1, 31), nsteps=20)
+    else:
+        w = WL.config3(n=(1, 30, 33), nsteps=20)
+    U, P, st, _ = gpu_run(G, w, w.nsteps)
+    Ur, Pr, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say(case, "2D rel-L1", err, st, sto)
+    assert np.all(err <= 1e-10)
+    assert st["fail"] == sto["fail"]
+
+
 # ---------------------------------------------------------------------------
 # exactness, determinism, failure policy, graph replay
 
