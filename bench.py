@@ -332,7 +332,7 @@ def main(argv=None) -> int:
         return 0
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported "
               "(the multi-GPU halo exchange is a design note, not an implemented path)" % args.gpus,
               file=sys.stderr)
         return 2
