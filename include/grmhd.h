@@ -221,7 +221,8 @@ int grmhd_cons(grmhd_ctx *ctx, const double *P, double *U);
 int grmhd_step(grmhd_ctx *ctx, double *U, double dt);
 
 /* The metric of a STORED context (section 2.1: the spacetime is given).
- * alpha and psi4 (device, double, read during the call only) hold the lapse
+ * alpha and psi4 (device, double; read by work queued on the context's
+ * stream, so they must stay valid until the stream reaches it) hold the lapse
  * and the conformal factor psi^4 (gamma_ij = psi^4 delta_ij, zero shift) at
  * the cell centres of the grid and of 2 ghost layers on every active axis:
  * dense [nz+2gz][ny+2gy][nx+2gx], x fastest, g = 2 on an axis with n > 1
@@ -345,7 +346,10 @@ int grmhd_batch_tune(grmhd_batch *b, const double *U, int trial_steps, int *thre
 
 /* Choose the launch shape of grmhd_batch_evolve by hand: threads per
  * workgroup (256, 512 or 1024) and whether the primitive rows live in LDS
- * (refused with GRMHD_ERR_ARG when the largest row does not fit in 160 KiB). */
+ * (refused with GRMHD_ERR_ARG when the largest row does not fit in 160 KiB, or
+ * when the device refused that much LDS at grmhd_batch_init).  Rows in LDS
+ * are the initial choice wherever they are allowed.  grmhd_batch_evolve makes
+ * no call but the launch, so it can be captured in a HIP graph. */
 int grmhd_batch_set_shape(grmhd_batch *b, int threads, int lds);
 
 /* As grmhd_status, for the batch. */

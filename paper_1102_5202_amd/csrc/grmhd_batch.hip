@@ -101,6 +101,7 @@ struct grmhd_batch {
     int shape = 1;                   // index into BATCH_THREADS
     int lds = 0;
     size_t lds_bytes = 0;
+    bool lds_ok = false;   // rows fit in LDS and their LDS size is allowed
     unsigned long long* cnt = nullptr;
 };
 
@@ -237,8 +238,17 @@ int grmhd_batch_init(grmhd_batch** out, const grmhd_batch_desc* desc, const grmh
         return (double)b->probs[x].n * b->probs[x].steps > (double)b->probs[y].n * b->probs[y].steps;
     });
     b->lds_bytes = es * 9 * (size_t)(L.nmax + 4);
-    b->lds = b->lds_bytes <= LDS_LIMIT ? 1 : 0;
     b->shape = 1;
+    // rows in LDS need their dynamic LDS size allowed once, here, outside any
+    // graph capture; where that fails (no device yet) the rows stay in HBM
+    if (b->lds_bytes <= LDS_LIMIT) {
+        const hipError_t e = b->mixed ? grmhd::allow_batch_lds<float>(b->lds_bytes)
+                                      : grmhd::allow_batch_lds<double>(b->lds_bytes);
+        if (e != hipSuccess)
+            (void)hipGetLastError();   // clear it: launches check the last error
+        b->lds_ok = e == hipSuccess;
+    }
+    b->lds = b->lds_ok ? 1 : 0;
     *out = b;
     return GRMHD_OK;
 }
@@ -312,7 +322,7 @@ int grmhd_batch_tune(grmhd_batch* b, const double* U, int trial_steps, int* thre
     float best = -1.0f;
     int best_shape = keep_shape, best_lds = keep_lds, rc = GRMHD_OK;
     for (int l = 0; l <= 1 && rc == GRMHD_OK; ++l) {
-        if (l == 1 && b->lds_bytes > LDS_LIMIT)
+        if (l == 1 && !b->lds_ok)
             break;
         for (int s = 0; s < grmhd::BATCH_SHAPES && rc == GRMHD_OK; ++s) {
             // fresh copies of the state for every candidate
@@ -372,7 +382,7 @@ int grmhd_batch_set_shape(grmhd_batch* b, int threads, int lds)
     for (int s = 0; s < grmhd::BATCH_SHAPES; ++s)
         if (grmhd::BATCH_THREADS[s] == threads)
             shape = s;
-    if (shape < 0 || (lds && b->lds_bytes > LDS_LIMIT))
+    if (shape < 0 || (lds && !b->lds_ok))
         return GRMHD_ERR_ARG;
     b->shape = shape;
     b->lds = lds ? 1 : 0;

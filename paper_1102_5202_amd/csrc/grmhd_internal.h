@@ -80,6 +80,11 @@ hipError_t launch_batch_prim(const BatchProb* probs, int nprob, long long ncell,
 // shape: index into BATCH_THREADS; lds: keep the primitive rows in LDS (needs
 // lds_bytes <= 160 KiB).  order: the problem each workgroup takes.  Pnext is
 // a second set of rows (the next substep's, or the staging of the LDS rows).
+// Allows k_batch_evolve's LDS variants `bytes` of dynamic LDS (set-up only:
+// not a stream operation, so never called while a step may be captured).
+template <typename T>
+hipError_t allow_batch_lds(size_t bytes);
+
 template <typename T>
 hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
                                double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps,

@@ -1233,17 +1233,33 @@ static hipError_t batch_evolve_k(int lds, size_t lds_bytes, BatchProb* probs, co
                                  unsigned long long* cnt, hipStream_t s)
 {
     if (lds) {
-        // dynamic LDS beyond the default launch limit must be allowed explicitly
-        hipError_t e = hipFuncSetAttribute((const void*)k_batch_evolve<T, NT, true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess)
-            return e;
+        // (the dynamic LDS size was allowed by allow_batch_lds at set-up)
         hipLaunchKernelGGL((k_batch_evolve<T, NT, true>), dim3(nprob), dim3(NT), lds_bytes, s, probs, order, U,
                            Us, Prow, Pnext, d, ns, max_steps, cnt);
     } else
         hipLaunchKernelGGL((k_batch_evolve<T, NT, false>), dim3(nprob), dim3(NT), 0, s, probs, order, U, Us,
                            Prow, Pnext, d, ns, max_steps, cnt);
     return hipGetLastError();
+}
+
+// Dynamic LDS beyond the default launch limit must be allowed per kernel, once,
+// outside any graph capture: raised for every launch shape of T to at least
+// `bytes`, never lowered (other contexts may need more).
+template <typename T>
+hipError_t allow_batch_lds(size_t bytes)
+{
+    static size_t allowed = 0;
+    if (bytes <= allowed)
+        return hipSuccess;
+    const void* fn[3] = {(const void*)k_batch_evolve<T, 256, true>, (const void*)k_batch_evolve<T, 512, true>,
+                         (const void*)k_batch_evolve<T, 1024, true>};
+    for (const void* f : fn) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess)
+            return e;
+    }
+    allowed = bytes;
+    return hipSuccess;
 }
 
 template <typename T>
@@ -1279,6 +1295,7 @@ hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* 
                                              const Dev&, hipStream_t);                                        \
     template hipError_t launch_batch_prim<T>(const BatchProb*, int, long long, const double*, double*, T*,     \
                                              const Dev&, unsigned long long*, hipStream_t);                   \
+    template hipError_t allow_batch_lds<T>(size_t);                                                           \
     template hipError_t launch_batch_evolve<T>(int, int, size_t, BatchProb*, const int*, int, double*, T*, T*, \
                                                T*, const Dev&, int, int, unsigned long long*, hipStream_t);
 GRMHD_INSTANTIATE_BATCH(double)

@@ -257,7 +257,13 @@ class Solver:
                                  % (name, shape, self.device))
         L = load()
         nb = int(L.grmhd_metric_bytes(C.byref(self._grid)))
-        self.metric_buffer = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        # the buffer is used on the solver's stream; the inputs are read there
+        # after this call returns, so the allocator must not hand them out
+        # again before that stream has passed the read
+        with torch.cuda.stream(self.stream):
+            self.metric_buffer = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        alpha.record_stream(self.stream)
+        psi4.record_stream(self.stream)
         _check(L.grmhd_set_metric(self._ctx, C.c_void_p(alpha.data_ptr()), C.c_void_p(psi4.data_ptr()),
                                   C.c_void_p(self.metric_buffer.data_ptr()), nb), "grmhd_set_metric")
 
@@ -363,9 +369,12 @@ class BatchSolver:
         _check(L.grmhd_batch_init(C.byref(ctx), C.byref(self._desc), C.byref(self._eos),
                                   C.byref(self._opts)), "grmhd_batch_init")
         self._ctx = ctx
-        st = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.stream = st
-        _check(L.grmhd_batch_set_stream(self._ctx, C.c_void_p(st.cuda_stream)), "grmhd_batch_set_stream")
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream(self.device))
+
+    def set_stream(self, stream) -> None:
+        self.stream = stream
+        _check(load().grmhd_batch_set_stream(self._ctx, C.c_void_p(stream.cuda_stream)),
+               "grmhd_batch_set_stream")
 
     def _t(self, x: torch.Tensor, name: str) -> int:
         if (not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_contiguous()

@@ -294,7 +294,12 @@ def test_batch_workspace_and_init_validation(lib):
     assert L.grmhd_batch_evolve(ctx, None, 5) == -1
     assert L.grmhd_batch_tune(ctx, C.c_void_p(addr), 5, None, None) == -4
     assert L.grmhd_batch_set_shape(ctx, 384, 0) == -1
-    assert L.grmhd_batch_set_shape(ctx, 1024, 1) == 0
+    assert L.grmhd_batch_set_shape(ctx, 1024, 0) == 0
+    # rows in LDS need the device to allow their LDS size at init: refused
+    # where there is no device
+    import torch
+    have_gpu = torch.cuda.device_count() > 0
+    assert L.grmhd_batch_set_shape(ctx, 1024, 1) == (0 if have_gpu else -1)
     assert L.grmhd_batch_free(ctx) == 0
     o.workspace_bytes = nb - 8
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == -2

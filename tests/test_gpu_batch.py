@@ -97,6 +97,35 @@ def test_batch_chunked_equals_one_shot_and_shapes_agree(G):
     say("tuned shape", th, lds)
 
 
+@pytest.mark.parametrize("precision,lds", [("fp64", False), ("fp64", True), ("mixed", True)])
+def test_batch_graph_replay_matches_eager(G, precision, lds):
+    """One persistent launch of a chunk of steps captured in a HIP graph and
+    replayed several times (eager work and synchronisation between the
+    replays) equals the same chunks run eagerly, bitwise, with the rows in
+    HBM and in LDS."""
+    e = WL.config5(nprob=7, nmin=40, nmax=260, k=3)
+    se = G.batch_for(e, device=DEV, precision=precision)
+    se.set_shape(512, lds)
+    Ue = se.cons(se.pack(e.P))
+    sg = G.batch_for(e, device=DEV, precision=precision)
+    sg.set_shape(512, lds)
+    Ug = sg.cons(sg.pack(e.P))
+    torch.cuda.synchronize()
+    chunk = 11
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sg.set_stream(torch.cuda.current_stream())
+        sg.evolve(Ug, chunk)
+    sg.set_stream(torch.cuda.current_stream())
+    for r in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        se.evolve(Ue, chunk)
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, Ue), r
+    say(precision, "graph replays match eager; status", sg.status())
+
+
 def test_batch_full_size_sampled(G, orc):
     """The ensemble at full size (256 problems, 200..4000 cells, each to
     t = 0.4): the three smallest problems against the oracle, every state
