@@ -88,8 +88,9 @@ typedef struct {
     double r_min;
 } grmhd_metric;
 
-/* Cartesian uniform mesh (section 3.2).  n[d] >= 1 cells on [lo[d], hi[d]];
- * active axes (n > 1) need n >= 2.  bc[d] applies on both ends of axis d:
+/* Cartesian uniform mesh (section 3.2).  n[d] >= 1 cells on [lo[d], hi[d]]
+ * (at most 2^20 per axis and 2^38 in all); active axes (n > 1) need n >= 2
+ * (n >= 3 with PPM).  bc[d] applies on both ends of axis d:
  * PERIODIC, or OUTFLOW (two zero-gradient ghost cells of the primitives). */
 typedef struct {
     int n[3];
@@ -306,8 +307,9 @@ int grmhd_prim_adjoint(grmhd_ctx *ctx, const double *U, const double *Pbar, doub
  * sum of the earlier n) follow those of problem b-1; all device, double.
  * The same ownership and error rules as the single-grid calls apply. */
 typedef struct {
-    int nprob;             /* number of problems, >= 1                          */
-    const int *n;          /* host array: cells of each problem, >= 2           */
+    int nprob;             /* number of problems, 1 .. 2^20                     */
+    const int *n;          /* host array: cells of each problem, 2 .. 2^24,
+                              at most 2^38 over all problems                    */
     const double *lo;      /* host arrays: domain [lo, hi] of each problem      */
     const double *hi;
     const double *dt;      /* host array: time step of each problem             */

@@ -59,7 +59,10 @@ bool grid_ok(const grmhd_grid* g)
         if (g->bc[d] != GRMHD_BC_PERIODIC && g->bc[d] != GRMHD_BC_OUTFLOW)
             return false;
     }
-    return true;
+    // at most 2^38 cells: workspace sizes stay far inside size_t and every
+    // launch inside the 2^31 - 1 workgroups of a grid dimension
+    const long long N = (long long)g->n[0] * g->n[1] * g->n[2];
+    return N <= (1LL << 38);
 }
 
 Layout make_layout(const grmhd_grid* g, size_t esize, bool adjoint = false, int ns = 3, int tape = 0,

@@ -38,15 +38,17 @@ bool desc_ok(const grmhd_batch_desc* d)
         return false;
     if (d->bc != GRMHD_BC_PERIODIC && d->bc != GRMHD_BC_OUTFLOW)
         return false;
+    long long cells = 0;
     for (int b = 0; b < d->nprob; ++b) {
         if (d->n[b] < 2 || d->n[b] > (1 << 24) || d->steps[b] < 0)
             return false;
+        cells += d->n[b];
         if (!(d->hi[b] > d->lo[b]) || !std::isfinite(d->lo[b]) || !std::isfinite(d->hi[b]))
             return false;
         if (!(d->dt[b] >= 0.0) || !std::isfinite(d->dt[b]))
             return false;
     }
-    return true;
+    return cells <= (1LL << 38);   // launches stay inside 2^31 - 1 workgroups
 }
 
 BatchLayout batch_layout(const grmhd_batch_desc* d, size_t esize)

@@ -418,12 +418,6 @@ struct C2P {
     double D, Qn, Qt2, Bc2, QB2;
 };
 
-__device__ __forceinline__ double c2p_press(const C2P& c, double gk, double Wc, double v2)
-{
-    double s = sqrt(1.0 - v2);
-    return gk * (Wc * (1.0 - v2) - c.D * s);
-}
-
 // Newton-Raphson on the two residuals, warm-started.  Converged when the
 // relative step in Wc falls below tol, after one more step (which takes the
 // iterate to its rounding limit, so that the root does not depend on the

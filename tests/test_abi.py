@@ -56,6 +56,11 @@ def test_workspace_and_init_validation(lib):
     assert nb >= 8 * 9 * (px * 12 * 1 + 16 * 8 + 17 * 8 + 16 * 9)
     bad = lib.make_grid((0, 8, 1), (0, 0, 0), (1, 1, 1), (0, 0, 0))
     assert L.grmhd_workspace_bytes(C.byref(bad), None) == 0
+    # sizes whose byte counts would overflow are refused, not wrapped
+    huge = lib.make_grid((1 << 20, 1 << 20, 1 << 20), (0, 0, 0), (1, 1, 1), (0, 0, 0))
+    assert L.grmhd_workspace_bytes(C.byref(huge), None) == 0
+    big = lib.make_grid((1 << 19, 1 << 19, 1), (0, 0, 0), (1, 1, 1), (0, 0, 0))
+    assert L.grmhd_workspace_bytes(C.byref(big), None) > 9 * 8 * (1 << 38)
     raw, addr = _host_ws(nb)
     m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
     e = lib.Eos(0, 5.0 / 3.0, 0.0)
