@@ -256,6 +256,22 @@ def test_two_dimensional_runs(G, orc, case):
     assert st["fail"] == sto["fail"]
 
 
+@pytest.mark.parametrize("case", ["flat2x2x2", "flat3x2x5", "curved3x2x2", "curved2x3x9", "riemann2"])
+def test_smallest_grids(G, orc, case):
+    """Active axes as short as the two ghost layers allow (periodic images and
+    zero-gradient copies of the same few cells; z columns shorter than one
+    march segment)."""
+    w = {"flat2x2x2": WL.config2(n=(2, 2, 2), nsteps=5), "flat3x2x5": WL.config2(n=(3, 2, 5), nsteps=5),
+         "curved3x2x2": WL.config3(n=(3, 2, 2), nsteps=5), "curved2x3x9": WL.config3(n=(2, 3, 9), nsteps=5),
+         "riemann2": WL.config1(0, n=2)}[case]
+    U, P, st, _ = gpu_run(G, w, 5)
+    Ur, Pr, sto, _ = oracle_run(orc, w, 5)
+    err = rel_l1(U, Ur)
+    say(case, "rel-L1", err, st, sto)
+    assert np.all(err <= 1e-10)
+    assert st["fail"] == sto["fail"] and st["atm"] == sto["atm"]
+
+
 # ---------------------------------------------------------------------------
 # exactness, determinism, failure policy, graph replay
 
