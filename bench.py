@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -39,10 +40,16 @@ KERNEL_SOURCES = ("paper_1102_5202_amd/csrc/grmhd_kernels.hip",
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources' code: comments and blank space are
+    dropped first, so that the stored counters stay valid across edits that
+    change no code."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,7 +1,6 @@
 // grmhd_kernels.hip -- HIP kernels of the GRMHD substep (gfx950, wave64).
 //
-// One substep (section 2.2 of the paper) on a 3D grid is four launches:
-//   k_ghosts          ghost zones of the primitive cache (periodic / zero-gradient)
+// One substep (section 2.2 of the paper) on a 3D grid is three launches:
 //   k_flux_x          per x face: MC reconstruction of the 9 primitives, exact
 //                     (normal field, Phi) cleaning pair, face physics of both
 //                     states, HLLE flux (section 3.2)
@@ -10,7 +9,12 @@
 //                     metric sources (eq. 2), SSP Runge-Kutta combination,
 //                     Newton recovery of the primitives with the
 //                     atmosphere/floor policy, status counters
-// 1D and 2D grids use the face kernels of every active axis and k_update.
+// Every kernel that writes primitives also writes their ghost images, so the
+// ghost pass k_ghosts runs only for caches filled otherwise.  1D and 2D grids,
+// PPM (k_flux_ppm) and flux-CT (k_ct_edges, k_ct_faces) use the face kernels of
+// every active axis and the cell kernel k_update.  Also here: the stored
+// metric's set-up (k_metric), the single-kernel maps (k_cons, k_prim, k_rhs)
+// and the batched 1D ensemble (k_batch_*).
 //
 // T is the type of the primitive caches, the face fluxes and the face physics:
 // double (FP64 path) or float (mixed precision).  The metric is always
