@@ -202,15 +202,15 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_face(const double* __restrict__ 
     }
 }
 
-// Cotangent of the primitives at position ci (ci[D] in -2 .. n+1, ghosts of
-// axis D included; interior along the other axes) from the faces along D,
-// added to mu: the left/right reconstructed-state cotangents FB (18 rows of
-// nf values) pulled back through the MC reconstruction.  Face f sits between
-// cells f-1 and f; the slope of cell j feeds the left state at face j+1 and
-// the right state at face j.
+// Cotangent of primitive v at position ci (ci[D] in -2 .. n+1, ghosts of
+// axis D included; interior along the other axes) from the faces along D:
+// the left/right reconstructed-state cotangents FB (18 rows of nf values)
+// pulled back through the MC reconstruction.  Face f sits between cells f-1
+// and f; the slope of cell j feeds the left state at face j+1 and the right
+// state at face j.
 template <int D>
-__device__ __forceinline__ void gather_pos(const Dev& d, const double* __restrict__ Pc,
-                                           const double* __restrict__ FB, const int* ci, double* mu)
+__device__ __forceinline__ double gather_pos_v(const Dev& d, const double* __restrict__ Pc,
+                                               const double* __restrict__ FB, const int* ci, int v)
 {
     const int i = ci[D], n = d.n[D];
     const long long nf = d.nf[D];
@@ -228,45 +228,39 @@ __device__ __forceinline__ void gather_pos(const Dev& d, const double* __restric
     const long long f_lo = has_lo ? face(i) : 0, f_hi = has_hi ? face(i + 1) : 0;
     const long long f_lm = (i - 1 >= 0 && i - 1 <= n) ? face(i - 1) : -1;   // face i-1
     const long long f_hp = (i + 2 >= 0 && i + 2 <= n) ? face(i + 2) : -1;   // face i+2
-#pragma unroll
-    for (int v = 0; v < 9; ++v) {
-        const double* Fl = FB + v * nf;          // left-state cotangents
-        const double* Fr = FB + (9 + v) * nf;    // right-state cotangents
-        double m = 0.0;
-        if (has_hi)
-            m += Fl[f_hi];
-        if (has_lo)
-            m += Fr[f_lo];
-        const double* P = Pc + v * d.sv + pc;
-        // j = i - 1 (q_i is its qp), j in [-1, n]
-        if (i - 1 >= -1 && i - 1 <= n) {
-            const double sb = 0.5 * ((has_lo ? Fl[f_lo] : 0.0) - (f_lm >= 0 ? Fr[f_lm] : 0.0));
-            if (sb != 0.0) {
-                double dm, d0, dp;
-                mc_slope_grad(P[-2 * st], P[-st], P[0], dm, d0, dp);
-                m += sb * dp;
-            }
+    const double* Fl = FB + v * nf;          // left-state cotangents
+    const double* Fr = FB + (9 + v) * nf;    // right-state cotangents
+    const double Fl_hi = has_hi ? Fl[f_hi] : 0.0, Fr_lo = has_lo ? Fr[f_lo] : 0.0;
+    double m = Fl_hi + Fr_lo;
+    const double* P = Pc + v * d.sv + pc;
+    // j = i - 1 (q_i is its qp), j in [-1, n]
+    if (i - 1 >= -1 && i - 1 <= n) {
+        const double sb = 0.5 * ((has_lo ? Fl[f_lo] : 0.0) - (f_lm >= 0 ? Fr[f_lm] : 0.0));
+        if (sb != 0.0) {
+            double dm, d0, dp;
+            mc_slope_grad(P[-2 * st], P[-st], P[0], dm, d0, dp);
+            m += sb * dp;
         }
-        // j = i
-        if (i >= -1 && i <= n) {
-            const double sb = 0.5 * ((has_hi ? Fl[f_hi] : 0.0) - (has_lo ? Fr[f_lo] : 0.0));
-            if (sb != 0.0) {
-                double dm, d0, dp;
-                mc_slope_grad(P[-st], P[0], P[st], dm, d0, dp);
-                m += sb * d0;
-            }
-        }
-        // j = i + 1 (q_i is its qm)
-        if (i + 1 >= -1 && i + 1 <= n) {
-            const double sb = 0.5 * ((f_hp >= 0 ? Fl[f_hp] : 0.0) - (has_hi ? Fr[f_hi] : 0.0));
-            if (sb != 0.0) {
-                double dm, d0, dp;
-                mc_slope_grad(P[0], P[st], P[2 * st], dm, d0, dp);
-                m += sb * dm;
-            }
-        }
-        mu[v] += m;
     }
+    // j = i
+    if (i >= -1 && i <= n) {
+        const double sb = 0.5 * (Fl_hi - Fr_lo);
+        if (sb != 0.0) {
+            double dm, d0, dp;
+            mc_slope_grad(P[-st], P[0], P[st], dm, d0, dp);
+            m += sb * d0;
+        }
+    }
+    // j = i + 1 (q_i is its qm)
+    if (i + 1 >= -1 && i + 1 <= n) {
+        const double sb = 0.5 * ((f_hp >= 0 ? Fl[f_hp] : 0.0) - (has_hi ? Fr[f_hi] : 0.0));
+        if (sb != 0.0) {
+            double dm, d0, dp;
+            mc_slope_grad(P[0], P[st], P[2 * st], dm, d0, dp);
+            m += sb * dm;
+        }
+    }
+    return m;
 }
 
 // Reverse of add_sources() (FP64): Rb (cotangent of R at the cell) -> qb.
@@ -428,13 +422,13 @@ __device__ __forceinline__ long long line_of(const Dev& d, const int* ci)
 }
 
 // The ghost positions of axis D, 4 per line (slots 0..3 = positions -2, -1,
-// n, n+1): the pull-back of the faces along D there, into G (layout
-// [9][4][lines]); the cell kernel adds each to the interior cell the ghost
-// fill copies into that position.
+// n, n+1): the pull-back of the faces along D there, variable v, into G
+// (layout [9][4][lines]); the cell kernel adds each to the interior cell the
+// ghost fill copies into that position.
 template <int D>
 __device__ __forceinline__ void gather_ghost(const Dev& d, const double* __restrict__ Pc,
                                              const double* __restrict__ FB, double* __restrict__ G,
-                                             long long t, long long lines)
+                                             long long t, long long lines, int v)
 {
     const int slot = (int)(t / lines);
     const long long line = t - slot * lines;
@@ -443,53 +437,48 @@ __device__ __forceinline__ void gather_ghost(const Dev& d, const double* __restr
     ci[a] = (int)(line % d.n[a]);
     ci[b] = (int)(line / d.n[a]);
     ci[D] = slot < 2 ? slot - 2 : d.n[D] + slot - 2;
-    double mu[9];
-#pragma unroll
-    for (int v = 0; v < 9; ++v)
-        mu[v] = 0.0;
-    gather_pos<D>(d, Pc, FB, ci, mu);
-#pragma unroll
-    for (int v = 0; v < 9; ++v)
-        G[(v * 4 + slot) * lines + line] = mu[v];
+    G[(v * 4 + slot) * lines + line] = gather_pos_v<D>(d, Pc, FB, ci, v);
 }
 
-// Threads [0, N): one per interior cell, the cotangent of its primitives from
-// the face-state cotangents of every active axis (FB0/1/2, 18 rows of nf
-// values each) pulled back through the MC reconstruction, into MU (dense
-// [9][N]).  Then, per active axis, 4 threads per line for its ghost positions
-// (into G0/1/2).  Light on registers: this kernel waits on scattered loads
-// and wants occupancy.
+// One thread per position and primitive variable v (v slowest, positions
+// fastest, so a wave reads consecutive cells of one variable): positions
+// [0, N) are the interior cells, whose cotangent from the face-state
+// cotangents of every active axis (FB0/1/2, 18 rows of nf values each)
+// pulled back through the MC reconstruction goes to MU (dense [9][N]); then,
+// per active axis, 4 positions per line for its ghost slots (into G0/1/2).
+// A thread does one variable's loads and slopes, so the many independent
+// threads hide the latency of the scattered loads.
 __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict__ Pc,
                                                         const double* __restrict__ FB0,
                                                         const double* __restrict__ FB1,
                                                         const double* __restrict__ FB2,
                                                         double* __restrict__ MU, double* __restrict__ G0,
-                                                        double* __restrict__ G1, double* __restrict__ G2, Dev d)
+                                                        double* __restrict__ G1, double* __restrict__ G2, Dev d,
+                                                        long long npos)
 {
-    long long t = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    const long long g = (long long)blockIdx.x * ABLOCK + threadIdx.x;
+    if (g >= 9 * npos)
+        return;
+    const int v = (int)(g / npos);
+    long long t = g - v * npos;
     if (t < d.N) {
         const long long r = t / d.n[0];
         const int ci[3] = {(int)(t % d.n[0]), (int)(r % d.n[1]), (int)(r / d.n[1])};
-        double mu[9];
-#pragma unroll
-        for (int v = 0; v < 9; ++v)
-            mu[v] = 0.0;
+        double m = 0.0;
         if (d.act[0])
-            gather_pos<0>(d, Pc, FB0, ci, mu);
+            m += gather_pos_v<0>(d, Pc, FB0, ci, v);
         if (d.act[1])
-            gather_pos<1>(d, Pc, FB1, ci, mu);
+            m += gather_pos_v<1>(d, Pc, FB1, ci, v);
         if (d.act[2])
-            gather_pos<2>(d, Pc, FB2, ci, mu);
-#pragma unroll
-        for (int v = 0; v < 9; ++v)
-            MU[v * d.N + t] = mu[v];
+            m += gather_pos_v<2>(d, Pc, FB2, ci, v);
+        MU[v * d.N + t] = m;
         return;
     }
     t -= d.N;
     if (d.act[0]) {
         const long long lines = d.N / d.n[0];
         if (t < 4 * lines) {
-            gather_ghost<0>(d, Pc, FB0, G0, t, lines);
+            gather_ghost<0>(d, Pc, FB0, G0, t, lines, v);
             return;
         }
         t -= 4 * lines;
@@ -497,7 +486,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
     if (d.act[1]) {
         const long long lines = d.N / d.n[1];
         if (t < 4 * lines) {
-            gather_ghost<1>(d, Pc, FB1, G1, t, lines);
+            gather_ghost<1>(d, Pc, FB1, G1, t, lines, v);
             return;
         }
         t -= 4 * lines;
@@ -505,7 +494,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
     if (d.act[2]) {
         const long long lines = d.N / d.n[2];
         if (t < 4 * lines)
-            gather_ghost<2>(d, Pc, FB2, G2, t, lines);
+            gather_ghost<2>(d, Pc, FB2, G2, t, lines, v);
     }
 }
 
@@ -696,12 +685,12 @@ hipError_t launch_adj_rec(int kind, double* Ub, const double* Pn, const unsigned
 hipError_t launch_adj_gather(const double* Pc, const double* const* FB, double* MU, double* const* G, const Dev& d,
                              hipStream_t s)
 {
-    long long total = d.N;
+    long long npos = d.N;
     for (int a = 0; a < 3; ++a)
         if (d.act[a])
-            total += 4 * (d.N / d.n[a]);
-    hipLaunchKernelGGL(k_adj_gather, dim3(ablocks(total)), dim3(ABLOCK), 0, s, Pc, FB[0], FB[1], FB[2], MU, G[0],
-                       G[1], G[2], d);
+            npos += 4 * (d.N / d.n[a]);
+    hipLaunchKernelGGL(k_adj_gather, dim3(ablocks(9 * npos)), dim3(ABLOCK), 0, s, Pc, FB[0], FB[1], FB[2], MU, G[0],
+                       G[1], G[2], d, npos);
     return hipGetLastError();
 }
 
