@@ -272,6 +272,66 @@ def test_smallest_grids(G, orc, case):
     assert st["fail"] == sto["fail"] and st["atm"] == sto["atm"]
 
 
+def _large_grid_fields(n, lo, dx, dev):
+    """Smooth analytic primitives on an n[0] x n[1] x n[2] grid, built on the
+    device (9 x 262M values would take minutes on the host)."""
+    xs = [torch.tensor(lo[d] + (np.arange(n[d]) + 0.5) * dx[d], device=dev) for d in range(3)]
+    X = xs[0].view(1, 1, -1)
+    Y = xs[1].view(1, -1, 1)
+    Z = xs[2].view(-1, 1, 1)
+    P = torch.empty((9, n[2], n[1], n[0]), dtype=torch.float64, device=dev)
+    tp = 2.0 * np.pi
+    P[0] = 1.0 + 0.2 * torch.sin(tp * X / 15.0) * torch.cos(tp * Y / 13.0)
+    P[1] = 0.3 + 0.05 * torch.cos(tp * Z / 11.0)
+    P[2] = 0.1 * torch.sin(tp * Y / 17.0)
+    P[3] = 0.1 * torch.cos(tp * Z / 19.0)
+    P[4] = 0.05 * torch.sin(tp * X / 23.0)
+    P[5], P[6], P[7], P[8] = 0.3, 0.1, 0.05, 0.0
+    return P
+
+
+def test_largest_grid_64bit_offsets(G, orc):
+    """A 648 x 640 x 632 grid in the curved metric, one SSP-RK3 step: 262M
+    cells, so the variable strides of the caches, faces and user arrays put
+    element offsets past 2^31 (byte offsets past 2^34).  Sampled cells,
+    including the last ones, recomputed by the oracle on the 13^3 box around
+    each (boxes at the domain's edge share its zero-gradient boundary)."""
+    n = (648, 640, 632)
+    lo, hi = (-30.0, -30.0, -30.0), (30.0, 30.0, 30.0)
+    dx = [(hi[d] - lo[d]) / n[d] for d in range(3)]
+    kw = dict(n=n, lo=lo, hi=hi, bc=(WL.OUTFLOW,) * 3, metric=WL.ISO_SCHW, M=1.0, soft=0, r_min=1.0,
+              gamma=5.0 / 3.0, rk_order=3, c_h=1.0, kappa=1.0, rho_atm=1e-10, p_atm=1e-12)
+    dt = WL.cfl_dt(n, lo, hi)
+    P = _large_grid_fields(n, lo, dx, DEV)
+    s = G.Solver(device=DEV, **kw)
+    U = s.cons(P)
+    s.step(U, dt)
+    torch.cuda.synchronize()
+    say("GPU step on %s done" % (n,), s.status())
+    scale = U.abs().reshape(9, -1).amax(dim=1).cpu().numpy()
+    R = 6
+    picks = [(0, 0, 0), (n[0] - 1, n[1] - 1, n[2] - 1), (n[0] // 2, n[1] // 2, n[2] // 2),
+             (17, 600, 631), (647, 3, 400), (320, 639, 0), (500, 250, 620)]
+    worst = np.zeros(9)
+    for (i, j, k) in picks:
+        lo_i = [max(c - R, 0) for c in (i, j, k)]
+        hi_i = [min(c + R, n[d] - 1) for d, c in enumerate((i, j, k))]
+        sub = np.ascontiguousarray(P[:, lo_i[2]:hi_i[2] + 1, lo_i[1]:hi_i[1] + 1, lo_i[0]:hi_i[0] + 1].cpu().numpy())
+        sk = dict(kw)
+        sk["n"] = tuple(hi_i[d] - lo_i[d] + 1 for d in range(3))
+        sk["lo"] = tuple(lo[d] + lo_i[d] * dx[d] for d in range(3))
+        sk["hi"] = tuple(lo[d] + (hi_i[d] + 1) * dx[d] for d in range(3))
+        pb = orc.Problem(**sk)
+        Ur, _, _ = orc.step(pb, orc.prim2con(pb, sub), sub, dt, 1)
+        ref = Ur[:, k - lo_i[2], j - lo_i[1], i - lo_i[0]]
+        got = U[:, k, j, i].cpu().numpy()
+        worst = np.maximum(worst, np.abs(got - ref) / np.maximum(scale, 1e-300))
+    say("largest grid sampled max err / scale", worst)
+    del U, P, s
+    torch.cuda.empty_cache()
+    assert np.all(worst <= 1e-12)
+
+
 # ---------------------------------------------------------------------------
 # exactness, determinism, failure policy, graph replay
 
