@@ -34,6 +34,8 @@ struct Dev {
     int c2p1d;       // recovery: 0 Newton on (Wc, v^2), 1 Newton on Wc alone
     int ppm;         // reconstruction: 0 MC (2 ghosts), 1 PPM (3 ghosts)
     int ct;          // divergence control: 0 cleaning (Phi), 1 flux-CT (Phi carried)
+    int nt;          // grid past the last-level cache: the kernel instances that
+                     // stream once-touched arrays with nontemporal accesses
     // stored metric: at cell centres [8][N] (alpha, psi^4, d_x,y,z alpha,
     // d_x,y,z psi^4), at the faces of axis a [2][nf[a]] (alpha, psi^4)
     const double* mc;

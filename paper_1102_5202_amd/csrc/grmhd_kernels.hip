@@ -30,6 +30,7 @@ namespace grmhd {
 
 static constexpr int BLOCK = 256;
 static constexpr int MARCH_SEG = 8;   // faces (cells) per thread in the z marches
+static constexpr unsigned MIN_BLOCKS = 1024;   // 4 workgroups per CU: enough to fill the GPU
 
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -98,22 +99,27 @@ __device__ __forceinline__ long long cache_index(const Dev& d, int i, int j, int
     return ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + (i + d.g[0]);
 }
 
-template <int D, int KIND, typename T>
+template <int D, int KIND, bool NT, typename T>
 __device__ __forceinline__ void face_store(T* qL, T* qR, double x, double y, double z, const Dev& d,
                                            T* __restrict__ F, long long NF, long long f)
 {
     T Fo[9];
     face_flux<D, KIND>(qL, qR, x, y, z, f, d, Fo);
-    // the face records are read back by another kernel, not by this one:
-    // nontemporal stores (the y march 7 % faster, measured; nontemporal
-    // stores of the update's new primitives measured slower and are not used)
+    // the face records are read back by another kernel, not by this one: on
+    // large grids (NT) nontemporal stores
+    if constexpr (NT) {
 #pragma unroll
-    for (int v = 0; v < 9; ++v)
-        __builtin_nontemporal_store(Fo[v], &F[v * NF + f]);
+        for (int v = 0; v < 9; ++v)
+            __builtin_nontemporal_store(Fo[v], &F[v * NF + f]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            F[v * NF + f] = Fo[v];
+    }
 }
 
 // x faces: one thread per face (the x stencil of a wave shares cache lines).
-template <int KIND, typename T>
+template <int KIND, bool NT, typename T>
 __global__ __launch_bounds__(BLOCK) void k_flux_x(const T* __restrict__ Pc, T* __restrict__ F, Dev d)
 {
     long long f = (long long)blockIdx.x * BLOCK + threadIdx.x;
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux_x(const T* __restrict__ Pc, T* _
         qL[v] = q1 + half * mc_slope(q0, q1, q2);
         qR[v] = q2 - half * mc_slope(q1, q2, q3);
     }
-    face_store<0, KIND>(qL, qR, d.lo[0] + i * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
+    face_store<0, KIND, NT>(qL, qR, d.lo[0] + i * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
                         d.lo[2] + (k + 0.5) * d.dx[2], d, F, d.nf[0], f);
 }
 
@@ -143,7 +149,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux_x(const T* __restrict__ Pc, T* _
 // fixed (i, other transverse index).  Moving from face f-1/2 to f+1/2 it keeps
 // q_f, q_{f+1} and the MC slope of cell f, so each face loads one new cell
 // (9 values instead of 36) and computes one slope instead of two.
-template <int D, int KIND, int SEG, typename T>
+template <int D, int KIND, int SEG, bool NT, typename T>
 __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, T* __restrict__ F, Dev d)
 {
     constexpr int O = D == 1 ? 2 : 1;          // the other transverse axis
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, 
             qc[v] = qd;
         }
         xyz[D] = d.lo[D] + f * d.dx[D];
-        face_store<D, KIND>(qL, qR, xyz[0], xyz[1], xyz[2], d, F, NF, fidx);
+        face_store<D, KIND, NT>(qL, qR, xyz[0], xyz[1], xyz[2], d, F, NF, fidx);
         fidx += fstr;
     }
 }
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, 
 // Faces along D with PPM reconstruction: one thread per face, the six cells
 // f-3 .. f+2 along D; the left state is the right edge of cell f-1, the
 // right state the left edge of cell f.  Needs 3 ghost layers.
-template <int D, int KIND, typename T>
+template <int D, int KIND, bool NT, typename T>
 __global__ __launch_bounds__(BLOCK) void k_flux_ppm(const T* __restrict__ Pc, T* __restrict__ F, Dev d)
 {
     const long long NF = d.nf[D];
@@ -241,7 +247,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux_ppm(const T* __restrict__ Pc, T*
 #pragma unroll
     for (int e = 0; e < 3; ++e)
         pos[e] = e == D ? d.lo[e] + fi[e] * d.dx[e] : d.lo[e] + (fi[e] + 0.5) * d.dx[e];
-    face_store<D, KIND>(qL, qR, pos[0], pos[1], pos[2], d, F, NF, f);
+    face_store<D, KIND, NT>(qL, qR, pos[0], pos[1], pos[2], d, F, NF, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,27 +476,37 @@ __device__ __forceinline__ void store_prim(const Dev& d, T* __restrict__ P, long
 // their ghost images).  TS and TO are the types of the stage states read and
 // written: double, or float for the intermediate stages of the mixed path.
 // fout (may be null) receives the cell's recovery flags.
-template <typename T, typename TS, typename TO>
+template <bool NT, typename T, typename TS, typename TO>
 __device__ __forceinline__ int stage_cell(const Dev& d, const Geo& g, const double* R, const T* q,
                                           const double* Un, const TS* Us, TO* Uout, long long c,
                                           T* Pout, long long pc, int i, int j, int k, double dt,
                                           double a, double b, unsigned char* fout, int& iters)
 {
-    // U^n, U^s and U^(s+1) are touched once per cell and substep: nontemporal
-    // accesses keep them from displacing the face records and primitives that
-    // neighbouring workgroups read again (update 6 % faster, measured)
+    // U^n, U^s and U^(s+1) are touched once per cell and substep: on large
+    // grids (NT) nontemporal accesses keep them from displacing the face
+    // records and primitives that neighbouring workgroups read again
     double u[9], p[9], qg[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
-        double un = __builtin_nontemporal_load(&Un[v * d.N + c]);
-        double us = (double)__builtin_nontemporal_load(&Us[v * d.N + c]);
+        double un, us;
+        if constexpr (NT) {
+            un = __builtin_nontemporal_load(&Un[v * d.N + c]);
+            us = (double)__builtin_nontemporal_load(&Us[v * d.N + c]);
+        } else {
+            un = Un[v * d.N + c];
+            us = (double)Us[v * d.N + c];
+        }
         u[v] = us + a * (un - us) + b * (dt * R[v]);
         qg[v] = (double)q[v];
     }
     int flags = recover_cell(d, g, u, qg, p, iters);
 #pragma unroll
-    for (int v = 0; v < 9; ++v)
-        __builtin_nontemporal_store((TO)u[v], &Uout[v * d.N + c]);
+    for (int v = 0; v < 9; ++v) {
+        if constexpr (NT)
+            __builtin_nontemporal_store((TO)u[v], &Uout[v * d.N + c]);
+        else
+            Uout[v * d.N + c] = (TO)u[v];
+    }
     store_prim(d, Pout, pc, i, j, k, p);
     if (fout)
         fout[c] = (unsigned char)flags;
@@ -500,7 +516,7 @@ __device__ __forceinline__ int stage_cell(const Dev& d, const Geo& g, const doub
 // 1D/2D update: flux differences, sources, RK combination and recovery of the
 // primitives for every cell.  The cell's primitives are read from Pc and the
 // new ones written to Pn (which may be Pc: each thread reads only its own cell).
-template <int KIND, typename T, typename TS, typename TO>
+template <int KIND, bool NT, typename T, typename TS, typename TO>
 __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, const T* __restrict__ Fy,
                                                  const T* __restrict__ Fz, const T* Pc, T* Pn,
                                                  const double* Un, const TS* Us, TO* Uout, Dev d,
@@ -524,7 +540,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, cons
         Geo g;
         rhs_cell<KIND>(d, Fx, Fy, Fz, c, i, j, k, q, g, R);
         int iters = 0;
-        int flags = stage_cell(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
+        int flags = stage_cell<NT>(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
         tally(flags, iters, nf, na, np, nb, itmax);
     }
     count_sums(cnt, nf, na, np, nb, itmax);
@@ -537,7 +553,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, cons
 // x/y face fluxes, adds the sources, combines the RK stage and recovers the
 // primitives, written to the other primitive cache Pn (segments of one column
 // overlap by two cells, so the cache read here cannot be updated in place).
-template <int KIND, int SEG, typename T, typename TS, typename TO>
+template <int KIND, int SEG, bool NT, typename T, typename TS, typename TO>
 __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
     const T* __restrict__ Fx, const T* __restrict__ Fy, const T* __restrict__ Pc, T* __restrict__ Pn,
     const double* Un, const TS* Us, TO* Uout, Dev d, double dt, double a, double b,
@@ -650,7 +666,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
             add_sources<KIND>(d, x, y, z, c, q, g, R);
             int iters = 0;
             const long long pc = col + (long long)(k + d.g[2]) * st;
-            int flags = stage_cell(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
+            int flags = stage_cell<NT>(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
             tally(flags, iters, nfail, natm, npf, nfb, itmax);
         }
     }
@@ -1018,32 +1034,38 @@ hipError_t launch_ghosts(T* Pc, const Dev& d, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int KIND, typename T>
+template <int KIND, bool NT, typename T>
 static hipError_t launch_flux_k(int dir, const T* Pc, T* F, const Dev& d, hipStream_t s)
 {
     if (d.ppm) {
         const unsigned nb = blocks_for(d.nf[dir]);
         if (dir == 0)
-            hipLaunchKernelGGL((k_flux_ppm<0, KIND, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+            hipLaunchKernelGGL((k_flux_ppm<0, KIND, NT, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
         else if (dir == 1)
-            hipLaunchKernelGGL((k_flux_ppm<1, KIND, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+            hipLaunchKernelGGL((k_flux_ppm<1, KIND, NT, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
         else
-            hipLaunchKernelGGL((k_flux_ppm<2, KIND, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+            hipLaunchKernelGGL((k_flux_ppm<2, KIND, NT, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
         return hipGetLastError();
     }
     if (dir == 0) {
-        hipLaunchKernelGGL((k_flux_x<KIND, T>), dim3(blocks_for(d.nf[0])), dim3(BLOCK), 0, s, Pc, F, d);
+        hipLaunchKernelGGL((k_flux_x<KIND, NT, T>), dim3(blocks_for(d.nf[0])), dim3(BLOCK), 0, s, Pc, F, d);
     } else {
         const int o = dir == 1 ? 2 : 1;
-        // faces per thread: 12 along y (fewer re-read window cells than 8: the
-        // y kernel 4 % faster, measured), 8 along z
-        const int seg = dir == 1 ? 12 : MARCH_SEG;
+        // faces per thread along y: 12 (fewer re-read window cells than 8: the
+        // y kernel 4 % faster at 192^3, measured) where that still gives
+        // MIN_BLOCKS workgroups, else 2 (small grids: the whole GPU busy);
+        // 8 along z
+        const long long lines = (long long)d.n[0] * d.n[o];
+        const bool longy = blocks_for(lines * ((d.n[1] + 1 + 11) / 12)) >= MIN_BLOCKS;
+        const int seg = dir == 1 ? (longy ? 12 : 2) : MARCH_SEG;
         long long nseg = (d.n[dir] + 1 + seg - 1) / seg;
-        unsigned nb = blocks_for((long long)d.n[0] * d.n[o] * nseg);
-        if (dir == 1)
-            hipLaunchKernelGGL((k_flux_march<1, KIND, 12, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+        unsigned nb = blocks_for(lines * nseg);
+        if (dir == 1 && longy)
+            hipLaunchKernelGGL((k_flux_march<1, KIND, 12, NT, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+        else if (dir == 1)
+            hipLaunchKernelGGL((k_flux_march<1, KIND, 2, NT, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
         else
-            hipLaunchKernelGGL((k_flux_march<2, KIND, MARCH_SEG, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
+            hipLaunchKernelGGL((k_flux_march<2, KIND, MARCH_SEG, NT, T>), dim3(nb), dim3(BLOCK), 0, s, Pc, F, d);
     }
     return hipGetLastError();
 }
@@ -1139,9 +1161,32 @@ hipError_t launch_ct(T* const* F, T* const* W, const Dev& d, hipStream_t s)
 template <typename T>
 hipError_t launch_flux(int kind, int dir, const T* Pc, T* F, const Dev& d, hipStream_t s)
 {
+    if (d.nt) {
+        if (kind == FLAT)
+            return launch_flux_k<FLAT, true>(dir, Pc, F, d, s);
+        return kind == ISO ? launch_flux_k<ISO, true>(dir, Pc, F, d, s)
+                           : launch_flux_k<STORED, true>(dir, Pc, F, d, s);
+    }
     if (kind == FLAT)
-        return launch_flux_k<FLAT>(dir, Pc, F, d, s);
-    return kind == ISO ? launch_flux_k<ISO>(dir, Pc, F, d, s) : launch_flux_k<STORED>(dir, Pc, F, d, s);
+        return launch_flux_k<FLAT, false>(dir, Pc, F, d, s);
+    return kind == ISO ? launch_flux_k<ISO, false>(dir, Pc, F, d, s) : launch_flux_k<STORED, false>(dir, Pc, F, d, s);
+}
+
+template <bool NT, typename T, typename TS, typename TO>
+static void launch_update_nt(int kind, const T* Fx, const T* Fy, const T* Fz, const T* Pc, T* Pn, const double* Un,
+                             const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
+                             unsigned long long* cnt, unsigned char* fout, hipStream_t s)
+{
+    unsigned nb = blocks_for(d.N);
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_update<FLAT, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
+                           Uout, d, dt, a, b, cnt, fout);
+    else if (kind == ISO)
+        hipLaunchKernelGGL((k_update<ISO, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
+                           Uout, d, dt, a, b, cnt, fout);
+    else
+        hipLaunchKernelGGL((k_update<STORED, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un,
+                           Us, Uout, d, dt, a, b, cnt, fout);
 }
 
 template <typename T, typename TS, typename TO>
@@ -1149,17 +1194,33 @@ hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, const 
                          const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
                          unsigned long long* cnt, unsigned char* fout, hipStream_t s)
 {
-    unsigned nb = blocks_for(d.N);
-    if (kind == FLAT)
-        hipLaunchKernelGGL((k_update<FLAT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
-                           Uout, d, dt, a, b, cnt, fout);
-    else if (kind == ISO)
-        hipLaunchKernelGGL((k_update<ISO, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un, Us,
-                           Uout, d, dt, a, b, cnt, fout);
+    if (d.nt)
+        launch_update_nt<true>(kind, Fx, Fy, Fz, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
     else
-        hipLaunchKernelGGL((k_update<STORED, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Fz, Pc, Pn, Un,
-                           Us, Uout, d, dt, a, b, cnt, fout);
+        launch_update_nt<false>(kind, Fx, Fy, Fz, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
     return hipGetLastError();
+}
+
+template <bool NT, int SEG, typename T, typename TS, typename TO>
+static void launch_update_zmarch_nt(int kind, const T* Fx, const T* Fy, const T* Pc, T* Pn, const double* Un,
+                                    const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
+                                    unsigned long long* cnt, unsigned char* fout, hipStream_t s)
+{
+    // cells per thread: with a float cache a longer march (fewer re-read
+    // window cells) pays, 1.5 %; with a double cache 8 is the fastest.  The
+    // caller picks SEG = 2 where the long march would leave the GPU short of
+    // workgroups (small grids).
+    long long nseg = (d.n[2] + SEG - 1) / SEG;
+    unsigned nb = blocks_for((long long)d.n[0] * d.n[1] * nseg);
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_update_zmarch<FLAT, SEG, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
+                           Un, Us, Uout, d, dt, a, b, cnt, fout);
+    else if (kind == ISO)
+        hipLaunchKernelGGL((k_update_zmarch<ISO, SEG, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
+                           Un, Us, Uout, d, dt, a, b, cnt, fout);
+    else
+        hipLaunchKernelGGL((k_update_zmarch<STORED, SEG, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc,
+                           Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
 }
 
 template <typename T, typename TS, typename TO>
@@ -1167,20 +1228,16 @@ hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc,
                                 const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
                                 unsigned long long* cnt, unsigned char* fout, hipStream_t s)
 {
-    // cells per thread: with a float cache a longer march (fewer re-read
-    // window cells) pays, 1.5 %; with a double cache 8 is the fastest
-    constexpr int SEG = sizeof(T) < sizeof(double) ? 12 : MARCH_SEG;
-    long long nseg = (d.n[2] + SEG - 1) / SEG;
-    unsigned nb = blocks_for((long long)d.n[0] * d.n[1] * nseg);
-    if (kind == FLAT)
-        hipLaunchKernelGGL((k_update_zmarch<FLAT, SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
-                           Un, Us, Uout, d, dt, a, b, cnt, fout);
-    else if (kind == ISO)
-        hipLaunchKernelGGL((k_update_zmarch<ISO, SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
-                           Un, Us, Uout, d, dt, a, b, cnt, fout);
+    constexpr int LONG = sizeof(T) < sizeof(double) ? 12 : MARCH_SEG;
+    const bool lng = blocks_for((long long)d.n[0] * d.n[1] * ((d.n[2] + LONG - 1) / LONG)) >= MIN_BLOCKS;
+    if (d.nt && lng)
+        launch_update_zmarch_nt<true, LONG>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
+    else if (d.nt)
+        launch_update_zmarch_nt<true, 2>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
+    else if (lng)
+        launch_update_zmarch_nt<false, LONG>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
     else
-        hipLaunchKernelGGL((k_update_zmarch<STORED, SEG, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc,
-                           Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
+        launch_update_zmarch_nt<false, 2>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
     return hipGetLastError();
 }
 
