@@ -10,7 +10,7 @@
 // (Ub^s = (1 - a_s) Ub~, Ub^n += a_s Ub~, Rb = b_s dt Ub~), then the
 // right-hand side's adjoint at P^s:
 //   k_adj_rec      the recovery + RK adjoint of the last stage (Pb = 0);
-//   k_adj_face<D>  per face along D: the flux cotangent (Rb_right - Rb_left)/dx
+//   k_adj_face     per face of every axis: the flux cotangent (Rb_right - Rb_left)/dx
 //                  pulled back through HLLE, the cleaning pair and the face
 //                  physics to the reconstructed left/right states;
 //   k_adj_gather   per cell and per ghost position: those pulled back
@@ -140,15 +140,13 @@ __device__ __forceinline__ void face_flux_rev(const double* qL0, const double* q
     qRb[8] += -0.5 * d.ic_h * Bsb + 0.5 * phb;
 }
 
-// One thread per face along D.  Face f sits between cells f-1 and f; the
+// Face f along D (one thread).  Face f sits between cells f-1 and f; the
 // flux cotangent is (Rb_f - Rb_(f-1)) / dx with out-of-domain cells absent.
 template <int D, int KIND>
-__global__ __launch_bounds__(ABLOCK) void k_adj_face(const double* __restrict__ Pc,
-                                                      const double* __restrict__ Rb,
-                                                      double* __restrict__ FB, Dev d)
+__device__ __forceinline__ void adj_face(long long f, const double* __restrict__ Pc,
+                                         const double* __restrict__ Rb, double* __restrict__ FB, const Dev& d)
 {
     const long long nf = d.nf[D];
-    const long long f = (long long)blockIdx.x * ABLOCK + threadIdx.x;
     if (f >= nf)
         return;
     int m[3] = {d.n[0], d.n[1], d.n[2]};
@@ -200,6 +198,29 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_face(const double* __restrict__ 
         FB[v * nf + f] = qLb[v];
         FB[(9 + v) * nf + f] = qRb[v];
     }
+}
+
+// The faces of every active axis in one launch: workgroups [0, nb0) take x
+// faces, the next nb1 y faces, the rest z faces (one launch instead of three
+// leaves one partly filled last wave of workgroups instead of three).
+template <int KIND>
+__global__ __launch_bounds__(ABLOCK) void k_adj_face(const double* __restrict__ Pc,
+                                                      const double* __restrict__ Rb,
+                                                      double* __restrict__ FB0, double* __restrict__ FB1,
+                                                      double* __restrict__ FB2, Dev d, unsigned nb0, unsigned nb1)
+{
+    unsigned b = blockIdx.x;
+    if (b < nb0) {
+        adj_face<0, KIND>((long long)b * ABLOCK + threadIdx.x, Pc, Rb, FB0, d);
+        return;
+    }
+    b -= nb0;
+    if (b < nb1) {
+        adj_face<1, KIND>((long long)b * ABLOCK + threadIdx.x, Pc, Rb, FB1, d);
+        return;
+    }
+    b -= nb1;
+    adj_face<2, KIND>((long long)b * ABLOCK + threadIdx.x, Pc, Rb, FB2, d);
 }
 
 // Cotangent of primitive v at position ci (ci[D] in -2 .. n+1, ghosts of
@@ -707,24 +728,22 @@ hipError_t launch_adj_cell(int kind, const double* Pc, const double* MU, const d
     return hipGetLastError();
 }
 
-template <int KIND>
-static hipError_t adj_face_k(int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
-                             hipStream_t s)
-{
-    const unsigned nb = ablocks(d.nf[dir]);
-    if (dir == 0)
-        hipLaunchKernelGGL((k_adj_face<0, KIND>), dim3(nb), dim3(ABLOCK), 0, s, Pc, Rb, FB, d);
-    else if (dir == 1)
-        hipLaunchKernelGGL((k_adj_face<1, KIND>), dim3(nb), dim3(ABLOCK), 0, s, Pc, Rb, FB, d);
-    else
-        hipLaunchKernelGGL((k_adj_face<2, KIND>), dim3(nb), dim3(ABLOCK), 0, s, Pc, Rb, FB, d);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_face(int kind, int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
+hipError_t launch_adj_face(int kind, const double* Pc, const double* Rb, double* const* FB, const Dev& d,
                            hipStream_t s)
 {
-    return kind == FLAT ? adj_face_k<FLAT>(dir, Pc, Rb, FB, d, s) : adj_face_k<ISO>(dir, Pc, Rb, FB, d, s);
+    unsigned nb[3];
+    for (int a = 0; a < 3; ++a)
+        nb[a] = d.act[a] ? ablocks(d.nf[a]) : 0;
+    const unsigned total = nb[0] + nb[1] + nb[2];
+    if (total == 0)
+        return hipSuccess;
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_adj_face<FLAT>), dim3(total), dim3(ABLOCK), 0, s, Pc, Rb, FB[0], FB[1], FB[2], d,
+                           nb[0], nb[1]);
+    else
+        hipLaunchKernelGGL((k_adj_face<ISO>), dim3(total), dim3(ABLOCK), 0, s, Pc, Rb, FB[0], FB[1], FB[2], d,
+                           nb[0], nb[1]);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_final(int kind, const double* Ub, const double* Pb, const double* P0, const double* Unacc,

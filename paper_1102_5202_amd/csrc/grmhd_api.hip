@@ -535,18 +535,13 @@ int reverse_sweep(grmhd_ctx* c, const double* const* Ps, const unsigned char* fl
     if (rc)
         return rc;
     for (int s = ns - 1; s >= 0; --s) {
-        bool any = false;
-        for (int dir = 0; dir < 3; ++dir) {
-            if (!c->d.act[dir])
-                continue;
+        const bool any = c->d.act[0] || c->d.act[1] || c->d.act[2];
+        if (any) {
             rc = timed(c, GRMHD_K_ADJ_FACE, [&] {
-                return grmhd::launch_adj_face(c->kind, dir, Ps[s], c->Rb, c->FB[dir], c->d, c->stream);
+                return grmhd::launch_adj_face(c->kind, Ps[s], c->Rb, c->FB, c->d, c->stream);
             });
             if (rc)
                 return rc;
-            any = true;
-        }
-        if (any) {
             rc = timed(c, GRMHD_K_ADJ_GATHER, [&] {
                 return grmhd::launch_adj_gather(Ps[s], c->FB, c->MU, c->GMU, c->d, c->stream);
             });

@@ -95,7 +95,7 @@ hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* 
 // primitives.
 hipError_t launch_adj_rec(int kind, double* Ub, const double* Pn, const unsigned char* flags, double* Unacc,
                           double* Rb, const Dev& d, double a, double b, double dt, hipStream_t s);
-hipError_t launch_adj_face(int kind, int dir, const double* Pc, const double* Rb, double* FB, const Dev& d,
+hipError_t launch_adj_face(int kind, const double* Pc, const double* Rb, double* const* FB, const Dev& d,
                            hipStream_t s);
 hipError_t launch_adj_gather(const double* Pc, const double* const* FB, double* MU, double* const* G, const Dev& d,
                              hipStream_t s);
