@@ -755,10 +755,10 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     d.ppm = opts->reconstruction == GRMHD_RECON_PPM;
     d.ct = opts->divergence == GRMHD_DIV_FLUXCT;
     // Nontemporal accesses for the once-touched arrays pay where a substep's
-    // arrays are far larger than the 256 MB Infinity Cache (192^3: the update
-    // 8 % faster) and cost where they would fit in it (64^3: a step 17 %
-    // slower), measured: on from 2^21 cells (128^3)
-    d.nt = d.N >= (1LL << 21);
+    // arrays are larger than the 256 MB Infinity Cache (192^3: the update 8 %
+    // faster; 128^3: the step 8 %; 96^3: 4 %) and cost where they would fit
+    // in it (64^3: a step 7 % slower), measured: on from 2^19 cells (80^3)
+    d.nt = d.N >= (1LL << 19);
 
     c->ws = (unsigned char*)opts->workspace;
     c->cnt = (unsigned long long*)(c->ws + L.off_cnt);
