@@ -272,6 +272,21 @@ def test_smallest_grids(G, orc, case):
     assert st["fail"] == sto["fail"] and st["atm"] == sto["atm"]
 
 
+def test_streaming_instances_full_run(G, orc):
+    """A grid just past the size where the kernels switch to their
+    nontemporal instances (82 x 81 x 80 = 531,360 cells >= 2^19) and short
+    enough for the short marches, in the curved metric: 4 SSP-RK3 steps
+    against the oracle over every cell."""
+    w = WL.config3(n=(82, 81, 80), nsteps=4)
+    assert 82 * 81 * 80 >= 1 << 19
+    U, P, st, _ = gpu_run(G, w, w.nsteps)
+    Ur, Pr, sto, _ = oracle_run(orc, w, w.nsteps)
+    err = rel_l1(U, Ur)
+    say("streaming instances rel-L1", err, st, sto)
+    assert np.all(err <= 1e-10)
+    assert st["fail"] == sto["fail"]
+
+
 def _large_grid_fields(n, lo, dx, dev):
     """Smooth analytic primitives on an n[0] x n[1] x n[2] grid, built on the
     device (9 x 262M values would take minutes on the host)."""
