@@ -398,6 +398,43 @@ def test_failure_policy_matches_oracle(G, orc):
     assert s.status()["fail"] == 0
 
 
+@pytest.mark.filterwarnings("ignore:invalid value encountered in sqrt")
+def test_negative_pressure_roots_match_oracle(G, orc):
+    """States whose recovery root lies below D (at rest or W <= 1.01, p < 0):
+    the GPU recovery finds the same root as the oracle and takes the same
+    pressure floor (flags counted alike, P equal to rounding)."""
+    from tests.test_oracle_point import _below_d_states, metric_iso
+    for w in (WL.config2(n=(10, 9, 8)), WL.config3(n=(12, 10, 9))):
+        kw = {**w.problem_kwargs(), "rho_atm": 1e-10, "p_atm": 1e-9}
+        pb = orc.Problem(**kw)
+        gamma = kw["gamma"]
+        rng = np.random.default_rng(47)
+        nz, ny, nx = w.P.shape[1:]
+        P = np.empty_like(w.P)
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    if kw["metric"] == orc.FLAT:
+                        psi4 = 1.0
+                    else:
+                        x = [kw["lo"][a] + (c + 0.5) * (kw["hi"][a] - kw["lo"][a]) / kw["n"][a]
+                             for a, c in enumerate((i, j, k))]
+                        psi4 = metric_iso(*x)[1]
+                    P[:, k, j, i] = _below_d_states(rng, gamma, psi4, 1 + (i + j + k) % 2)[-1]
+        U = orc.prim2con(pb, P)
+        Pg = P * (1.0 + 1e-3 * rng.uniform(-1, 1, P.shape))
+        s = G.solver_for(w, device=DEV, rho_atm=1e-10, p_atm=1e-9)
+        s.cons(torch.from_numpy(Pg).to(DEV))
+        Pd = s.prim(torch.from_numpy(U).to(DEV)).cpu().numpy()
+        st = s.status(reset=True)
+        Pr, _, flags, sto = orc.con2prim(pb, U, Pg)
+        say(w.name, st, sto)
+        assert sto == {"fail": 0, "atm": 0, "pfloor": P[0].size}
+        assert (st["fail"], st["atm"], st["pfloor"]) == (0, 0, P[0].size)
+        assert np.all(Pd[1] == kw["p_atm"])
+        np.testing.assert_allclose(Pd, Pr, rtol=1e-12, atol=1e-14)
+
+
 def test_graph_replay_matches_eager(G):
     """A captured step replayed several times (with eager work and
     synchronisation between replays) equals eager steps, bitwise."""

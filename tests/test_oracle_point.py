@@ -349,3 +349,101 @@ def test_face_cleaning_pair_is_exact_linear_riemann_solution(orc):
         phis, Bs = F[5], F[8] / c_h ** 2
         np.testing.assert_allclose(phis + c_h * Bs, qL[8] + c_h * qL[5], rtol=1e-13, atol=1e-14)
         np.testing.assert_allclose(phis - c_h * Bs, qR[8] - c_h * qR[5], rtol=1e-13, atol=1e-14)
+
+
+def _below_d_states(rng, gamma, psi4, count):
+    """States whose recovery root lies below D (Wc = w W^2 < D = rho W, i.e.
+    h W < 1): at rest or slow (W <= 1.01) with a negative pressure large
+    enough that h = 1 + gamma/(gamma-1) p/rho < 1/W.  Magnetised."""
+    out = []
+    while len(out) < count:
+        rho = 10 ** rng.uniform(-3, 1)
+        slow = len(out) % 2 == 1
+        W = 1.0 + (10 ** rng.uniform(-6, -2) if slow else 0.0)
+        # h W < 1 needs -p/rho > (gamma-1)/gamma (1 - 1/W); take 2-50x that,
+        # floored at 1e-8 (at rest any p < 0 has its root below D)
+        need = (gamma - 1.0) / gamma * (1.0 - 1.0 / W)
+        p = -rho * max(need * 10 ** rng.uniform(np.log10(2.0), np.log10(50.0)), 1e-8 * 10 ** rng.uniform(0, 3))
+        if -p / rho >= 0.5 * (gamma - 1.0) / gamma:
+            continue                 # keep h > 0 by a margin
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        ut = np.sqrt(W * W - 1.0) * n / np.sqrt(psi4)
+        B = rng.normal(size=3) * np.sqrt(rho) * 10 ** rng.uniform(-2, 0)
+        P = np.array([rho, p, *ut, *B, 0.0])
+        tb = textbook(P, gamma, psi4=psi4)[3]
+        assert tb["w"] * tb["W"] ** 2 < rho * tb["W"]       # the root is below D
+        out.append(P)
+    return out
+
+
+@pytest.mark.filterwarnings("ignore:invalid value encountered in sqrt")
+@pytest.mark.parametrize("metric", ["flat", "curved"])
+def test_recovery_root_below_d_negative_pressure(orc, metric):
+    """The bracket's search below Wc = D: conserved states of a fluid at rest or
+    nearly so (W <= 1.01) with p < 0, built by the textbook formulas, are
+    recovered with their negative pressure (the point recovery accepts roots
+    with h W < 1); the error bound is the conditioning of p against the
+    energy density, as in the round-trip pin."""
+    rng = np.random.default_rng(41)
+    pts = [(0.0, 0.0, 0.0)] if metric == "flat" else POINTS
+    for (x, y, z) in pts:
+        alpha, psi4 = (1.0, 1.0) if metric == "flat" else metric_iso(x, y, z)
+        mk = {} if metric == "flat" else dict(metric=orc.ISO_SCHW, M=1.0)
+        for gamma in GAMMAS:
+            for P in _below_d_states(rng, gamma, psi4, 40 // len(pts) + 2):
+                U_ref = textbook(P, gamma, alpha=alpha, psi4=psi4)[0]
+                P2, ok = orc.point_c2p(U_ref, gamma, x, y, z, **mk)
+                assert ok, P
+                W = np.sqrt(1 + psi4 * P[2:5] @ P[2:5])
+                assert P2[1] < 0.0
+                en = (U_ref[1] + U_ref[0]) / U_ref[0]
+                assert abs(P2[1] - P[1]) <= 1e-13 * max(abs(P[1]), en * P[0])
+                assert abs(P2[0] - P[0]) <= 1e-13 * P[0]
+                assert np.abs(P2[2:5] - P[2:5]).max() <= 1e-13 * max(W - 1.0, 1e-3)
+                assert np.abs(P2[5:8] - P[5:8]).max() <= 1e-15 * np.abs(P[5:8]).max()
+
+
+@pytest.mark.filterwarnings("ignore:invalid value encountered in sqrt")
+@pytest.mark.parametrize("metric", ["flat", "curved"])
+def test_negative_pressure_root_takes_the_pressure_floor(orc, metric):
+    """The cell recovery after a root below D: the pressure is raised to p_atm,
+    only the pressure-floor flag is set, density, velocity and field keep their
+    recovered values, and the matter part of U is rebuilt from the floored
+    primitives (textbook formulas); the field and Phi rows are untouched."""
+    rng = np.random.default_rng(43)
+    gamma = 5.0 / 3.0
+    n = 24
+    if metric == "flat":
+        kw = dict(n=(n, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                  bc=(orc.OUTFLOW,) * 3, gamma=gamma)
+        xs = [((i + 0.5) / n, 0.5, 0.5) for i in range(n)]
+        geo = [(1.0, 1.0)] * n
+    else:
+        kw = dict(n=(n, 1, 1), lo=(-3.0, 0.7, -0.4), hi=(9.0, 1.7, 0.6),
+                  bc=(orc.OUTFLOW,) * 3, gamma=gamma, metric=orc.ISO_SCHW, M=1.0)
+        xs = [(-3.0 + (i + 0.5) * 0.5, 1.2, 0.1) for i in range(n)]
+        geo = [metric_iso(*x) for x in xs]
+    pb = orc.Problem(rho_atm=1e-10, p_atm=1e-9, **kw)
+    Ps = []
+    for i in range(n):
+        Ps.append(_below_d_states(rng, gamma, geo[i][1], 1 + i % 2)[-1])
+    P = np.array(Ps).T.reshape(9, 1, 1, n).copy()
+    U = np.zeros_like(P)
+    for i in range(n):
+        U[:, 0, 0, i] = textbook(P[:, 0, 0, i], gamma, alpha=geo[i][0], psi4=geo[i][1])[0]
+    Pn, Ua, flags, st = orc.con2prim(pb, U, P)
+    assert np.all(flags == orc.FLAG_PFLOOR)
+    assert st == {"fail": 0, "atm": 0, "pfloor": n}
+    assert np.all(Pn[1] == pb.p_atm)
+    np.testing.assert_allclose(Pn[0], P[0], rtol=1e-13)
+    assert np.abs(Pn[2:5] - P[2:5]).max() <= 1e-15
+    np.testing.assert_allclose(Pn[5:8], P[5:8], rtol=1e-15, atol=1e-15 * np.abs(P[5:8]).max())
+    for i in range(n):
+        Pf = Pn[:, 0, 0, i].copy()
+        Uf = textbook(Pf, gamma, alpha=geo[i][0], psi4=geo[i][1])[0]
+        np.testing.assert_allclose(Ua[:5, 0, 0, i], Uf[:5], rtol=1e-13,
+                                   atol=1e-13 * np.abs(Uf[:5]).max())
+        assert np.array_equal(Ua[5:, 0, 0, i], U[5:, 0, 0, i])
+        # the rebuilt energy carries the raised pressure: it exceeds the input's
+        assert Ua[1, 0, 0, i] > U[1, 0, 0, i]
