@@ -55,40 +55,55 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# Algorithmic HBM bytes per cell and Runge-Kutta substep of a fully fused
+# substep: read P^s and U^n, write U^(s+1) and P^(s+1), 36 values; the stage
+# state U^s is recomputable from P^s and the metric is evaluated in closed
+# form, so neither is counted.  FP64: 36 x 8 = 288 B; mixed precision with the
+# primitives in FP32: 2 x 36 + 2 x 72 = 216 B.
+SUBSTEP_BYTES = {"fp64": 288.0, "mixed": 216.0}
+
+
+def design_bytes_per_cell(nsub: int, precision: str = "fp64") -> float:
+    """Bytes per cell and substep that this design has to move at the least,
+    averaged over the substeps of a step: the primitives read and written
+    once (FP64 or FP32), U^n read, the stage state U^s read by every substep
+    but the first (which reads U^n as its stage state) and U^(s+1) written
+    (the intermediate stage states in FP32 in mixed precision, the step's
+    result in FP64)."""
+    wp = 72.0 if precision == "fp64" else 36.0
+    ws = 72.0 if precision == "fp64" else 36.0
+    inner = (nsub - 1) / nsub
+    return 2 * wp + 72.0 + ws * inner + (ws * inner + 72.0 / nsub)
+
+
 def algorithmic_bytes(kernel: str, n, nsub: int, precision: str = "fp64") -> float:
     """Algorithmic HBM bytes of ONE launch of a kernel class on an n[0] x n[1] x n[2]
     grid (3D), each value that has to cross HBM counted once:
-      flux_x / flux_y : the primitives once + one 9-value flux record per face;
-      update          : the x and y face records (one unique record per cell and
-                        axis), the primitives once (the z faces are computed in
-                        the kernel) and the new primitives, U^n, the stage state
-                        U^s read (all substeps but the first, which reads U^n)
-                        and U^(s+1) written -- averaged over the substeps of a
-                        step;
-      bc              : read and write the 2-cell ghost slabs of the three axes.
-    In mixed precision the primitive caches, face records and the intermediate
-    stage state are FP32; U^n and the step's result U^(n+1) stay FP64."""
+      update          : the fused substep kernel (faces of all axes, flux
+                        differences, sources, Runge-Kutta combination,
+                        recovery): SUBSTEP_BYTES per cell;
+      flux_x/y/z      : (1D/2D grids and scheme variants) the primitives once +
+                        one 9-value flux record per face;
+      bc              : read and write the 2-cell ghost slabs of the three axes."""
     N = n[0] * n[1] * n[2]
-    wu = 8.0 * 9                     # bytes of one 9-variable FP64 record
-    w = wu if precision == "fp64" else 4.0 * 9
+    w = 72.0 if precision == "fp64" else 36.0
     if kernel in ("flux_x", "flux_y", "flux_z"):
         d = "xyz".index(kernel[-1])
         nf = N // n[d] * (n[d] + 1)
         return w * N + w * nf
     if kernel == "update":
-        fx = (n[0] + 1) / n[0]
-        fy = (n[1] + 1) / n[1]
-        inner = (nsub - 1) / nsub            # substeps that read / write the stage state
-        return N * (w * (fx + fy + 1 + 1) + wu + w * inner + (w * inner + wu / nsub))
+        return SUBSTEP_BYTES[precision] * N
     if kernel == "bc":
         g = 2
         return w * 2 * g * (n[1] * n[2] + n[0] * n[2] + n[0] * n[1]) * 2
     return float("nan")
 
 
-def load_traffic(kernel: str, workload: str, precision: str = "fp64"):
-    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
-    (scaled by a copy-kernel calibration), if taken on the current sources."""
+def load_counters(kernel: str, workload: str, precision: str = "fp64"):
+    """The counter entry of a kernel class (profiles/traffic.json: HBM bytes
+    per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel
+    calibration, and VALU wave-instructions per launch), if taken on the
+    current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -98,7 +113,7 @@ def load_traffic(kernel: str, workload: str, precision: str = "fp64"):
     e = t.get(workload, {}).get(precision, {}).get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
-    return e.get("bytes_per_launch")
+    return e
 
 
 def _read_csv(path):
@@ -109,7 +124,7 @@ def _read_csv(path):
 
 def _short(name: str) -> str:
     """Kernel class of a demangled kernel name."""
-    for key, short in (("k_flux_x", "flux_x"), ("k_flux_march<1", "flux_y"),
+    for key, short in (("k_substep", "update"), ("k_flux_x", "flux_x"), ("k_flux_march<1", "flux_y"),
                        ("k_flux_march<2", "flux_z"), ("k_update", "update"), ("k_ghosts", "bc"),
                        ("k_cons", "cons"),
                        ("k_prim", "prim"), ("k_rhs", "rhs"), ("copyBuffer", "copy_probe")):
@@ -118,15 +133,25 @@ def _short(name: str) -> str:
     return name[:40]
 
 
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
+                 "SQ_INSTS_VALU_TRANS_F64")
+
+
 def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: str, precision: str,
-                out_json: str):
+                out_json: str, valu_csv: str = None):
     """Per-launch HBM bytes of each kernel class from two rocprofv3 --pmc runs
     (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each scaled by what the same
-    counter reads for the copy probe of known size (probe_bytes read and written)."""
+    counter reads for the copy probe of known size (probe_bytes read and
+    written); with a third counter file, the VALU wave-instructions per launch
+    (all, and the FP64 arithmetic ones)."""
     per = {}
-    for path, ctr in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+    files = [(fetch_csv, ("FETCH_SIZE",)), (write_csv, ("WRITE_SIZE",))]
+    if valu_csv:
+        files.append((valu_csv, VALU_COUNTERS))
+    for path, ctrs in files:
         for r in _read_csv(path):
-            if r.get("Counter_Name") != ctr:
+            ctr = r.get("Counter_Name")
+            if ctr not in ctrs:
                 continue
             k = _short(r["Kernel_Name"])
             per.setdefault(k, {}).setdefault(ctr, []).append(float(r["Counter_Value"]))
@@ -162,6 +187,11 @@ def pmc_summary(fetch_csv: str, write_csv: str, probe_bytes: float, workload: st
         res[workload][precision][k] = {"fetch_KiB": fk, "write_KiB": wk,
                             "bytes_per_launch": 1024.0 * (fk * ff + wk * fw),
                             "dispatches": len(c["FETCH_SIZE"]), "source_hash": kernel_source_hash()}
+        if all(v in c for v in VALU_COUNTERS):
+            mean = {v: sum(c[v]) / len(c[v]) for v in VALU_COUNTERS}
+            res[workload][precision][k]["valu_insts_per_launch"] = mean["SQ_INSTS_VALU"]
+            res[workload][precision][k]["fp64_valu_insts_per_launch"] = sum(
+                mean[v] for v in VALU_COUNTERS[1:])
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)
     return res
@@ -176,7 +206,8 @@ def accuracy(grmhd, w, P0, dev, nsteps):
     variables: sum |U_m - U_d| over the group's components divided by the
     largest component L1 norm of the group in U_d.  "physical" is the maximum
     over D, tau, S and the densitised field; Phi (the cleaning scalar, whose
-    size is set by the discretisation error of div B) is given apart."""
+    size is set by the discretisation error of div B) is given apart; "all"
+    is the maximum over every group."""
     import torch
     Us = {}
     for prec in ("fp64", "mixed"):
@@ -194,6 +225,7 @@ def accuracy(grmhd, w, P0, dev, nsteps):
         den = max(float(b[i].abs().sum()) for i in g)
         out[name] = num / den if den > 0 else num
     out["physical"] = max(out[k] for k in ("D", "tau", "S", "B"))
+    out["all"] = max(out["physical"], out["Phi"])
     return out
 
 
@@ -311,27 +343,79 @@ def batch_throughput(grmhd, e, dev):
     return out
 
 
-def cpu_baseline(w, pb_kwargs):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, small):
+    """The plain CPU oracle (test infrastructure, never on the GPU path) timed
+    on the host: one full RK step of the benchmark workload on all the cores
+    OpenMP is given, and one full RK step of the same workload recipe at a
+    smaller size on one thread (the per-cell rate does not depend on the
+    size)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    oracle.set_threads(threads)
-    pb = oracle.Problem(**pb_kwargs)
-    U0 = oracle.prim2con(pb, w.P)
-    t0 = time.perf_counter()
-    oracle.step(pb, U0, w.P, w.dt, 1)
-    dt = time.perf_counter() - t0
-    subs = w.rk_order * w.ncell
-    return {"value": subs / dt, "unit": "zone-updates/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
+    out = {}
+    for wl, nth in ((w, threads), (small, 1)):
+        oracle.set_threads(nth)
+        pb = oracle.Problem(**wl.problem_kwargs())
+        U0 = oracle.prim2con(pb, wl.P)
+        t0 = time.perf_counter()
+        oracle.step(pb, U0, wl.P, wl.dt, 1)
+        dt = time.perf_counter() - t0
+        out[nth == 1 and wl is small] = (wl.rk_order * wl.ncell / dt, oracle.get_threads(), dt, wl)
+    v, cores, dt, wl = out[False]
+    v1, _, dt1, wl1 = out[True]
+    return {"value": v, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
             "sample": "one full SSP-RK%d step (%d substeps) of the %s workload, %d cells, %.1f s wall"
-                      % (w.rk_order, w.rk_order, w.name, w.ncell, dt)}
+                      % (wl.rk_order, wl.rk_order, wl.name, wl.ncell, dt),
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": v1, "cores": 1,
+                           "sample": "one full SSP-RK%d step of the same workload at %d^3 (%d cells), %.1f s wall"
+                                     % (wl1.rk_order, wl1.n[0], wl1.ncell, dt1)}}
+
+
+def batch_accuracy(grmhd, e, dev, nsteps: int = None):
+    """Relative L1 distance of the mixed-precision ensemble from the FP64 one
+    after every problem ran to its end, per problem (the largest over all 9
+    conserved variables, vector components normalised as in accuracy()):
+    median, 90th percentile and maximum over the problems."""
+    import numpy as np
+    import torch
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = grmhd.batch_for(e, device=dev, precision=prec)
+        U = s.cons(s.pack(e.P))
+        s.evolve(U)
+        torch.cuda.synchronize()
+        res[prec] = [u.double().cpu().numpy() for u in s.unpack(U)]
+        del s, U
+    errs = []
+    for a, b in zip(res["mixed"], res["fp64"]):
+        e_b = 0.0
+        for _, g in GROUPS:
+            num = sum(np.abs(a[i] - b[i]).sum() for i in g)
+            den = max(np.abs(b[i]).sum() for i in g)
+            e_b = max(e_b, num / den if den > 0 else num)
+        errs.append(e_b)
+    errs = np.array(errs)
+    return {"median": float(np.median(errs)), "p90": float(np.percentile(errs, 90)), "max": float(errs.max()),
+            "problems_above_1e-5": int((errs > 1e-5).sum())}
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--repeats", type=int, default=5, help="timed runs of --steps steps; the median is reported")
     ap.add_argument("--n", type=int, default=192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
@@ -345,18 +429,21 @@ def main(argv=None) -> int:
                          "the precision the counter files were taken on")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files "
-                         "(taken with --copy-probe) and exit")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
+                    help="write profiles/traffic.json from rocprofv3 --pmc counter files: FETCH_SIZE, "
+                         "WRITE_SIZE (taken with --copy-probe) and optionally the VALU counters; then exit")
     ap.add_argument("--probe-mib", type=float, default=1024.0)
     args = ap.parse_args(argv)
 
     if args.pmc_summary:
         if args.precision == "both":
             raise SystemExit("--pmc-summary needs --precision fp64 or mixed")
+        if len(args.pmc_summary) not in (2, 3):
+            raise SystemExit("--pmc-summary takes FETCH_CSV WRITE_CSV [VALU_CSV]")
         res = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.probe_mib * 2 ** 20,
                           "curved_blob_%d^3" % args.n, args.precision,
-                          os.path.join(ROOT, "profiles", "traffic.json"))
+                          os.path.join(ROOT, "profiles", "traffic.json"),
+                          args.pmc_summary[2] if len(args.pmc_summary) == 3 else None)
         print(json.dumps(res, indent=1))
         return 0
 
@@ -383,44 +470,71 @@ def main(argv=None) -> int:
     wl_name = "curved_blob_%d^3" % args.n
     nsub = w.rk_order
     P0 = torch.from_numpy(w.P).to(dev)
+    N = w.ncell
 
-    def timed_run(precision, stored=None, **over):
+    def timed_run(precision, stored=None, repeats=None, **over):
+        repeats = args.repeats if repeats is None else repeats
         s = grmhd.solver_for(w, device=dev, timing=not args.no_timing, precision=precision, **over)
         if stored is not None:
             s.set_metric(*stored)
-        U = s.cons(P0)
-        for _ in range(args.warmup):
-            s.step(U, w.dt)
-        torch.cuda.synchronize()
-        s.timing(reset=True)
-        s.status(reset=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            s.step(U, w.dt)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        r = {"value": w.ncell * nsub * args.steps / elapsed,
+        runs = []
+        for _ in range(max(1, repeats)):
+            U = s.cons(P0)
+            for _ in range(args.warmup):
+                s.step(U, w.dt)
+            torch.cuda.synchronize()
+            s.timing(reset=True)
+            s.status(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                s.step(U, w.dt)
+            torch.cuda.synchronize()
+            elapsed = time.perf_counter() - t0
+            runs.append((elapsed, s.timing(), s.status(), bool(torch.isfinite(U).all().item())))
+            del U
+        runs.sort(key=lambda r: r[0])
+        elapsed, timing, status, finite = runs[len(runs) // 2]
+        r = {"value": N * nsub * args.steps / elapsed,
              "ms_per_step": 1e3 * elapsed / args.steps,
-             "recovery": s.status(), "finite": bool(torch.isfinite(U).all().item()),
+             "ms_per_step_runs": [round(1e3 * x[0] / args.steps, 4) for x in runs],
+             "recovery": status, "finite": all(x[3] for x in runs),
              "kernels": {}, "roofline": None}
         if not args.no_timing:
             kernels = r["kernels"]
-            for k, (ms, cnt) in s.timing().items():
+            for k, (ms, cnt) in timing.items():
                 if cnt:
                     avg = ms / cnt
                     bk = algorithmic_bytes(k, w.n, nsub, precision)
                     kernels[k] = {"launches": cnt, "total_ms": round(ms, 4), "avg_ms": round(avg, 5),
                                   "alg_GBps": round(bk / (avg * 1e-3) / 1e9, 1) if bk == bk else None}
             dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+            avg_s = kernels[dom]["avg_ms"] * 1e-3
             bk = algorithmic_bytes(dom, w.n, nsub, precision)
-            achieved = bk / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
-            r["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(achieved / HBM_PEAK_GBS, 4),
-                             "traffic": load_traffic(dom, wl_name, precision),
-                             "alg_bytes_per_launch": bk}
-        del U, s
+            achieved = bk / avg_s / 1e9
+            sub_s = r["ms_per_step"] * 1e-3 / nsub
+            cnt = load_counters(dom, wl_name, precision)
+            rl = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                  "traffic": cnt["bytes_per_launch"] if cnt else None,
+                  "alg_bytes_per_cell": SUBSTEP_BYTES[precision] if dom == "update" else bk / N,
+                  "alg_bytes_per_launch": bk,
+                  "whole_substep_frac": round(SUBSTEP_BYTES[precision] * N / sub_s / 1e9 / HBM_PEAK_GBS, 4),
+                  "design_bytes_per_cell": round(design_bytes_per_cell(nsub, precision), 1),
+                  "design_frac": round(design_bytes_per_cell(nsub, precision) * N / avg_s / 1e9 / HBM_PEAK_GBS,
+                                       4)}
+            if cnt:
+                rl["traffic_bytes_per_cell"] = round(cnt["bytes_per_launch"] / N, 1)
+                rl["traffic_frac"] = round(cnt["bytes_per_launch"] / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+                if "valu_insts_per_launch" in cnt:
+                    # issue time of the counted wave-instructions (4 cycles each
+                    # on a 16-lane SIMD) on all 1024 SIMDs at 2.4 GHz
+                    issue = lambda x: x * 4.0 / (1024 * 2.4e9)
+                    rl["valu_insts_per_cell"] = round(cnt["valu_insts_per_launch"] * 64 / N, 1)
+                    rl["valu_busy"] = round(issue(cnt["valu_insts_per_launch"]) / avg_s, 4)
+                    rl["fp64_valu_util"] = round(issue(cnt["fp64_valu_insts_per_launch"]) / avg_s, 4)
+            r["roofline"] = rl
+        del s
         return r
 
     fp64 = timed_run("fp64") if args.precision != "mixed" else None
@@ -435,10 +549,13 @@ def main(argv=None) -> int:
     if fp64 and mixed:
         mixed["speedup_vs_fp64"] = round(mixed["value"] / fp64["value"], 3)
         if args.accuracy_steps > 0:
+            # against the FP64 GPU path, which the parity tests hold to the
+            # FP64 oracle at 1e-10 (the oracle takes minutes for this run)
             acc = accuracy(grmhd, w, P0, dev, args.accuracy_steps)
-            mixed["rel_l1_vs_fp64"] = acc["physical"]
+            mixed["rel_l1_vs_fp64"] = acc["all"]
             mixed["rel_l1_vs_fp64_groups"] = acc
             mixed["rel_l1_steps"] = args.accuracy_steps
+            mixed["meets_1e-5"] = {"all_variables": acc["all"] <= 1e-5, "without_Phi": acc["physical"] <= 1e-5}
     main = fp64 or mixed
 
     out = {
@@ -457,9 +574,11 @@ def main(argv=None) -> int:
         "config": {"workload": wl_name + " static curved spacetime (isotropic Schwarzschild, "
                    "r_s = sqrt(r^2+1)), [-20,20]^3, Gamma=2, SSP-RK3, "
                    + ("FP64" if fp64 else "mixed precision"),
-                   "cells": w.ncell, "substeps_per_step": nsub, "dt": w.dt},
+                   "cells": N, "substeps_per_step": nsub, "dt": w.dt,
+                   "timing": "median of %d runs of %d steps" % (args.repeats, args.steps)},
         "roofline": main["roofline"],
         "kernels": main["kernels"],
+        "ms_per_step_runs": main["ms_per_step_runs"],
         "recovery": main["recovery"],
         "finite": main["finite"],
         "mixed": mixed if fp64 else None,
@@ -478,17 +597,19 @@ def main(argv=None) -> int:
         for name, over in (("recovery_1d", {"recovery": "1d"}), ("ppm", {"reconstruction": "ppm"}),
                            ("fluxct", {"divergence": "fluxct"}),
                            ("stored_metric", {"metric": grmhd.STORED, "stored": stored})):
-            v = timed_run("fp64", **over)
+            v = timed_run("fp64", repeats=1, **over)
             out["variants"][name] = {
                 "value": v["value"], "ms_per_step": v["ms_per_step"], "recovery": v["recovery"],
                 "finite": v["finite"], "kernels_avg_ms": {k: x["avg_ms"] for k, x in v["kernels"].items()},
                 "vs_default": round(v["value"] / fp64["value"], 3)}
     if not args.no_batch and fp64:
         # 256 magnetised 1D Riemann problems of 200..4000 cells, each to t = 0.4
-        out["batch"] = batch_throughput(grmhd, workloads.config5(), dev)
+        e5 = workloads.config5()
+        out["batch"] = batch_throughput(grmhd, e5, dev)
+        out["batch"]["mixed"]["rel_l1_vs_fp64"] = batch_accuracy(grmhd, e5, dev)
     finite = all(r["finite"] for r in (fp64, mixed) if r)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, w.problem_kwargs())
+        out["cpu_baseline"] = cpu_baseline(w, workloads.config3(n=96, nsteps=1))
     print(json.dumps(out), flush=True)
     return 0 if finite else 1
 

@@ -415,9 +415,8 @@ int update_stage(grmhd_ctx* c, bool zmarch, int src, int dst, const double* U, c
 {
     return timed(c, GRMHD_K_UPDATE, [&] {
         if (zmarch)
-            return grmhd::launch_update_zmarch(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
-                                               (const T*)cache<T>(c, src), cache<T>(c, dst), U, Us, Uout,
-                                               c->d, dt, a, b, c->cnt, (unsigned char*)nullptr, c->stream);
+            return grmhd::launch_substep(c->kind, (const T*)cache<T>(c, src), cache<T>(c, dst), U, Us, Uout, c->d,
+                                         dt, a, b, c->cnt, (unsigned char*)nullptr, c->stream);
         return grmhd::launch_update(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
                                     (const T*)faces<T>(c, 2), (const T*)cache<T>(c, src), cache<T>(c, dst), U,
                                     Us, Uout, c->d, dt, a, b, c->cnt, (unsigned char*)nullptr, c->stream);
@@ -441,7 +440,7 @@ int step_t(grmhd_ctx* c, double* U, double dt)
     for (int s = 0; s < ns; ++s) {
         const int src = zmarch ? s : 0;
         const int dst = zmarch ? (s == ns - 1 ? 0 : s + 1) : 0;
-        int rc = fluxes<T>(c, src, zmarch ? 2 : 3);
+        int rc = fluxes<T>(c, src, zmarch ? 0 : 3);
         if (rc)
             return rc;
         if (s == 0)
@@ -494,7 +493,7 @@ int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, con
         return rc;
     for (int s = 0; s < ns; ++s) {
         const double* Ps = c->Ac[s];
-        for (int dir = 0; dir < (zmarch ? 2 : 3); ++dir) {
+        for (int dir = 0; dir < (zmarch ? 0 : 3); ++dir) {
             if (!c->d.act[dir])
                 continue;
             rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
@@ -507,9 +506,8 @@ int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, con
         unsigned char* fl = c->Aflags + (size_t)s * c->L.N;
         rc = timed(c, GRMHD_K_UPDATE, [&] {
             if (zmarch)
-                return grmhd::launch_update_zmarch(c->kind, (const double*)c->F[0], (const double*)c->F[1], Ps,
-                                                   c->Ac[s + 1], U, Us, c->Aus, c->d, dt, A[s], B[s], c->cnt,
-                                                   fl, c->stream);
+                return grmhd::launch_substep(c->kind, Ps, c->Ac[s + 1], U, Us, c->Aus, c->d, dt, A[s], B[s], c->cnt,
+                                             fl, c->stream);
             return grmhd::launch_update(c->kind, (const double*)c->F[0], (const double*)c->F[1],
                                         (const double*)c->F[2], Ps, c->Ac[s + 1], U, Us, c->Aus, c->d, dt,
                                         A[s], B[s], c->cnt, fl, c->stream);
@@ -609,7 +607,7 @@ int step_record(grmhd_ctx* c, double* U, double dt, int slot)
     for (int s = 0; s < ns; ++s) {
         const double* Ps = tape_cache(c, slot, s);
         double* Pn = tape_cache(c, slot, s + 1);
-        for (int dir = 0; dir < (zmarch ? 2 : 3); ++dir) {
+        for (int dir = 0; dir < (zmarch ? 0 : 3); ++dir) {
             if (!c->d.act[dir])
                 continue;
             rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
@@ -623,8 +621,8 @@ int step_record(grmhd_ctx* c, double* U, double dt, int slot)
         unsigned char* f = fl + (size_t)s * c->L.N;
         rc = timed(c, GRMHD_K_UPDATE, [&] {
             if (zmarch)
-                return grmhd::launch_update_zmarch(c->kind, (const double*)c->F[0], (const double*)c->F[1], Ps,
-                                                   Pn, U, Uin, Uo, c->d, dt, A[s], B[s], c->cnt, f, c->stream);
+                return grmhd::launch_substep(c->kind, Ps, Pn, U, Uin, Uo, c->d, dt, A[s], B[s], c->cnt, f,
+                                             c->stream);
             return grmhd::launch_update(c->kind, (const double*)c->F[0], (const double*)c->F[1],
                                         (const double*)c->F[2], Ps, Pn, U, Uin, Uo, c->d, dt, A[s], B[s],
                                         c->cnt, f, c->stream);
@@ -665,12 +663,15 @@ size_t grmhd_workspace_bytes(const grmhd_grid* grid, const grmhd_opts* opts)
         .total;
 }
 
-int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
-               const grmhd_eos* eos, const grmhd_opts* opts)
+}  // extern "C"
+
+namespace {
+
+// Validate the arguments of grmhd_init and fill the (host-side) context c,
+// whose workspace is opts->workspace.
+int init_ctx(grmhd_ctx* c, const grmhd_metric* metric, const grmhd_grid* grid, const grmhd_eos* eos,
+             const grmhd_opts* opts)
 {
-    if (!out || !metric || !grid || !eos || !opts)
-        return GRMHD_ERR_ARG;
-    *out = nullptr;
     if (!grid_ok(grid))
         return GRMHD_ERR_ARG;
     if (metric->kind != GRMHD_METRIC_FLAT && metric->kind != GRMHD_METRIC_ISO_SCHW &&
@@ -709,9 +710,6 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
     if (((uintptr_t)opts->workspace) % 256 != 0)
         return GRMHD_ERR_WORKSPACE;
 
-    grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
-    if (!c)
-        return GRMHD_ERR_ARG;
     c->L = L;
     c->kind = metric->kind == GRMHD_METRIC_FLAT ? grmhd::FLAT
               : (metric->kind == GRMHD_METRIC_ISO_SCHW ? grmhd::ISO : grmhd::STORED);
@@ -784,6 +782,27 @@ int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* gr
         for (int a = 0; a < 3; ++a)
             c->GMU[a] = L.nf[a] ? (double*)(c->ws + L.off_gmu[a]) : nullptr;
         c->tape_dt.assign((size_t)L.tape, std::nan(""));
+    }
+    return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grmhd_init(grmhd_ctx** out, const grmhd_metric* metric, const grmhd_grid* grid,
+               const grmhd_eos* eos, const grmhd_opts* opts)
+{
+    if (!out || !metric || !grid || !eos || !opts)
+        return GRMHD_ERR_ARG;
+    *out = nullptr;
+    grmhd_ctx* c = new (std::nothrow) grmhd_ctx();
+    if (!c)
+        return GRMHD_ERR_ARG;
+    const int rc = init_ctx(c, metric, grid, eos, opts);
+    if (rc) {
+        delete c;
+        return rc;
     }
     *out = c;
     return GRMHD_OK;

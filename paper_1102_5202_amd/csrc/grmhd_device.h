@@ -306,13 +306,13 @@ __device__ __forceinline__ bool finite(double x)
 
 // ---------------------------------------------------------------------------
 // Face solver: from the reconstructed left/right primitives at a face along D
-// (positions x, y, z), the 9 components Fo of the numerical flux: exact
-// (Bd^n, Phi) cleaning pair, then HLLE on the rest.
-template <int D, int KIND, typename T>
-__device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, double z, long long f,
-                                          const Dev& d, T* Fo)
+// and the metric there, the 9 components Fo of the numerical flux: exact
+// (Bd^n, Phi) cleaning pair, then HLLE on the rest.  The metric is
+// conformally flat, so a face of axis D is also a face of axis 0 with the
+// vector components cycled (D, D+1, D+2) -> (0, 1, 2).
+template <int D, typename T>
+__device__ __forceinline__ void face_solve(T* qL, T* qR, const GeoT<T>& g, const Dev& d, T* Fo)
 {
-    const GeoT<T> g = geo_cast<T>(face_geo<D, KIND>(d, x, y, z, f));
     const T half = T(0.5), ch = (T)d.c_h, ich = (T)d.ic_h;
 
     // cleaning pair: exact solution of the linear (Bd^n, Phi) Riemann problem
@@ -361,6 +361,14 @@ __device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, doub
     // fluxes are replaced once the edge values are known)
     Fo[5 + D] = d.ct ? T(0) : phs;
     Fo[8] = d.ct ? T(0) : (T)d.c_h2 * Bs;
+}
+
+// The face solver at face f of axis D (position x, y, z) with the metric there.
+template <int D, int KIND, typename T>
+__device__ __forceinline__ void face_flux(T* qL, T* qR, double x, double y, double z, long long f,
+                                          const Dev& d, T* Fo)
+{
+    face_solve<D>(qL, qR, geo_cast<T>(face_geo<D, KIND>(d, x, y, z, f)), d, Fo);
 }
 
 

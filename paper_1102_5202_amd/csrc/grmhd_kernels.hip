@@ -31,6 +31,9 @@ namespace grmhd {
 static constexpr int BLOCK = 256;
 static constexpr int MARCH_SEG = 8;   // faces (cells) per thread in the z marches
 static constexpr unsigned MIN_BLOCKS = 1024;   // 4 workgroups per CU: enough to fill the GPU
+// the fused substep kernel: tile of TX x TY columns, SUB_SEG planes per workgroup
+static constexpr int SUB_TX = 32, SUB_TY = 8, SUB_SEG = 8;
+static constexpr long long SUB_MIN_BLOCKS = 1024;
 
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -470,33 +473,42 @@ __device__ __forceinline__ void store_prim(const Dev& d, T* __restrict__ P, long
     }
 }
 
-// Runge-Kutta combination U^(s+1) = U^s + a (U^n - U^s) + b dt R and recovery
-// of the primitives for one cell (all in double); q are the cell's current
-// primitives (the Newton guess).  Writes U^(s+1) and the new primitives (with
-// their ghost images).  TS and TO are the types of the stage states read and
-// written: double, or float for the intermediate stages of the mixed path.
-// fout (may be null) receives the cell's recovery flags.
-template <bool NT, typename T, typename TS, typename TO>
-__device__ __forceinline__ int stage_cell(const Dev& d, const Geo& g, const double* R, const T* q,
-                                          const double* Un, const TS* Us, TO* Uout, long long c,
-                                          T* Pout, long long pc, int i, int j, int k, double dt,
-                                          double a, double b, unsigned char* fout, int& iters)
+// The stage inputs of cell c: U^n and U^s.  U^n, U^s and U^(s+1) are touched
+// once per cell and substep: on large grids (NT) nontemporal accesses keep them
+// from displacing the face records and primitives that neighbouring
+// workgroups read again.
+template <bool NT, typename TS>
+__device__ __forceinline__ void stage_load(const Dev& d, const double* Un, const TS* Us, long long c, double* un,
+                                           double* us)
 {
-    // U^n, U^s and U^(s+1) are touched once per cell and substep: on large
-    // grids (NT) nontemporal accesses keep them from displacing the face
-    // records and primitives that neighbouring workgroups read again
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        if constexpr (NT) {
+            un[v] = __builtin_nontemporal_load(&Un[v * d.N + c]);
+            us[v] = (double)__builtin_nontemporal_load(&Us[v * d.N + c]);
+        } else {
+            un[v] = Un[v * d.N + c];
+            us[v] = (double)Us[v * d.N + c];
+        }
+    }
+}
+
+// Runge-Kutta combination U^(s+1) = U^s + a (U^n - U^s) + b dt R and recovery
+// of the primitives for one cell (all in double) from its stage inputs un, us;
+// q are the cell's current primitives (the Newton guess).  Writes U^(s+1) and
+// the new primitives (with their ghost images).  TO is the type of the stage
+// state written: double, or float for the intermediate stages of the mixed
+// path.  fout (may be null) receives the cell's recovery flags.
+template <bool NT, typename T, typename TO>
+__device__ __forceinline__ int stage_finish(const Dev& d, const Geo& g, const double* R, const T* q,
+                                            const double* un, const double* us, TO* Uout, long long c, T* Pout,
+                                            long long pc, int i, int j, int k, double dt, double a, double b,
+                                            unsigned char* fout, int& iters)
+{
     double u[9], p[9], qg[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
-        double un, us;
-        if constexpr (NT) {
-            un = __builtin_nontemporal_load(&Un[v * d.N + c]);
-            us = (double)__builtin_nontemporal_load(&Us[v * d.N + c]);
-        } else {
-            un = Un[v * d.N + c];
-            us = (double)Us[v * d.N + c];
-        }
-        u[v] = us + a * (un - us) + b * (dt * R[v]);
+        u[v] = us[v] + a * (un[v] - us[v]) + b * (dt * R[v]);
         qg[v] = (double)q[v];
     }
     int flags = recover_cell(d, g, u, qg, p, iters);
@@ -511,6 +523,18 @@ __device__ __forceinline__ int stage_cell(const Dev& d, const Geo& g, const doub
     if (fout)
         fout[c] = (unsigned char)flags;
     return flags;
+}
+
+// stage_load then stage_finish.  TS is the type of the stage state read.
+template <bool NT, typename T, typename TS, typename TO>
+__device__ __forceinline__ int stage_cell(const Dev& d, const Geo& g, const double* R, const T* q,
+                                          const double* Un, const TS* Us, TO* Uout, long long c,
+                                          T* Pout, long long pc, int i, int j, int k, double dt,
+                                          double a, double b, unsigned char* fout, int& iters)
+{
+    double un[9], us[9];
+    stage_load<NT>(d, Un, Us, c, un, us);
+    return stage_finish<NT>(d, g, R, q, un, us, Uout, c, Pout, pc, i, j, k, dt, a, b, fout, iters);
 }
 
 // 1D/2D update: flux differences, sources, RK combination and recovery of the
@@ -667,6 +691,278 @@ __global__ __launch_bounds__(BLOCK) void k_update_zmarch(
             int iters = 0;
             const long long pc = col + (long long)(k + d.g[2]) * st;
             int flags = stage_cell<NT>(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
+            tally(flags, iters, nfail, natm, npf, nfb, itmax);
+        }
+    }
+    count_sums(cnt, nfail, natm, npf, nfb, itmax);
+}
+
+// ---------------------------------------------------------------------------
+// The whole substep of a 3D grid in one kernel (MC reconstruction, cleaning).
+// A workgroup owns a TX x TY tile of z columns and a segment of SEG planes and
+// walks the planes upwards.  For plane k it
+//   (1) stages the primitives of the tile and of a 2-cell halo in x and y (the
+//       cross-shaped stencil, no corners) in LDS: each thread writes its own
+//       cell from its z window, the halo cells come from the cache in HBM;
+//   (2) solves the tile's x faces (TX + 1 per row) and y faces (TY + 1 per
+//       column) from LDS into LDS, one face of each axis per thread plus the
+//       tile's last row and column of faces;
+//   (3) per cell, as k_update_zmarch: the z face above the cell from the
+//       thread's register window (one new cell and one slope per plane), the
+//       flux differences of the three axes, the sources, the Runge-Kutta
+//       combination and the recovery, the new primitives (with their ghost
+//       images) going to another cache.
+// The x and y face fluxes never leave the chip, and every primitive of the
+// cache is read from HBM once per substep, plus the halo rows and columns
+// shared with the neighbouring tiles.
+template <int TX, int TY>
+struct Tile {
+    static constexpr int NT = TX * TY;          // threads: one column each
+    static constexpr int W = TX + 4;            // LDS row of a staged plane
+    static constexpr int PLANE = (TY + 4) * W;  // staged positions per variable
+    static constexpr int NFX = (TX + 1) * TY;   // x faces of the tile
+    static constexpr int NFY = TX * (TY + 1);   // y faces of the tile
+    static constexpr int NH = 4 * (TX + TY);    // halo positions
+    static_assert(NH <= NT - 64, "one halo position per thread, the last wave free");
+    static_assert(TX + TY <= 64 && NT % 64 == 0, "the tile's last faces in one wave");
+};
+
+// An x (dir 0) or y (dir 1) face of the tile, dir per lane, solved as a face
+// of axis 0 with the vector components cycled (the metric is conformally
+// flat): MC states from the four staged cells at sP + base + m * stride
+// (m = 0..3, the face between the 2nd and the 3rd), the face solver, the flux
+// into sF.
+template <int KIND, int PLANE, typename T>
+__device__ __forceinline__ void tile_face(const T* sP, int dir, int base, int stride, double fx, double fy,
+                                          double fz, long long fglob, const Dev& d, T* sF, int nslot, int slot)
+{
+    const T half = T(0.5);
+    int vo[9];   // variable v of the cycled frame is variable vo[v] of the grid
+    vo[0] = 0;
+    vo[1] = 1;
+    vo[8] = 8;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int c = dir == 0 ? m : (m == 2 ? 0 : m + 1);
+        vo[2 + m] = 2 + c;
+        vo[5 + m] = 5 + c;
+    }
+    T qL[9], qR[9], Fo[9];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        const T* p = sP + vo[v] * PLANE + base;
+        const T q0 = p[0], q1 = p[stride], q2 = p[2 * stride], q3 = p[3 * stride];
+        qL[v] = q1 + half * mc_slope(q0, q1, q2);
+        qR[v] = q2 - half * mc_slope(q1, q2, q3);
+    }
+    Geo g;
+    if (KIND == STORED) {
+        const double* mf = dir == 0 ? d.mf[0] : d.mf[1];
+        const long long nf = dir == 0 ? d.nf[0] : d.nf[1];
+        g = geo_from_ap(mf[fglob], mf[nf + fglob]);
+    } else {
+        g = geo_at<KIND>(d, fx, fy, fz);
+    }
+    face_solve<0>(qL, qR, geo_cast<T>(g), d, Fo);
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        sF[vo[v] * nslot + slot] = Fo[v];
+}
+
+template <int KIND, int TX, int TY, int SEG, bool NT, typename T, typename TS, typename TO>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_substep(const T* __restrict__ Pc, T* __restrict__ Pn,
+                                                    const double* Un, const TS* Us, TO* Uout, Dev d, double dt,
+                                                    double a, double b, unsigned long long* __restrict__ cnt,
+                                                    unsigned char* __restrict__ fout, int ntx, int ntiles)
+{
+    using G = Tile<TX, TY>;
+    __shared__ T sP[9 * G::PLANE];
+    __shared__ T sFx[9 * G::NFX];
+    __shared__ T sFy[9 * G::NFY];
+
+    const int t = threadIdx.x;
+    const int tx = t % TX, ty = t / TX;
+    const unsigned nbk = gridDim.x;
+    const unsigned item = (nbk % 8 == 0) ? (blockIdx.x % 8) * (nbk / 8) + blockIdx.x / 8 : blockIdx.x;
+    const int tile = (int)(item % (unsigned)ntiles);
+    const int seg = (int)(item / (unsigned)ntiles);
+    const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+    const int i = i0 + tx, j = j0 + ty;
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    const bool act = i < nx && j < ny;
+    const bool ax = d.act[0], ay = d.act[1];   // an axis of one cell has no faces
+    const int k0 = seg * SEG;
+    const int k1 = min(k0 + SEG, nz);
+    const long long st = (long long)d.px * d.py;
+    // cache address of (i, j, k = 0); cell k adds k * st
+    const long long col = (long long)(j + d.g[1]) * d.px + i + d.g[0] + (long long)d.g[2] * st;
+    const double x = d.lo[0] + (i + 0.5) * d.dx[0];
+    const double y = d.lo[1] + (j + 0.5) * d.dx[1];
+    const T half = T(0.5);
+    int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
+
+    // The cell this thread stages from HBM each plane: a halo position
+    // (threads t < NH), or its own position when it is a ghost cell that a
+    // face near the domain's edge reads (ragged tiles); -1: none.
+    int hslot = -1;
+    long long hoff = 0;
+    {
+        int hx = tx, hy = ty;
+        bool need = false;
+        if (t < G::NH) {
+            if (t < 2 * TX) {
+                hx = t % TX;
+                hy = -2 + t / TX;
+            } else if (t < 4 * TX) {
+                hx = (t - 2 * TX) % TX;
+                hy = TY + (t - 2 * TX) / TX;
+            } else if (t < 4 * TX + 2 * TY) {
+                hx = -2 + (t - 4 * TX) % 2;
+                hy = (t - 4 * TX) / 2;
+            } else {
+                hx = TX + (t - 4 * TX - 2 * TY) % 2;
+                hy = (t - 4 * TX - 2 * TY) / 2;
+            }
+            const int gi = i0 + hx, gj = j0 + hy;
+            // rows below/above: an interior column; columns left/right: an interior row
+            need = (hy < 0 || hy >= TY) ? (ay && gi < nx && gj < ny + 2) : (ax && gj < ny && gi < nx + 2);
+        }
+        if (need) {
+            hslot = (hy + 2) * G::W + hx + 2;
+            hoff = (long long)(j0 + hy + d.g[1]) * d.px + i0 + hx + d.g[0] + (long long)d.g[2] * st;
+        }
+    }
+    const bool own_ghost = !act && ((ax && i < nx + 2 && j < ny) || (ay && i < nx && j < ny + 2));
+    const int oslot = (ty + 2) * G::W + tx + 2;
+
+    // z window of the thread's column: qb = q_k, qc = q_(k+1), sc = slope of
+    // cell k, Fp = the flux through the face below cell k
+    T qb[9], qc[9], sc[9], Fp[9];
+    if (act) {
+        const long long base = col + (long long)(k0 - 2) * st;
+        T qa[9], qL[9], qR[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            const T* p = Pc + v * d.sv + base;
+            qa[v] = p[0];
+            qb[v] = p[st];
+            qc[v] = p[2 * st];
+        }
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            T qd = Pc[v * d.sv + base + 3 * st];
+            T s0 = mc_slope(qa[v], qb[v], qc[v]);   // cell k0-1
+            T s1 = mc_slope(qb[v], qc[v], qd);      // cell k0
+            qL[v] = qb[v] + half * s0;
+            qR[v] = qc[v] - half * s1;
+            sc[v] = s1;
+            qb[v] = qc[v];
+            qc[v] = qd;
+        }
+        face_flux<2, KIND>(qL, qR, x, y, d.lo[2] + k0 * d.dx[2],
+                           i + (long long)nx * (j + (long long)ny * k0), d, Fp);
+    }
+
+    for (int k = k0; k < k1; ++k) {
+        // (1) the new cell k+2 of the window (used in (3)), the staged plane
+        T qd[9];
+        if (act) {
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                qd[v] = Pc[v * d.sv + col + (long long)(k + 2) * st];
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                sP[v * G::PLANE + oslot] = qb[v];
+        } else if (own_ghost) {
+            const long long o = col + (long long)k * st;
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                sP[v * G::PLANE + oslot] = Pc[v * d.sv + o];
+        }
+        if (hslot >= 0) {
+            const long long o = hoff + (long long)k * st;
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                sP[v * G::PLANE + hslot] = Pc[v * d.sv + o];
+        }
+        __syncthreads();
+
+        // (2) the faces of the plane: every thread the x face left of its
+        // cell and the y face below it; the last wave, which stages no halo
+        // cells, also the tile's last face of each row and column.  One face
+        // solver serves both axes (a loop, not unrolled, keeps one copy of
+        // its code).
+        const double zc = d.lo[2] + (k + 0.5) * d.dx[2];
+        const int ntask = t >= G::NT - 64 ? 3 : 2;
+#pragma nounroll
+        for (int task = 0; task < ntask; ++task) {
+            int dir = task, xs = tx, ys = ty;
+            if (task == 2) {
+                const int l = t - (G::NT - 64);
+                dir = l < TY ? 0 : 1;
+                xs = l < TY ? TX : l - TY;
+                ys = l < TY ? l : TY;
+                if (l >= TX + TY)
+                    continue;
+            }
+            const int fi = i0 + xs, fj = j0 + ys;
+            if (dir == 0 ? !(ax && fi <= nx && fj < ny) : !(ay && fj <= ny && fi < nx))
+                continue;
+            const double fx = d.lo[0] + (dir == 0 ? fi : fi + 0.5) * d.dx[0];
+            const double fy = d.lo[1] + (dir == 0 ? fj + 0.5 : fj) * d.dx[1];
+            const long long fglob = dir == 0 ? fi + (long long)(nx + 1) * (fj + (long long)ny * k)
+                                             : fi + (long long)nx * (fj + (long long)(ny + 1) * k);
+            tile_face<KIND, G::PLANE>(sP, dir, dir == 0 ? (ys + 2) * G::W + xs : ys * G::W + xs + 2,
+                                      dir == 0 ? 1 : G::W, fx, fy, zc, fglob, d, dir == 0 ? sFx : sFy,
+                                      dir == 0 ? G::NFX : G::NFY, dir == 0 ? ys * (TX + 1) + xs : ys * TX + xs);
+        }
+        __syncthreads();
+
+        // (3) the cell update; the stage inputs are loaded first, so that the
+        // z face's arithmetic covers their latency
+        if (act) {
+            const long long c = i + (long long)nx * (j + (long long)ny * k);
+            double un[9], us[9];
+            constexpr bool early = sizeof(T) < sizeof(double);
+            if constexpr (early)
+                stage_load<NT>(d, Un, Us, c, un, us);
+            T q[9], qL[9], qR[9], Fc[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                T sn = mc_slope(qb[v], qc[v], qd[v]);   // cell k+1
+                q[v] = qb[v];
+                qL[v] = qb[v] + half * sc[v];
+                qR[v] = qc[v] - half * sn;
+                sc[v] = sn;
+                qb[v] = qc[v];
+                qc[v] = qd[v];
+            }
+            face_flux<2, KIND>(qL, qR, x, y, zc + 0.5 * d.dx[2],
+                               i + (long long)nx * (j + (long long)ny * (k + 1)), d, Fc);
+            if constexpr (!early)
+                stage_load<NT>(d, Un, Us, c, un, us);
+            double R[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                R[v] = -((double)Fc[v] - (double)Fp[v]) * d.idx[2];
+                Fp[v] = Fc[v];
+            }
+            const int fx = ty * (TX + 1) + tx, fy = ty * TX + tx;
+            if (ax) {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    R[v] -= ((double)sFx[v * G::NFX + fx + 1] - (double)sFx[v * G::NFX + fx]) * d.idx[0];
+            }
+            if (ay) {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    R[v] -= ((double)sFy[v * G::NFY + fy + TX] - (double)sFy[v * G::NFY + fy]) * d.idx[1];
+            }
+            Geo g;
+            add_sources<KIND>(d, x, y, zc, c, q, g, R);
+            int iters = 0;
+            const long long pc = col + (long long)k * st;
+            int flags = stage_finish<NT>(d, g, R, q, un, us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
             tally(flags, iters, nfail, natm, npf, nfb, itmax);
         }
     }
@@ -1241,6 +1537,46 @@ hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc,
     return hipGetLastError();
 }
 
+template <bool NT, int SEG, typename T, typename TS, typename TO>
+static void launch_substep_nt(int kind, const T* Pc, T* Pn, const double* Un, const TS* Us, TO* Uout, const Dev& d,
+                              double dt, double a, double b, unsigned long long* cnt, unsigned char* fout,
+                              hipStream_t s)
+{
+    constexpr int TX = SUB_TX, TY = SUB_TY;
+    const int ntx = (d.n[0] + TX - 1) / TX, nty = (d.n[1] + TY - 1) / TY;
+    const int ntiles = ntx * nty;
+    const long long nseg = (d.n[2] + SEG - 1) / SEG;
+    const dim3 grid((unsigned)(ntiles * nseg)), block(TX * TY);
+    if (kind == FLAT)
+        hipLaunchKernelGGL((k_substep<FLAT, TX, TY, SEG, NT, T, TS, TO>), grid, block, 0, s, Pc, Pn, Un, Us, Uout, d,
+                           dt, a, b, cnt, fout, ntx, ntiles);
+    else if (kind == ISO)
+        hipLaunchKernelGGL((k_substep<ISO, TX, TY, SEG, NT, T, TS, TO>), grid, block, 0, s, Pc, Pn, Un, Us, Uout, d,
+                           dt, a, b, cnt, fout, ntx, ntiles);
+    else
+        hipLaunchKernelGGL((k_substep<STORED, TX, TY, SEG, NT, T, TS, TO>), grid, block, 0, s, Pc, Pn, Un, Us, Uout,
+                           d, dt, a, b, cnt, fout, ntx, ntiles);
+}
+
+template <typename T, typename TS, typename TO>
+hipError_t launch_substep(int kind, const T* Pc, T* Pn, const double* Un, const TS* Us, TO* Uout, const Dev& d,
+                          double dt, double a, double b, unsigned long long* cnt, unsigned char* fout, hipStream_t s)
+{
+    // planes per workgroup: the long segment where it still gives enough
+    // workgroups to fill the GPU, else a short one (small grids)
+    const long long tiles = (long long)((d.n[0] + SUB_TX - 1) / SUB_TX) * ((d.n[1] + SUB_TY - 1) / SUB_TY);
+    const bool lng = tiles * ((d.n[2] + SUB_SEG - 1) / SUB_SEG) >= SUB_MIN_BLOCKS;
+    if (d.nt && lng)
+        launch_substep_nt<true, SUB_SEG>(kind, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
+    else if (d.nt)
+        launch_substep_nt<true, 2>(kind, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
+    else if (lng)
+        launch_substep_nt<false, SUB_SEG>(kind, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
+    else
+        launch_substep_nt<false, 2>(kind, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_rhs(int kind, const T* Fx, const T* Fy, const T* Fz, const T* Pc, double* R,
                       const Dev& d, hipStream_t s)
@@ -1363,7 +1699,10 @@ hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* 
     template hipError_t launch_update_zmarch<T, TS, TO>(int, const T*, const T*, const T*, T*,          \
                                                         const double*, const TS*, TO*, const Dev&,      \
                                                         double, double, double, unsigned long long*,    \
-                                                        unsigned char*, hipStream_t);
+                                                        unsigned char*, hipStream_t);            \
+    template hipError_t launch_substep<T, TS, TO>(int, const T*, T*, const double*, const TS*, TO*,     \
+                                                  const Dev&, double, double, double, unsigned long long*, \
+                                                  unsigned char*, hipStream_t);
 #define GRMHD_INSTANTIATE_BATCH(T)                                                                      \
     template hipError_t launch_batch_cons<T>(const BatchProb*, int, long long, const double*, double*, T*,     \
                                              const Dev&, hipStream_t);                                        \
