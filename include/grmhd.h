@@ -251,6 +251,31 @@ int grmhd_prim(grmhd_ctx *ctx, const double *U, double *P);
  * Loads P into the context's primitive cache, as grmhd_cons does. */
 int grmhd_rhs(grmhd_ctx *ctx, const double *P, double *R);
 
+/* ---- Without allocation --------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.
+ * grmhd_rhs_noalloc computes what grmhd_init + grmhd_set_stream + grmhd_rhs
+ * compute (the same kernels on the same inputs: R comes out bitwise the
+ * same), with no context and no workspace: its scratch storage (the ghosted
+ * primitive caches, the face fluxes and the counters) is a file-scope device
+ * array of GRMHD_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds until the process ends.  The call allocates nothing, on the device
+ * or on the host.
+ * Arguments as for grmhd_init (opts.workspace, timing, adjoint and
+ * tape_steps are ignored; metric kind STORED, whose metric buffer the caller
+ * would have to provide, is rejected with GRMHD_ERR_ARG) and grmhd_rhs (P
+ * read, R written, device arrays [9][nz][ny][nx]); stream is the hipStream_t
+ * (as void*) the work is enqueued on, asynchronously.  Returns
+ * GRMHD_ERR_WORKSPACE when grmhd_workspace_bytes(grid, opts) exceeds
+ * GRMHD_NOALLOC_SCRATCH_BYTES (64 MiB: a 3D grid of about 45^3 cells in FP64,
+ * 55^3 in MIXED).  Every call on one GPU uses that GPU's one scratch array
+ * and clears what must start at zero itself: calls on one stream follow each
+ * other safely, calls that overlap on one GPU (other streams, other host
+ * threads) race. */
+#define GRMHD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int grmhd_rhs_noalloc(const grmhd_metric *metric, const grmhd_grid *grid, const grmhd_eos *eos,
+                      const grmhd_opts *opts, const double *P, double *R, void *stream);
+
 /* ---- Adjoint (reverse mode) of the discrete update, FP64 ----------------
  * The step is a map U^n -> U^(n+1) (with P^n the primitives of U^n).  The
  * adjoint calls return vector-Jacobian products of that map and of the

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <vector>
 
 #include "grmhd.h"
@@ -870,6 +871,72 @@ int grmhd_rhs(grmhd_ctx* c, const double* P, double* R)
     if (!c->metric_ok)
         return GRMHD_ERR_STATE;
     return c->mixed ? rhs_t<float>(c, P, R) : rhs_t<double>(c, P, R);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of grmhd_rhs_noalloc: one array per GPU (its copy of this
+// file-scope device array), its address taken once per device on the first
+// call there.  In host code `noalloc_scratch` names a host-side stand-in, not
+// device memory: only the address from hipGetSymbolAddress is used.
+__device__ __align__(256) unsigned char noalloc_scratch[GRMHD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+void* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (nullptr on failure).
+void* noalloc_base()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p)
+            return nullptr;
+        noalloc_ptr[dev] = p;
+    }
+    return noalloc_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int grmhd_rhs_noalloc(const grmhd_metric* metric, const grmhd_grid* grid, const grmhd_eos* eos,
+                      const grmhd_opts* opts, const double* P, double* R, void* stream)
+{
+    if (!metric || !grid || !eos || !opts || !P || !R)
+        return GRMHD_ERR_ARG;
+    if (metric->kind == GRMHD_METRIC_STORED)
+        return GRMHD_ERR_ARG;   // its metric buffer would be a second allocation
+    grmhd_opts o = *opts;
+    o.timing = 0;
+    o.adjoint = 0;
+    o.tape_steps = 0;
+    if (!grid_ok(grid) || !opts_fit(grid, &o))
+        return GRMHD_ERR_ARG;
+    const size_t need = grmhd_workspace_bytes(grid, &o);
+    if (need == 0)
+        return GRMHD_ERR_ARG;
+    if (need > GRMHD_NOALLOC_SCRATCH_BYTES)
+        return GRMHD_ERR_WORKSPACE;
+    void* base = noalloc_base();
+    if (!base)
+        return GRMHD_ERR_HIP;
+    o.workspace = base;
+    o.workspace_bytes = GRMHD_NOALLOC_SCRATCH_BYTES;
+    // a context on the stack (no timing, no adjoint: nothing of it allocates)
+    grmhd_ctx c;
+    int rc = init_ctx(&c, metric, grid, eos, &o);
+    if (rc)
+        return rc;
+    c.stream = (hipStream_t)stream;
+    return c.mixed ? rhs_t<float>(&c, P, R) : rhs_t<double>(&c, P, R);
 }
 
 int grmhd_step(grmhd_ctx* c, double* U, double dt)

@@ -34,7 +34,7 @@ SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_con
            "grmhd_prim_adjoint", "grmhd_status", "grmhd_timing", "grmhd_free", "grmhd_strerror",
            "grmhd_batch_workspace_bytes", "grmhd_batch_init", "grmhd_batch_set_stream",
            "grmhd_batch_cons", "grmhd_batch_evolve", "grmhd_batch_prim", "grmhd_batch_tune",
-           "grmhd_batch_set_shape", "grmhd_batch_status", "grmhd_batch_free")
+           "grmhd_batch_set_shape", "grmhd_batch_status", "grmhd_batch_free", "grmhd_rhs_noalloc")
 
 
 class Metric(C.Structure):
@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.grmhd_batch_set_shape.argtypes = [vp, C.c_int, C.c_int]
     L.grmhd_batch_status.argtypes = [vp, C.POINTER(Stats), C.c_int]
     L.grmhd_batch_free.argtypes = [vp]
+    L.grmhd_rhs_noalloc.argtypes = [C.POINTER(Metric), C.POINTER(Grid), C.POINTER(Eos), C.POINTER(Opts), vp, vp,
+                                    vp]
     L.grmhd_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
     L.grmhd_free.argtypes = [vp]
     L.grmhd_strerror.argtypes = [C.c_int]
@@ -449,6 +451,47 @@ def batch_for(ensemble, **over) -> BatchSolver:
               rho_atm=ensemble.rho_atm, p_atm=ensemble.p_atm)
     kw.update(over)
     return BatchSolver(**kw)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def rhs_noalloc(P: torch.Tensor, n, lo, hi, bc, metric=FLAT, M=0.0, soft=SOFT_SQRT, r_min=1.0,
+                gamma=5.0 / 3.0, K=0.0, rk_order=3, c_h=1.0, kappa=1.0, rho_atm=1e-12, p_atm=1e-12,
+                newton_tol=1e-12, newton_maxit=50, precision="fp64", recovery="2d", reconstruction="mc",
+                divergence="cleaning", R: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """grmhd_rhs_noalloc: the right-hand side of the primitives P (float64,
+    (9, nz, ny, nx), on a GPU) with the library's static scratch, no context
+    and no workspace.  R is written (allocated here by torch if not given)."""
+    n = tuple(int(v) for v in n)
+    shape = (NVAR, n[2], n[1], n[0])
+    if (not isinstance(P, torch.Tensor) or P.dtype != torch.float64 or not P.is_contiguous()
+            or P.device.type != "cuda" or tuple(P.shape) != shape):
+        raise ValueError("P must be a contiguous float64 GPU tensor of shape %s" % (shape,))
+    R = torch.empty_like(P) if R is None else R
+    if (R.dtype != torch.float64 or not R.is_contiguous() or R.device != P.device
+            or tuple(R.shape) != shape):
+        raise ValueError("R must be a contiguous float64 tensor of shape %s on %s" % (shape, P.device))
+    opts = Opts(int(rk_order), PRECISIONS[precision], float(c_h), float(kappa), float(rho_atm),
+                float(p_atm), float(newton_tol), int(newton_maxit), RECOVERY[recovery],
+                RECONSTRUCTION[reconstruction], DIVERGENCE[divergence], 0, 0, 0, None, 0)
+    st = stream if stream is not None else torch.cuda.current_stream(P.device)
+    with torch.cuda.device(P.device):
+        _check(load().grmhd_rhs_noalloc(C.byref(Metric(int(metric), int(soft), float(M), float(r_min))),
+                                        C.byref(make_grid(n, lo, hi, bc)), C.byref(Eos(0, float(gamma), float(K))),
+                                        C.byref(opts), C.c_void_p(P.data_ptr()), C.c_void_p(R.data_ptr()),
+                                        C.c_void_p(st.cuda_stream)), "grmhd_rhs_noalloc")
+    return R
+
+
+def rhs_noalloc_for(workload, P: torch.Tensor, **over) -> torch.Tensor:
+    """rhs_noalloc configured for a :class:`workloads.Workload`."""
+    kw = dict(n=workload.n, lo=workload.lo, hi=workload.hi, bc=workload.bc, metric=workload.metric,
+              M=workload.M, soft=workload.soft, r_min=workload.r_min, gamma=workload.gamma,
+              rk_order=workload.rk_order, c_h=workload.c_h, kappa=workload.kappa,
+              rho_atm=workload.rho_atm, p_atm=workload.p_atm)
+    kw.update(over)
+    return rhs_noalloc(P, **kw)
 
 
 def solver_for(workload, **over) -> Solver:

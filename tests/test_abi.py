@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 28, names
+    assert len(names) == 29, names
     assert set(names) == set(lib.SYMBOLS)
     L = lib.load()
     for n in names:
@@ -308,3 +308,24 @@ def test_batch_workspace_and_init_validation(lib):
     assert L.grmhd_batch_free(ctx) == 0
     o.workspace_bytes = nb - 8
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == -2
+
+
+def test_rhs_noalloc_validates_before_touching_a_device(lib):
+    """Refusals of grmhd_rhs_noalloc happen host-side, before any HIP call:
+    missing arguments, the stored metric (whose buffer would be a second
+    allocation), and a grid whose workspace exceeds the static scratch."""
+    L = lib.load()
+    g = lib.make_grid((16, 8, 4), (0, 0, 0), (1, 1, 1), (0, 0, 0))
+    m = lib.Metric(0, 0, 0.0, 1.0)
+    e = lib.Eos(0, 5.0 / 3.0, 0.0)
+    o = lib.Opts()
+    o.rk_order, o.rho_atm = 3, 1e-10
+    fake = C.c_void_p(256)   # never dereferenced: every call below is refused first
+    ERR_ARG, ERR_WS = -1, -2
+    assert L.grmhd_rhs_noalloc(None, C.byref(g), C.byref(e), C.byref(o), fake, fake, None) == ERR_ARG
+    assert L.grmhd_rhs_noalloc(C.byref(m), C.byref(g), C.byref(e), C.byref(o), None, fake, None) == ERR_ARG
+    stored = lib.Metric(2, 0, 0.0, 1.0)
+    assert L.grmhd_rhs_noalloc(C.byref(stored), C.byref(g), C.byref(e), C.byref(o), fake, fake, None) == ERR_ARG
+    big = lib.make_grid((64, 64, 64), (0, 0, 0), (1, 1, 1), (0, 0, 0))
+    assert L.grmhd_workspace_bytes(C.byref(big), C.byref(o)) > lib.NOALLOC_SCRATCH_BYTES
+    assert L.grmhd_rhs_noalloc(C.byref(m), C.byref(big), C.byref(e), C.byref(o), fake, fake, None) == ERR_WS
