@@ -411,11 +411,11 @@ const double RK2B[2] = {1.0, 0.5};
 // One substep's update launch with the stage-state types TS (read) and TO
 // (written).
 template <typename T, typename TS, typename TO>
-int update_stage(grmhd_ctx* c, bool zmarch, int src, int dst, const double* U, const TS* Us, TO* Uout,
+int update_stage(grmhd_ctx* c, bool fused, int src, int dst, const double* U, const TS* Us, TO* Uout,
                  double dt, double a, double b)
 {
     return timed(c, GRMHD_K_UPDATE, [&] {
-        if (zmarch)
+        if (fused)
             return grmhd::launch_substep(c->kind, (const T*)cache<T>(c, src), cache<T>(c, dst), U, Us, Uout, c->d,
                                          dt, a, b, c->cnt, (unsigned char*)nullptr, c->stream);
         return grmhd::launch_update(c->kind, (const T*)faces<T>(c, 0), (const T*)faces<T>(c, 1),
@@ -430,26 +430,27 @@ int step_t(grmhd_ctx* c, double* U, double dt)
     const int ns = c->rk_order;
     const double* A = ns == 3 ? RK3A : RK2A;
     const double* B = ns == 3 ? RK3B : RK2B;
-    // 3D grids with MC and cleaning: the z faces are computed inside the fused
-    // update kernel, which writes the new primitives to another cache;
-    // otherwise (1D, 2D, PPM, flux-CT) the update works in place on the cache
-    // with all face fluxes precomputed (and, for flux-CT, corrected).  The first stage
+    // 3D grids with MC and cleaning: one launch of the fused substep kernel
+    // (the faces of every axis, the differences, sources, RK combination and
+    // recovery), which writes the new primitives to another cache; otherwise
+    // (1D, 2D, PPM, flux-CT) the face kernels and then the update in place on
+    // the cache (for flux-CT with the face fluxes corrected in between).  The first stage
     // reads U^n as its stage state; the intermediate stage state has the cache
     // type (float in the mixed path); the last stage writes U.
-    const bool zmarch = c->d.act[2] && !c->d.ppm && !c->d.ct;
+    const bool fused = c->d.act[2] && !c->d.ppm && !c->d.ct;
     T* Us = (T*)c->Us;
     for (int s = 0; s < ns; ++s) {
-        const int src = zmarch ? s : 0;
-        const int dst = zmarch ? (s == ns - 1 ? 0 : s + 1) : 0;
-        int rc = fluxes<T>(c, src, zmarch ? 0 : 3);
+        const int src = fused ? s : 0;
+        const int dst = fused ? (s == ns - 1 ? 0 : s + 1) : 0;
+        int rc = fluxes<T>(c, src, fused ? 0 : 3);
         if (rc)
             return rc;
         if (s == 0)
-            rc = update_stage<T>(c, zmarch, src, dst, U, (const double*)U, Us, dt, A[s], B[s]);
+            rc = update_stage<T>(c, fused, src, dst, U, (const double*)U, Us, dt, A[s], B[s]);
         else if (s < ns - 1)
-            rc = update_stage<T>(c, zmarch, src, dst, U, (const T*)Us, Us, dt, A[s], B[s]);
+            rc = update_stage<T>(c, fused, src, dst, U, (const T*)Us, Us, dt, A[s], B[s]);
         else
-            rc = update_stage<T>(c, zmarch, src, dst, U, (const T*)Us, U, dt, A[s], B[s]);
+            rc = update_stage<T>(c, fused, src, dst, U, (const T*)Us, U, dt, A[s], B[s]);
         if (rc)
             return rc;
         c->ghosts_ok[dst] = true;
@@ -486,7 +487,7 @@ int adj_prepare(grmhd_ctx* c)
 int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, const double* B)
 {
     const int ns = c->rk_order;
-    const bool zmarch = c->d.act[2] && !c->d.ppm && !c->d.ct;
+    const bool fused = c->d.act[2] && !c->d.ppm && !c->d.ct;
     int rc = timed(c, GRMHD_K_PRIM, [&] {
         return grmhd::launch_prim(c->kind, U, c->Pb, c->Ac[0], c->d, c->cnt, c->stream);
     });
@@ -494,7 +495,7 @@ int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, con
         return rc;
     for (int s = 0; s < ns; ++s) {
         const double* Ps = c->Ac[s];
-        for (int dir = 0; dir < (zmarch ? 0 : 3); ++dir) {
+        for (int dir = 0; dir < (fused ? 0 : 3); ++dir) {
             if (!c->d.act[dir])
                 continue;
             rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
@@ -506,7 +507,7 @@ int adj_recompute(grmhd_ctx* c, const double* U, double dt, const double* A, con
         const double* Us = s == 0 ? U : c->Aus;
         unsigned char* fl = c->Aflags + (size_t)s * c->L.N;
         rc = timed(c, GRMHD_K_UPDATE, [&] {
-            if (zmarch)
+            if (fused)
                 return grmhd::launch_substep(c->kind, Ps, c->Ac[s + 1], U, Us, c->Aus, c->d, dt, A[s], B[s], c->cnt,
                                              fl, c->stream);
             return grmhd::launch_update(c->kind, (const double*)c->F[0], (const double*)c->F[1],
@@ -591,7 +592,7 @@ int step_record(grmhd_ctx* c, double* U, double dt, int slot)
     const int ns = c->rk_order;
     const double* A = ns == 3 ? RK3A : RK2A;
     const double* B = ns == 3 ? RK3B : RK2B;
-    const bool zmarch = c->d.act[2] && !c->d.ppm && !c->d.ct;
+    const bool fused = c->d.act[2] && !c->d.ppm && !c->d.ct;
     const size_t bytes = sizeof(double) * 9 * (size_t)c->L.sv;
     int rc = GRMHD_OK;
     if (!c->ghosts_ok[0]) {
@@ -608,7 +609,7 @@ int step_record(grmhd_ctx* c, double* U, double dt, int slot)
     for (int s = 0; s < ns; ++s) {
         const double* Ps = tape_cache(c, slot, s);
         double* Pn = tape_cache(c, slot, s + 1);
-        for (int dir = 0; dir < (zmarch ? 0 : 3); ++dir) {
+        for (int dir = 0; dir < (fused ? 0 : 3); ++dir) {
             if (!c->d.act[dir])
                 continue;
             rc = timed(c, GRMHD_K_FLUX_X + dir, [&] {
@@ -621,7 +622,7 @@ int step_record(grmhd_ctx* c, double* U, double dt, int slot)
         double* Uo = s == ns - 1 ? U : Us;
         unsigned char* f = fl + (size_t)s * c->L.N;
         rc = timed(c, GRMHD_K_UPDATE, [&] {
-            if (zmarch)
+            if (fused)
                 return grmhd::launch_substep(c->kind, Ps, Pn, U, Uin, Uo, c->d, dt, A[s], B[s], c->cnt, f,
                                              c->stream);
             return grmhd::launch_update(c->kind, (const double*)c->F[0], (const double*)c->F[1],

@@ -42,10 +42,6 @@ template <typename T, typename TS, typename TO>
 hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, const T* Pc, T* Pn, const double* Un,
                          const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
                          unsigned long long* cnt, unsigned char* fout, hipStream_t s);
-template <typename T, typename TS, typename TO>
-hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc, T* Pn, const double* Un,
-                                const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
-                                unsigned long long* cnt, unsigned char* fout, hipStream_t s);
 // The whole substep of a 3D grid (MC, cleaning) in one launch: faces of all
 // three axes, flux differences, sources, RK combination and recovery; reads
 // the primitives from Pc, writes the new ones (with ghost images) to Pn.

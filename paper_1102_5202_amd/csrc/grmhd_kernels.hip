@@ -1,20 +1,19 @@
 // grmhd_kernels.hip -- HIP kernels of the GRMHD substep (gfx950, wave64).
 //
-// One substep (section 2.2 of the paper) on a 3D grid is three launches:
-//   k_flux_x          per x face: MC reconstruction of the 9 primitives, exact
-//                     (normal field, Phi) cleaning pair, face physics of both
-//                     states, HLLE flux (section 3.2)
-//   k_flux_march<1>   the same for y faces, a thread marching along y
-//   k_update_zmarch   a thread marching along z: z faces, flux differences,
-//                     metric sources (eq. 2), SSP Runge-Kutta combination,
-//                     Newton recovery of the primitives with the
-//                     atmosphere/floor policy, status counters
-// Every kernel that writes primitives also writes their ghost images, so the
-// ghost pass k_ghosts runs only for caches filled otherwise.  1D and 2D grids,
-// PPM (k_flux_ppm) and flux-CT (k_ct_edges, k_ct_faces) use the face kernels of
-// every active axis and the cell kernel k_update.  Also here: the stored
-// metric's set-up (k_metric), the single-kernel maps (k_cons, k_prim, k_rhs)
-// and the batched 1D ensemble (k_batch_*).
+// One substep (section 2.2 of the paper) on a 3D grid is one launch of
+// k_substep: per tile of z columns and plane, the primitives staged in LDS,
+// MC reconstruction of the 9 primitives, exact (normal field, Phi) cleaning
+// pair, face physics of both states and HLLE flux (section 3.2) for the x and
+// y faces from LDS and for the z faces from a register window, then per cell
+// the flux differences, metric sources (eq. 2), SSP Runge-Kutta combination,
+// Newton recovery of the primitives with the atmosphere/floor policy and the
+// status counters.  Every kernel that writes primitives also writes their
+// ghost images, so the ghost pass k_ghosts runs only for caches filled
+// otherwise.  1D and 2D grids, PPM (k_flux_ppm) and flux-CT (k_ct_edges,
+// k_ct_faces) use face kernels per active axis (k_flux_x, k_flux_march) and the
+// cell kernel k_update.  Also here: the stored metric's set-up (k_metric), the
+// single-kernel maps (k_cons, k_prim, k_rhs) and the batched 1D ensemble
+// (k_batch_*).
 //
 // T is the type of the primitive caches, the face fluxes and the face physics:
 // double (FP64 path) or float (mixed precision).  The metric is always
@@ -29,7 +28,7 @@
 namespace grmhd {
 
 static constexpr int BLOCK = 256;
-static constexpr int MARCH_SEG = 8;   // faces (cells) per thread in the z marches
+static constexpr int MARCH_SEG = 8;   // faces per thread in the z face march (flux-CT)
 static constexpr unsigned MIN_BLOCKS = 1024;   // 4 workgroups per CU: enough to fill the GPU
 // the fused substep kernel: tile of TX x TY columns, SUB_SEG planes per workgroup
 static constexpr int SUB_TX = 32, SUB_TY = 8, SUB_SEG = 8;
@@ -570,133 +569,6 @@ __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, cons
     count_sums(cnt, nf, na, np, nb, itmax);
 }
 
-// z faces and the cell update fused (3D grids).  A thread owns cells
-// k0..k1-1 of the column (i, j), computes the z faces k0-1/2 .. k1-1/2 in
-// order (one face per cell plus one) keeping the previous face flux in
-// registers, and for each cell forms R from that z flux difference and the
-// x/y face fluxes, adds the sources, combines the RK stage and recovers the
-// primitives, written to the other primitive cache Pn (segments of one column
-// overlap by two cells, so the cache read here cannot be updated in place).
-template <int KIND, int SEG, bool NT, typename T, typename TS, typename TO>
-__global__ __launch_bounds__(BLOCK) void k_update_zmarch(
-    const T* __restrict__ Fx, const T* __restrict__ Fy, const T* __restrict__ Pc, T* __restrict__ Pn,
-    const double* Un, const TS* Us, TO* Uout, Dev d, double dt, double a, double b,
-    unsigned long long* __restrict__ cnt, unsigned char* __restrict__ fout)
-{
-    const int nz = d.n[2];
-    const int nseg = (nz + SEG - 1) / SEG;
-    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
-    if (t < (long long)d.n[0] * d.n[1] * nseg) {
-        const int i = (int)(t % d.n[0]);
-        const long long r = t / d.n[0];
-        const int j = (int)(r % d.n[1]);
-        const int seg = (int)(r / d.n[1]);
-        const int k0 = seg * SEG;
-        const int k1 = min(k0 + SEG, nz);
-        const long long st = (long long)d.px * d.py;
-        const long long col = (long long)(j + d.g[1]) * d.px + i + d.g[0];
-        // ghosted address of cell k0 - 2
-        const long long base = col + (long long)(k0 - 2 + d.g[2]) * st;
-        const double x = d.lo[0] + (i + 0.5) * d.dx[0];
-        const double y = d.lo[1] + (j + 0.5) * d.dx[1];
-        const T half = T(0.5);
-        T qb[9], qc[9], sc[9], Fp[9];
-        {
-            T qa[9], qL[9], qR[9];
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                const T* p = Pc + v * d.sv + base;
-                qa[v] = p[0];
-                qb[v] = p[st];
-                qc[v] = p[2 * st];
-            }
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                T qd = Pc[v * d.sv + base + 3 * st];
-                T s0 = mc_slope(qa[v], qb[v], qc[v]);   // cell k0-1
-                T s1 = mc_slope(qb[v], qc[v], qd);      // cell k0
-                qL[v] = qb[v] + half * s0;
-                qR[v] = qc[v] - half * s1;
-                sc[v] = s1;
-                qb[v] = qc[v];
-                qc[v] = qd;
-            }
-            face_flux<2, KIND>(qL, qR, x, y, d.lo[2] + k0 * d.dx[2],
-                               i + (long long)d.n[0] * (j + (long long)d.n[1] * k0), d, Fp);
-        }
-        // window now: qb = q_k0, qc = q_{k0+1}, sc = slope of cell k0.  With a
-        // float cache the new cell k+2 of each iteration is loaded one
-        // iteration ahead into qn (3 % faster); a double cache has no
-        // registers to spare for it (more than 256 VGPRs halve the waves).
-        constexpr bool ahead = sizeof(T) < sizeof(double);
-        T qn[9];
-        if constexpr (ahead) {
-#pragma unroll
-            for (int v = 0; v < 9; ++v)
-                qn[v] = Pc[v * d.sv + base + 4 * st];
-        }
-        for (int k = k0; k < k1; ++k) {
-            T q[9], qL[9], qR[9], Fc[9], qd[9];
-            const long long pnext = base + (long long)(k - k0 + 4) * st;   // cell k+2
-            if constexpr (ahead) {
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    qd[v] = qn[v];
-                if (k + 1 < k1) {
-#pragma unroll
-                    for (int v = 0; v < 9; ++v)
-                        qn[v] = Pc[v * d.sv + pnext + st];
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    qd[v] = Pc[v * d.sv + pnext];
-            }
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                T sn = mc_slope(qb[v], qc[v], qd[v]);   // cell k+1
-                q[v] = qb[v];
-                qL[v] = qb[v] + half * sc[v];
-                qR[v] = qc[v] - half * sn;
-                sc[v] = sn;
-                qb[v] = qc[v];
-                qc[v] = qd[v];
-            }
-            const double z = d.lo[2] + (k + 0.5) * d.dx[2];
-            face_flux<2, KIND>(qL, qR, x, y, z + 0.5 * d.dx[2],
-                               i + (long long)d.n[0] * (j + (long long)d.n[1] * (k + 1)), d, Fc);
-            const long long c = i + (long long)d.n[0] * (j + (long long)d.n[1] * k);
-            double R[9];
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                R[v] = -((double)Fc[v] - (double)Fp[v]) * d.idx[2];
-                Fp[v] = Fc[v];
-            }
-            if (d.act[0]) {
-                long long f = i + (long long)(d.n[0] + 1) * (j + (long long)d.n[1] * k);
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    R[v] -= ((double)Fx[v * d.nf[0] + f + 1] - (double)Fx[v * d.nf[0] + f]) * d.idx[0];
-            }
-            if (d.act[1]) {
-                long long f = i + (long long)d.n[0] * (j + (long long)(d.n[1] + 1) * k);
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    R[v] -= ((double)Fy[v * d.nf[1] + f + d.n[0]] - (double)Fy[v * d.nf[1] + f]) *
-                            d.idx[1];
-            }
-            Geo g;
-            add_sources<KIND>(d, x, y, z, c, q, g, R);
-            int iters = 0;
-            const long long pc = col + (long long)(k + d.g[2]) * st;
-            int flags = stage_cell<NT>(d, g, R, q, Un, Us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
-            tally(flags, iters, nfail, natm, npf, nfb, itmax);
-        }
-    }
-    count_sums(cnt, nfail, natm, npf, nfb, itmax);
-}
-
 // ---------------------------------------------------------------------------
 // The whole substep of a 3D grid in one kernel (MC reconstruction, cleaning).
 // A workgroup owns a TX x TY tile of z columns and a segment of SEG planes and
@@ -863,6 +735,17 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
                            i + (long long)nx * (j + (long long)ny * k0), d, Fp);
     }
 
+    // with a float cache the halo cell of the plane to stage next is loaded
+    // one plane ahead (during the recovery of the plane before), so that
+    // staging waits for nothing (6 % on a mixed substep); a double cache has
+    // no registers to spare for it
+    constexpr bool pre = sizeof(T) < sizeof(double);
+    T hv[9];
+    if (pre && hslot >= 0) {
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            hv[v] = Pc[v * d.sv + hoff + (long long)k0 * st];
+    }
     for (int k = k0; k < k1; ++k) {
         // (1) the new cell k+2 of the window (used in (3)), the staged plane
         T qd[9];
@@ -879,7 +762,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
             for (int v = 0; v < 9; ++v)
                 sP[v * G::PLANE + oslot] = Pc[v * d.sv + o];
         }
-        if (hslot >= 0) {
+        if (pre && hslot >= 0) {
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                sP[v * G::PLANE + hslot] = hv[v];
+        } else if (hslot >= 0) {
             const long long o = hoff + (long long)k * st;
 #pragma unroll
             for (int v = 0; v < 9; ++v)
@@ -960,10 +847,19 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
             }
             Geo g;
             add_sources<KIND>(d, x, y, zc, c, q, g, R);
+            if (pre && hslot >= 0 && k + 1 < k1) {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    hv[v] = Pc[v * d.sv + hoff + (long long)(k + 1) * st];
+            }
             int iters = 0;
             const long long pc = col + (long long)k * st;
             int flags = stage_finish<NT>(d, g, R, q, un, us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
             tally(flags, iters, nfail, natm, npf, nfb, itmax);
+        } else if (pre && hslot >= 0 && k + 1 < k1) {
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                hv[v] = Pc[v * d.sv + hoff + (long long)(k + 1) * st];
         }
     }
     count_sums(cnt, nfail, natm, npf, nfb, itmax);
@@ -1498,46 +1394,6 @@ hipError_t launch_update(int kind, const T* Fx, const T* Fy, const T* Fz, const 
 }
 
 template <bool NT, int SEG, typename T, typename TS, typename TO>
-static void launch_update_zmarch_nt(int kind, const T* Fx, const T* Fy, const T* Pc, T* Pn, const double* Un,
-                                    const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
-                                    unsigned long long* cnt, unsigned char* fout, hipStream_t s)
-{
-    // cells per thread: with a float cache a longer march (fewer re-read
-    // window cells) pays, 1.5 %; with a double cache 8 is the fastest.  The
-    // caller picks SEG = 2 where the long march would leave the GPU short of
-    // workgroups (small grids).
-    long long nseg = (d.n[2] + SEG - 1) / SEG;
-    unsigned nb = blocks_for((long long)d.n[0] * d.n[1] * nseg);
-    if (kind == FLAT)
-        hipLaunchKernelGGL((k_update_zmarch<FLAT, SEG, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
-                           Un, Us, Uout, d, dt, a, b, cnt, fout);
-    else if (kind == ISO)
-        hipLaunchKernelGGL((k_update_zmarch<ISO, SEG, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc, Pn,
-                           Un, Us, Uout, d, dt, a, b, cnt, fout);
-    else
-        hipLaunchKernelGGL((k_update_zmarch<STORED, SEG, NT, T, TS, TO>), dim3(nb), dim3(BLOCK), 0, s, Fx, Fy, Pc,
-                           Pn, Un, Us, Uout, d, dt, a, b, cnt, fout);
-}
-
-template <typename T, typename TS, typename TO>
-hipError_t launch_update_zmarch(int kind, const T* Fx, const T* Fy, const T* Pc, T* Pn, const double* Un,
-                                const TS* Us, TO* Uout, const Dev& d, double dt, double a, double b,
-                                unsigned long long* cnt, unsigned char* fout, hipStream_t s)
-{
-    constexpr int LONG = sizeof(T) < sizeof(double) ? 12 : MARCH_SEG;
-    const bool lng = blocks_for((long long)d.n[0] * d.n[1] * ((d.n[2] + LONG - 1) / LONG)) >= MIN_BLOCKS;
-    if (d.nt && lng)
-        launch_update_zmarch_nt<true, LONG>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
-    else if (d.nt)
-        launch_update_zmarch_nt<true, 2>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
-    else if (lng)
-        launch_update_zmarch_nt<false, LONG>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
-    else
-        launch_update_zmarch_nt<false, 2>(kind, Fx, Fy, Pc, Pn, Un, Us, Uout, d, dt, a, b, cnt, fout, s);
-    return hipGetLastError();
-}
-
-template <bool NT, int SEG, typename T, typename TS, typename TO>
 static void launch_substep_nt(int kind, const T* Pc, T* Pn, const double* Un, const TS* Us, TO* Uout, const Dev& d,
                               double dt, double a, double b, unsigned long long* cnt, unsigned char* fout,
                               hipStream_t s)
@@ -1696,10 +1552,6 @@ hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* 
                                                  const double*, const TS*, TO*, const Dev&, double,     \
                                                  double, double, unsigned long long*, unsigned char*,   \
                                                  hipStream_t);                                          \
-    template hipError_t launch_update_zmarch<T, TS, TO>(int, const T*, const T*, const T*, T*,          \
-                                                        const double*, const TS*, TO*, const Dev&,      \
-                                                        double, double, double, unsigned long long*,    \
-                                                        unsigned char*, hipStream_t);            \
     template hipError_t launch_substep<T, TS, TO>(int, const T*, T*, const double*, const TS*, TO*,     \
                                                   const Dev&, double, double, double, unsigned long long*, \
                                                   unsigned char*, hipStream_t);
