@@ -336,7 +336,10 @@ def batch_throughput(grmhd, e, dev):
         s.evolve(U)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        out[prec] = {"value": work / t, "seconds": round(t, 4), "threads": th, "lds_rows": lds,
+        out[prec] = {"value": work / t, "seconds": round(t, 4), "threads": th,
+                     "placement": {0: "one workgroup per problem, rows in HBM",
+                                   1: "one workgroup per problem, rows in LDS",
+                                   2: "problems split among workgroups by work"}[lds],
                      "recovery": s.status(), "finite": bool(torch.isfinite(U).all().item())}
         del s, U
     out["mixed"]["speedup_vs_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)

@@ -365,21 +365,33 @@ int grmhd_batch_evolve(grmhd_batch *b, double *U, int max_steps);
 /* Primitives from conserved variables for every problem (packed). */
 int grmhd_batch_prim(grmhd_batch *b, const double *U, double *P);
 
-/* Time each launch shape (workgroup size; LDS or global primitive rows) on
- * trial_steps steps of copies of the current state (U and the rows are left
- * as they are), keep the fastest for grmhd_batch_evolve, and report it in
- * *shape (threads) and *lds when not NULL.  Synchronises. */
+/* Time each launch shape (workgroup size; placement of the primitive rows)
+ * on copies of the current state (U and the rows are left as they are), each
+ * problem taking a share of trial_steps steps in proportion to the steps it
+ * has left (the problem with the most left takes trial_steps), keep the
+ * fastest for grmhd_batch_evolve, and report it in *threads and *lds (the
+ * placement, as for grmhd_batch_set_shape) when not NULL.  Synchronises. */
 int grmhd_batch_tune(grmhd_batch *b, const double *U, int trial_steps, int *threads, int *lds);
 
 /* Choose the launch shape of grmhd_batch_evolve by hand: threads per
- * workgroup (256, 512 or 1024) and whether the primitive rows live in LDS
- * (refused with GRMHD_ERR_ARG when the largest row does not fit in 160 KiB, or
- * when the device refused that much LDS at grmhd_batch_init).  Rows in LDS
- * are the initial choice wherever they are allowed.  grmhd_batch_evolve makes
- * no call but the launch, so it can be captured in a HIP graph. */
+ * workgroup (256, 512 or 1024) and the placement lds of the primitive rows:
+ * 0 one workgroup per problem, rows in HBM; 1 one workgroup per problem,
+ * rows in LDS (refused with GRMHD_ERR_ARG when the largest row does not fit
+ * in 160 KiB, or when the device refused that much LDS at grmhd_batch_init);
+ * 2 (threads 256) every problem split among workgroups in proportion to its
+ * work (cells x steps), all of them resident at once, the parts of a problem
+ * exchanging the cells beside their segments through rows in HBM after each
+ * substep (refused where grmhd_batch_init could not size the split for the
+ * device).  Rows in LDS are the initial choice wherever they are allowed.
+ * grmhd_batch_evolve makes no call but its launches (one; two for the split:
+ * the parts' progress counters are set from the step counts first), so it
+ * can be captured in a HIP graph. */
 int grmhd_batch_set_shape(grmhd_batch *b, int threads, int lds);
 
-/* As grmhd_status, for the batch. */
+/* As grmhd_status, for the batch.  Returns GRMHD_ERR_STATE when a part of a
+ * split launch stopped waiting for a neighbouring part (the parts were not
+ * all resident at once, e.g. beside other work on the GPU); the state of the
+ * problems is then not valid.  The counters are returned all the same. */
 int grmhd_batch_status(grmhd_batch *b, grmhd_stats *st, int reset);
 
 int grmhd_batch_free(grmhd_batch *b);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <new>
@@ -20,6 +21,11 @@ using grmhd::Dev;
 namespace {
 
 constexpr size_t LDS_LIMIT = 160 * 1024;
+// Split launch: at most this many parts, each at least this many cells.
+constexpr int SPLIT_MAX_PARTS = 4096;
+constexpr int SPLIT_MIN_CELLS = 64;
+// Placement of the primitive rows (grmhd_batch_set_shape's lds argument).
+enum { PLACE_HBM = 0, PLACE_LDS = 1, PLACE_SPLIT = 2 };
 
 size_t up(size_t x, size_t a)
 {
@@ -29,7 +35,8 @@ size_t up(size_t x, size_t a)
 struct BatchLayout {
     long long ncell = 0, nrow = 0;   // cells in all; elements of all ghosted rows
     int nmax = 0;
-    size_t off_cnt, off_probs, off_order, off_probs_t, off_prow, off_pnext, off_us, off_prow_t, off_u_t, total;
+    size_t off_cnt, off_probs, off_order, off_probs_t, off_prow, off_pnext, off_us, off_prow_t, off_u_t;
+    size_t off_parts, off_flags, total;
 };
 
 bool desc_ok(const grmhd_batch_desc* d)
@@ -78,6 +85,10 @@ BatchLayout batch_layout(const grmhd_batch_desc* d, size_t esize)
     off = up(off + esize * L.nrow, 256);
     L.off_u_t = off;
     off = up(off + sizeof(double) * 9 * L.ncell, 256);
+    L.off_parts = off;                   // the split launch's parts and their flags
+    off = up(off + sizeof(grmhd::BatchPart) * SPLIT_MAX_PARTS, 256);
+    L.off_flags = off;
+    off = up(off + sizeof(int) * SPLIT_MAX_PARTS, 256);
     L.total = off;
     return L;
 }
@@ -104,6 +115,7 @@ struct grmhd_batch {
     int lds = 0;
     size_t lds_bytes = 0;
     bool lds_ok = false;   // rows fit in LDS and their LDS size is allowed
+    std::vector<grmhd::BatchPart> parts;   // the split launch (empty: not available)
     unsigned long long* cnt = nullptr;
 };
 
@@ -128,6 +140,10 @@ int upload(grmhd_batch* b, bool reset)
         if (hipMemcpyAsync(at<int>(b, b->L.off_order), b->order.data(), sizeof(int) * b->nprob,
                            hipMemcpyHostToDevice, b->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
+        if (!b->parts.empty() &&
+            hipMemcpyAsync(at<grmhd::BatchPart>(b, b->L.off_parts), b->parts.data(),
+                           sizeof(grmhd::BatchPart) * b->parts.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+            return GRMHD_ERR_HIP;
         if (grmhd::launch_zero_counters(b->cnt, b->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
         b->uploaded = true;
@@ -138,6 +154,13 @@ int upload(grmhd_batch* b, bool reset)
 template <typename T>
 int evolve_t(grmhd_batch* b, double* U, int max_steps, size_t off_probs, size_t off_prow)
 {
+    if (b->lds == PLACE_SPLIT) {
+        const hipError_t e = grmhd::launch_batch_split<T>(
+            at<BatchProb>(b, off_probs), at<grmhd::BatchPart>(b, b->L.off_parts), (int)b->parts.size(),
+            at<int>(b, b->L.off_flags), U, at<T>(b, b->L.off_us), at<T>(b, off_prow), at<T>(b, b->L.off_pnext), b->d,
+            b->rk_order, max_steps, b->cnt, b->stream);
+        return e == hipSuccess ? GRMHD_OK : GRMHD_ERR_HIP;
+    }
     const hipError_t e = grmhd::launch_batch_evolve<T>(
         b->shape, b->lds, b->lds_bytes, at<BatchProb>(b, off_probs), at<int>(b, b->L.off_order), b->nprob, U,
         at<T>(b, b->L.off_us), at<T>(b, off_prow), at<T>(b, b->L.off_pnext), b->d, b->rk_order, max_steps, b->cnt,
@@ -149,6 +172,56 @@ int evolve(grmhd_batch* b, double* U, int max_steps, size_t off_probs, size_t of
 {
     return b->mixed ? evolve_t<float>(b, U, max_steps, off_probs, off_prow)
                     : evolve_t<double>(b, U, max_steps, off_probs, off_prow);
+}
+
+// The split launch's parts: every problem gets parts in proportion to its
+// work (cells x steps), at least one and at most one per SPLIT_MIN_CELLS
+// cells, so that the parts' work is about even and all of them fit on the
+// GPU at once (cap: resident workgroups of the split kernel).  A problem's
+// parts are consecutive; with periodic ends its first and last part are
+// neighbours.
+std::vector<grmhd::BatchPart> split_parts(const std::vector<BatchProb>& probs, int bc, int cap)
+{
+    std::vector<grmhd::BatchPart> parts;
+    const int np = (int)probs.size();
+    cap = std::min(cap, SPLIT_MAX_PARTS);
+    if (cap < np)
+        return parts;
+    double total = 0.0;
+    for (const BatchProb& p : probs)
+        total += (double)p.n * std::max(p.steps, 1);
+    double w = total / cap;
+    std::vector<int> g(np);
+    for (int tries = 0; tries < 1000; ++tries) {
+        long long sum = 0;
+        for (int b = 0; b < np; ++b) {
+            const double work = (double)probs[b].n * std::max(probs[b].steps, 1);
+            const int gmax = std::max(1, probs[b].n / SPLIT_MIN_CELLS);
+            g[b] = (int)std::min<double>(gmax, std::max(1.0, std::ceil(work / w)));
+            sum += g[b];
+        }
+        if (sum <= cap)
+            break;
+        w *= 1.05;
+    }
+    for (int b = 0; b < np; ++b) {
+        const int first = (int)parts.size(), n = probs[b].n;
+        for (int q = 0; q < g[b]; ++q) {
+            grmhd::BatchPart pt{};
+            pt.b = b;
+            pt.c0 = (int)((long long)n * q / g[b]);
+            pt.c1 = (int)((long long)n * (q + 1) / g[b]);
+            const bool wrap = bc == 0 && g[b] > 1;
+            pt.left = q > 0 ? first + q - 1 : (wrap ? first + g[b] - 1 : -1);
+            pt.right = q + 1 < g[b] ? first + q + 1 : (wrap ? first : -1);
+            pt.first = first;
+            pt.count = g[b];
+            parts.push_back(pt);
+        }
+    }
+    if ((long long)parts.size() > cap)
+        parts.clear();
+    return parts;
 }
 
 }  // namespace
@@ -250,7 +323,17 @@ int grmhd_batch_init(grmhd_batch** out, const grmhd_batch_desc* desc, const grmh
             (void)hipGetLastError();   // clear it: launches check the last error
         b->lds_ok = e == hipSuccess;
     }
-    b->lds = b->lds_ok ? 1 : 0;
+    b->lds = b->lds_ok ? PLACE_LDS : PLACE_HBM;
+    // the split launch needs every part resident at once: its occupancy on
+    // this device (where that cannot be asked, there is no split launch)
+    int dev = -1, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+        const int occ = b->mixed ? grmhd::batch_split_occupancy<float>() : grmhd::batch_split_occupancy<double>();
+        if (occ > 0 && cus > 0)
+            b->parts = split_parts(b->probs, desc->bc == GRMHD_BC_PERIODIC ? 0 : 1, occ * cus);
+    }
+    (void)hipGetLastError();
     *out = b;
     return GRMHD_OK;
 }
@@ -320,20 +403,42 @@ int grmhd_batch_tune(grmhd_batch* b, const double* U, int trial_steps, int* thre
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return GRMHD_ERR_HIP;
+    // The trial records: every problem keeps its step count so far and gets a
+    // share of trial_steps in proportion to the steps it has left, so that
+    // the problems' work in a trial is in the same proportion as in the run
+    // (a shape that balances uneven problems is judged on uneven problems).
+    std::vector<BatchProb> tp(b->nprob);
+    if (hipMemcpyAsync(tp.data(), at<BatchProb>(b, b->L.off_probs), sizeof(BatchProb) * b->nprob,
+                       hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return GRMHD_ERR_HIP;
+    }
+    int left_max = 0;
+    for (const BatchProb& p : tp)
+        left_max = std::max(left_max, p.steps - p.done);
+    for (BatchProb& p : tp) {
+        const int left = p.steps - p.done;
+        const int share = left_max > 0 ? (int)std::ceil((double)left * trial_steps / left_max) : 0;
+        p.steps = p.done + std::min(left, share);
+    }
     const int keep_shape = b->shape, keep_lds = b->lds;
     float best = -1.0f;
     int best_shape = keep_shape, best_lds = keep_lds, rc = GRMHD_OK;
-    for (int l = 0; l <= 1 && rc == GRMHD_OK; ++l) {
-        if (l == 1 && !b->lds_ok)
-            break;
+    for (int l = PLACE_HBM; l <= PLACE_SPLIT && rc == GRMHD_OK; ++l) {
+        if ((l == PLACE_LDS && !b->lds_ok) || (l == PLACE_SPLIT && b->parts.empty()))
+            continue;
         for (int s = 0; s < grmhd::BATCH_SHAPES && rc == GRMHD_OK; ++s) {
+            if (l == PLACE_SPLIT && grmhd::BATCH_THREADS[s] != grmhd::BATCH_SPLIT_THREADS)
+                continue;
             // fresh copies of the state for every candidate
             if (hipMemcpyAsync(Ut, U, sizeof(double) * 9 * b->L.ncell, hipMemcpyDeviceToDevice, b->stream) !=
                     hipSuccess ||
                 hipMemcpyAsync(b->ws + b->L.off_prow_t, b->ws + b->L.off_prow, es * b->L.nrow,
                                hipMemcpyDeviceToDevice, b->stream) != hipSuccess ||
-                hipMemcpyAsync(b->ws + b->L.off_probs_t, b->ws + b->L.off_probs, sizeof(BatchProb) * b->nprob,
-                               hipMemcpyDeviceToDevice, b->stream) != hipSuccess) {
+                hipMemcpyAsync(b->ws + b->L.off_probs_t, tp.data(), sizeof(BatchProb) * b->nprob,
+                               hipMemcpyHostToDevice, b->stream) != hipSuccess) {
                 rc = GRMHD_ERR_HIP;
                 break;
             }
@@ -343,9 +448,9 @@ int grmhd_batch_tune(grmhd_batch* b, const double* U, int trial_steps, int* thre
                 rc = GRMHD_ERR_HIP;
                 break;
             }
-            rc = evolve(b, Ut, trial_steps, b->L.off_probs_t, b->L.off_prow_t);
+            rc = evolve(b, Ut, INT_MAX, b->L.off_probs_t, b->L.off_prow_t);
             if (rc) {
-                if (l == 1) {        // an LDS size the runtime refuses: not a candidate
+                if (l == PLACE_LDS) {   // an LDS size the runtime refuses: not a candidate
                     (void)hipGetLastError();
                     rc = GRMHD_OK;
                     continue;
@@ -384,10 +489,12 @@ int grmhd_batch_set_shape(grmhd_batch* b, int threads, int lds)
     for (int s = 0; s < grmhd::BATCH_SHAPES; ++s)
         if (grmhd::BATCH_THREADS[s] == threads)
             shape = s;
-    if (shape < 0 || (lds && !b->lds_ok))
+    if (shape < 0 || lds < PLACE_HBM || lds > PLACE_SPLIT || (lds == PLACE_LDS && !b->lds_ok))
+        return GRMHD_ERR_ARG;
+    if (lds == PLACE_SPLIT && (b->parts.empty() || threads != grmhd::BATCH_SPLIT_THREADS))
         return GRMHD_ERR_ARG;
     b->shape = shape;
-    b->lds = lds ? 1 : 0;
+    b->lds = lds;
     return GRMHD_OK;
 }
 
@@ -413,11 +520,12 @@ int grmhd_batch_status(grmhd_batch* b, grmhd_stats* st, int reset)
     st->p_floor_hits = (long long)h[grmhd::CNT_PFLOOR];
     st->fallback_1d = (long long)h[grmhd::CNT_FALLBACK];
     st->max_newton_it = (int)h[grmhd::CNT_MAXIT];
+    const bool stalled = h[grmhd::CNT_STALL] != 0;
     if (reset && b->uploaded) {
         if (grmhd::launch_zero_counters(b->cnt, b->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
     }
-    return GRMHD_OK;
+    return stalled ? GRMHD_ERR_STATE : GRMHD_OK;
 }
 
 int grmhd_batch_free(grmhd_batch* b)

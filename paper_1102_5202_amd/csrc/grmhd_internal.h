@@ -74,6 +74,18 @@ struct BatchProb {
 static constexpr int BATCH_SHAPES = 3;
 static constexpr int BATCH_THREADS[BATCH_SHAPES] = {256, 512, 1024};
 
+// A problem split among several workgroups ("parts") that run at the same
+// time: part p owns the cells [c0, c1) of problem b; left and right are the
+// parts holding the cells beside c0 and c1 (-1 at the problem's ends); the
+// problem's parts are [first, first + count).
+struct BatchPart {
+    int b, c0, c1, left, right, first, count, pad;
+};
+static constexpr int BATCH_SPLIT_THREADS = 256;
+// Word of the counter block set when a part of a split launch stopped waiting
+// for a neighbour (the parts were not all resident at once).
+enum { CNT_STALL = 5 };
+
 template <typename T>
 hipError_t launch_batch_cons(const BatchProb* probs, int nprob, long long ncell, const double* P, double* U,
                              T* Prow, const Dev& d, hipStream_t s);
@@ -87,6 +99,16 @@ hipError_t launch_batch_prim(const BatchProb* probs, int nprob, long long ncell,
 // not a stream operation, so never called while a step may be captured).
 template <typename T>
 hipError_t allow_batch_lds(size_t bytes);
+
+// The split launch: parts[nparts] as above, flags[nparts] the substeps each
+// part has completed (kept across launches, consistent with probs[].done).
+template <typename T>
+hipError_t launch_batch_split(BatchProb* probs, const BatchPart* parts, int nparts, int* flags, double* U, T* Us,
+                              T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps, unsigned long long* cnt,
+                              hipStream_t s);
+// Resident workgroups of the split launch per CU (0 if unknown).
+template <typename T>
+int batch_split_occupancy();
 
 template <typename T>
 hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,

@@ -1189,6 +1189,211 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
     count_sums(cnt, nfail, natm, npf, nfb, itmax);
 }
 
+// k_batch_split: a problem's cells divided among several workgroups (parts)
+// that run at the same time, each part marching its segment as
+// k_batch_evolve does with the rows in HBM.  The two cells beside a
+// segment's ends come from the neighbouring parts through the rows.  Parts
+// may sit on different XCDs, whose L2 caches are not kept coherent for this
+// memory, so the values that cross parts (each segment's two end cells at
+// either end and their ghost images) are stored and loaded with system-scope
+// accesses, which bypass the non-coherent caches, while the rest of the row
+// stays cached: after a substep the threads that wrote such values wait for
+// their stores, and one thread publishes the part's count of completed
+// substeps in flags; before the next substep one thread waits until both
+// neighbours have completed the current one (which also tells them this part
+// no longer reads the row they are about to overwrite).  Waits are bounded:
+// past the limit the part counts a stall (CNT_STALL) and stops instead of
+// hanging, so that a launch whose parts are not all resident ends.
+static constexpr int SPLIT_SPIN = 1 << 22;   // polls of the flags before a part gives up
+
+template <typename T>
+__device__ __forceinline__ T sys_load(const T* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Thread 0 polls until the flags of parts l and r (-1: none) reach target;
+// the result is shared through LDS.  Returns false on a stall.
+__device__ __forceinline__ bool split_wait(int* flags, int l, int r, int target, int* s_ok)
+{
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        for (int it = 0;; ++it) {
+            const int fl = l >= 0 ? sys_load(&flags[l]) : target;
+            const int fr = r >= 0 ? sys_load(&flags[r]) : target;
+            if (fl >= target && fr >= target)
+                break;
+            if (it >= SPLIT_SPIN) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// row_store with system-scope stores (values other parts read).
+template <typename T>
+__device__ __forceinline__ void row_store_sys(T* __restrict__ row, int pitch, int n, int bc, int c, const double* p)
+{
+#pragma unroll
+    for (int v = 0; v < 9; ++v)
+        __hip_atomic_store(&row[v * pitch + c + 2], (T)p[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    int o[2], no = 0;
+    if (bc == 0) {
+        if (c < 2)
+            o[no++] = c + n;
+        if (c >= n - 2)
+            o[no++] = c - n;
+    } else if (c == 0) {
+        o[no++] = -1;
+        o[no++] = -2;
+    } else if (c == n - 1) {
+        o[no++] = n;
+        o[no++] = n + 1;
+    }
+    for (int e = 0; e < no; ++e)
+#pragma unroll
+        for (int v = 0; v < 9; ++v)
+            __hip_atomic_store(&row[v * pitch + o[e] + 2], (T)p[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_batch_split(BatchProb* __restrict__ probs, const BatchPart* __restrict__ parts,
+                                                    int* flags, double* __restrict__ U, T* __restrict__ Us,
+                                                    T* Prow, T* Pnext, Dev d, int ns, int max_steps,
+                                                    unsigned long long* __restrict__ cnt)
+{
+    __shared__ int s_ok;
+    const int part = blockIdx.x;
+    const BatchPart pt = parts[part];
+    const BatchProb pr = probs[pt.b];
+    const int n = pr.n, pitch = n + 4;
+    const int nsteps = min(max_steps, pr.steps - pr.done);
+    const int base = pr.done * ns;   // substeps every part of the problem had completed
+    const int nsub = nsteps * ns;
+    const int ch = (pt.c1 - pt.c0 + NT - 1) / NT;
+    const int c0 = min(pt.c0 + (int)threadIdx.x * ch, pt.c1), c1 = min(c0 + ch, pt.c1);
+    // cells within two of either end of the segment (and those beyond it,
+    // the neighbours' and the ghost images) are written and read with
+    // system-scope accesses; the rest of the row with plain ones
+    auto edge = [&](int x) { return x < pt.c0 + 2 || x >= pt.c1 - 2; };
+    auto rd = [&](const T* r, int x) { return edge(x) ? sys_load(r + x + 2) : r[x + 2]; };
+    const bool edge_thread = c0 < c1 && (edge(c0) || edge(c1 - 1));
+    double* Ub = U + 9 * pr.off;
+    T* Usb = Us + 9 * pr.off;
+    T* cur = Prow + pr.poff;
+    T* nxt = Pnext + pr.poff;
+    const Geo geo = geo_at<FLAT>(d, 0.0, 0.0, 0.0);
+    const T half = T(0.5);
+    int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
+    bool stalled = false;
+    for (int i = 0; i < nsub && !stalled; ++i) {
+        if (i > 0 && !split_wait(flags, pt.left, pt.right, base + i, &s_ok)) {
+            stalled = true;
+            break;
+        }
+        const int s = i % ns;
+        const double a = ns == 3 ? (s == 0 ? 0.0 : (s == 1 ? 0.75 : 1.0 / 3.0)) : (s == 0 ? 0.0 : 0.5);
+        const double bb = ns == 3 ? (s == 0 ? 1.0 : (s == 1 ? 0.25 : 2.0 / 3.0)) : (s == 0 ? 1.0 : 0.5);
+        T Fp[9];
+        if (c0 < c1) {
+            // face c0 - 1/2 from cells c0-2 .. c0+1 (row index + 2); the first
+            // thread's two cells before c0 belong to the left neighbour
+            T qL[9], qR[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                const T* r = cur + v * pitch;
+                const T q0 = rd(r, c0 - 2), q1 = rd(r, c0 - 1), q2 = rd(r, c0), q3 = rd(r, c0 + 1);
+                qL[v] = q1 + half * mc_slope(q0, q1, q2);
+                qR[v] = q2 - half * mc_slope(q1, q2, q3);
+            }
+            face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fp);
+        }
+        for (int c = c0; c < c1; ++c) {
+            T qL[9], qR[9], Fc[9], q[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                const T* r = cur + v * pitch;              // cells c-1 .. c+2
+                const T q0 = rd(r, c - 1), q1 = rd(r, c), q2 = rd(r, c + 1), q3 = rd(r, c + 2);
+                q[v] = q1;
+                qL[v] = q1 + half * mc_slope(q0, q1, q2);
+                qR[v] = q2 - half * mc_slope(q1, q2, q3);
+            }
+            face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
+            double R[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                R[v] = -((double)Fc[v] - (double)Fp[v]) * pr.idx;
+                Fp[v] = Fc[v];
+            }
+            R[8] -= d.kappa * (double)q[8];
+            double u[9], qg[9], p[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                const double un = Ub[(long long)v * n + c];
+                const double us = s == 0 ? un : (double)Usb[(long long)v * n + c];
+                u[v] = us + a * (un - us) + bb * (pr.dt * R[v]);
+                qg[v] = (double)q[v];
+            }
+            int iters = 0;
+            const int fl = recover_cell(d, geo, u, qg, p, iters);
+            tally(fl, iters, nfail, natm, npf, nfb, itmax);
+            if (s == ns - 1) {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    Ub[(long long)v * n + c] = u[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    Usb[(long long)v * n + c] = (T)u[v];
+            }
+            if (edge(c))
+                row_store_sys(nxt, pitch, n, d.bc[0], c, p);
+            else
+                row_store(nxt, pitch, n, d.bc[0], c, p);
+        }
+        // publish: the values other parts read have reached memory, then the count
+        if (edge_thread)
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&flags[part], base + i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        T* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (!stalled && (nsub & 1)) {
+        // the row ended in Pnext: once the neighbours no longer read Prow (they
+        // completed every substep), copy the own cells and their ghost images
+        if (!split_wait(flags, pt.left, pt.right, base + nsub, &s_ok))
+            stalled = true;
+        else {
+            for (int c = c0; c < c1; ++c) {
+                double p[9];
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    p[v] = (double)rd(cur + v * pitch, c);
+                row_store(Prow + pr.poff, pitch, n, d.bc[0], c, p);
+            }
+        }
+    }
+    // the problem's first part records the steps once every part has taken them
+    if (!stalled && part == pt.first) {
+        for (int q = 0; q < pt.count && !stalled; ++q)
+            if (!split_wait(flags, pt.first + q, -1, base + nsub, &s_ok))
+                stalled = true;
+        if (!stalled && threadIdx.x == 0)
+            probs[pt.b].done = pr.done + nsteps;
+    }
+    if (stalled && threadIdx.x == 0)
+        atomicAdd(&cnt[(size_t)(blockIdx.x % CNT_SLOTS) * CNT_WORDS + CNT_STALL], 1ull);
+    count_sums(cnt, nfail, natm, npf, nfb, itmax);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (T = double or float)
 
@@ -1528,6 +1733,42 @@ hipError_t allow_batch_lds(size_t bytes)
     return hipSuccess;
 }
 
+// Before a split launch: every part's flag at the substeps its problem has
+// completed, so that the flags agree with the records whatever ran before
+// (another launch shape, a tuning run on copies, a reset).
+__global__ __launch_bounds__(BLOCK) void k_split_flags(const BatchProb* __restrict__ probs,
+                                                       const BatchPart* __restrict__ parts, int nparts,
+                                                       int* __restrict__ flags, int ns)
+{
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p < nparts)
+        flags[p] = probs[parts[p].b].done * ns;
+}
+
+template <typename T>
+hipError_t launch_batch_split(BatchProb* probs, const BatchPart* parts, int nparts, int* flags, double* U, T* Us,
+                              T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps, unsigned long long* cnt,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_split_flags, dim3(blocks_for(nparts)), dim3(BLOCK), 0, s, probs, parts, nparts, flags,
+                       rk_order);
+    hipLaunchKernelGGL((k_batch_split<T, BATCH_SPLIT_THREADS>), dim3(nparts), dim3(BATCH_SPLIT_THREADS), 0, s, probs,
+                       parts, flags, U, Us, Prow, Pnext, d, rk_order, max_steps, cnt);
+    return hipGetLastError();
+}
+
+template <typename T>
+int batch_split_occupancy()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_split<T, BATCH_SPLIT_THREADS>,
+                                                     BATCH_SPLIT_THREADS, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
 template <typename T>
 hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
                                double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps,
@@ -1561,6 +1802,9 @@ hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* 
     template hipError_t launch_batch_prim<T>(const BatchProb*, int, long long, const double*, double*, T*,     \
                                              const Dev&, unsigned long long*, hipStream_t);                   \
     template hipError_t allow_batch_lds<T>(size_t);                                                           \
+    template hipError_t launch_batch_split<T>(BatchProb*, const BatchPart*, int, int*, double*, T*, T*, T*,     \
+                                              const Dev&, int, int, unsigned long long*, hipStream_t);         \
+    template int batch_split_occupancy<T>();                                                                  \
     template hipError_t launch_batch_evolve<T>(int, int, size_t, BatchProb*, const int*, int, double*, T*, T*, \
                                                T*, const Dev&, int, int, unsigned long long*, hipStream_t);
 GRMHD_INSTANTIATE_BATCH(double)

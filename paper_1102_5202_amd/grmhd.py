@@ -415,16 +415,19 @@ class BatchSolver:
 
     def tune(self, U: torch.Tensor, trial_steps: int = 20):
         """Pick the fastest launch shape on copies of the state; returns
-        (threads per workgroup, primitive rows in LDS)."""
+        (threads per workgroup, placement): placement 0 one workgroup per
+        problem with the rows in HBM, 1 the same with the rows in LDS, 2 the
+        problems split among workgroups in proportion to their work."""
         th, lds = C.c_int(), C.c_int()
         _check(load().grmhd_batch_tune(self._ctx, C.c_void_p(self._t(U, "U")), int(trial_steps),
                                        C.byref(th), C.byref(lds)), "grmhd_batch_tune")
-        return th.value, bool(lds.value)
+        return th.value, lds.value
 
-    def set_shape(self, threads: int, lds: bool) -> None:
+    def set_shape(self, threads: int, lds) -> None:
         """Launch shape of evolve: threads per workgroup (256, 512, 1024) and
-        primitive rows in LDS."""
-        _check(load().grmhd_batch_set_shape(self._ctx, int(threads), int(bool(lds))), "grmhd_batch_set_shape")
+        the placement (0 / False: rows in HBM, 1 / True: rows in LDS, 2: split
+        problems, with 256 threads)."""
+        _check(load().grmhd_batch_set_shape(self._ctx, int(threads), int(lds)), "grmhd_batch_set_shape")
 
     def status(self, reset: bool = False) -> dict:
         st = Stats()

@@ -305,6 +305,10 @@ def test_batch_workspace_and_init_validation(lib):
     import torch
     have_gpu = torch.cuda.device_count() > 0
     assert L.grmhd_batch_set_shape(ctx, 1024, 1) == (0 if have_gpu else -1)
+    # the split placement: 256 threads only, sized for the device at init
+    assert L.grmhd_batch_set_shape(ctx, 512, 2) == -1
+    assert L.grmhd_batch_set_shape(ctx, 256, 2) == (0 if have_gpu else -1)
+    assert L.grmhd_batch_set_shape(ctx, 256, 3) == -1
     assert L.grmhd_batch_free(ctx) == 0
     o.workspace_bytes = nb - 8
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == -2

@@ -80,8 +80,8 @@ def test_batch_chunked_equals_one_shot_and_shapes_agree(G):
         if ref is None:
             ref = out
         assert np.array_equal(out, ref)
-    for th in (256, 512, 1024):
-        for lds in (False, True):
+    for th, lds in [(t, l) for t in (256, 512, 1024) for l in (0, 1)] + [(256, 2)]:
+        if True:
             s = G.batch_for(e, device=DEV)
             s.set_shape(th, lds)
             U = s.cons(s.pack(e.P))
@@ -97,18 +97,19 @@ def test_batch_chunked_equals_one_shot_and_shapes_agree(G):
     say("tuned shape", th, lds)
 
 
-@pytest.mark.parametrize("precision,lds", [("fp64", False), ("fp64", True), ("mixed", True)])
+@pytest.mark.parametrize("precision,lds", [("fp64", 0), ("fp64", 1), ("mixed", 1), ("fp64", 2), ("mixed", 2)])
 def test_batch_graph_replay_matches_eager(G, precision, lds):
-    """One persistent launch of a chunk of steps captured in a HIP graph and
-    replayed several times (eager work and synchronisation between the
-    replays) equals the same chunks run eagerly, bitwise, with the rows in
-    HBM and in LDS."""
+    """One persistent launch of a chunk of steps (for split problems, the
+    flag set-up and the launch) captured in a HIP graph and replayed several
+    times (eager work and synchronisation between the replays) equals the same
+    chunks run eagerly, bitwise, with the rows in HBM, in LDS and split."""
     e = WL.config5(nprob=7, nmin=40, nmax=260, k=3)
+    th = 256 if lds == 2 else 512
     se = G.batch_for(e, device=DEV, precision=precision)
-    se.set_shape(512, lds)
+    se.set_shape(th, lds)
     Ue = se.cons(se.pack(e.P))
     sg = G.batch_for(e, device=DEV, precision=precision)
-    sg.set_shape(512, lds)
+    sg.set_shape(th, lds)
     Ug = sg.cons(sg.pack(e.P))
     torch.cuda.synchronize()
     chunk = 11
