@@ -408,6 +408,14 @@ int grmhd_timing(grmhd_ctx *ctx, double *ms, long long *launches, int reset);
 /* Release the context (host memory and HIP events only). */
 int grmhd_free(grmhd_ctx *ctx);
 
+/* For callers that check the library's compiled device arithmetic: on the
+ * device arrays x, y (n doubles each), out[0..n) = x / y, out[n..2n) =
+ * sqrt(x), out[2n..3n) = 1 / sqrt(x), evaluated as the kernels evaluate these
+ * operations (FP64 division as a Newton-refined reciprocal times the
+ * numerator; see the build flags), to be compared with correctly rounded
+ * results.  out (3n doubles) is written, asynchronously on stream. */
+int grmhd_device_arith(const double *x, const double *y, double *out, long long n, void *stream);
+
 /* Static description of an error code. */
 const char *grmhd_strerror(int code);
 

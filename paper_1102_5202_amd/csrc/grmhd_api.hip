@@ -1096,6 +1096,13 @@ int grmhd_free(grmhd_ctx* c)
     return GRMHD_OK;
 }
 
+int grmhd_device_arith(const double* x, const double* y, double* out, long long n, void* stream)
+{
+    if (!x || !y || !out || n < 0 || n > (1LL << 38))
+        return GRMHD_ERR_ARG;
+    return grmhd::launch_arith(x, y, out, n, (hipStream_t)stream) == hipSuccess ? GRMHD_OK : GRMHD_ERR_HIP;
+}
+
 const char* grmhd_strerror(int code)
 {
     switch (code) {

@@ -21,6 +21,7 @@ static constexpr size_t CNT_BYTES = sizeof(unsigned long long) * CNT_WORDS * CNT
 template <typename T>
 hipError_t launch_fill(T* p, long long n, double v, hipStream_t s);
 hipError_t launch_zero_counters(unsigned long long* cnt, hipStream_t s);
+hipError_t launch_arith(const double* x, const double* y, double* out, long long n, hipStream_t s);
 template <typename T>
 hipError_t launch_ghosts(T* Pc, const Dev& d, hipStream_t s);
 template <typename T>

@@ -1394,12 +1394,33 @@ __global__ __launch_bounds__(NT) void k_batch_split(BatchProb* __restrict__ prob
     count_sums(cnt, nfail, natm, npf, nfb, itmax);
 }
 
+// The device arithmetic the kernels use, on arrays, for checking it against
+// correctly rounded results: x / y, sqrt(x), rsqrt(x) (FP64).
+__global__ __launch_bounds__(BLOCK) void k_arith(const double* __restrict__ x, const double* __restrict__ y,
+                                                double* __restrict__ out, long long n)
+{
+    const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= n)
+        return;
+    const double a = x[t], b = y[t];
+    out[t] = a / b;
+    out[n + t] = sqrt(a);
+    out[2 * n + t] = rsqrt(a);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (T = double or float)
 
 static inline unsigned blocks_for(long long n)
 {
     return (unsigned)((n + BLOCK - 1) / BLOCK);
+}
+
+hipError_t launch_arith(const double* x, const double* y, double* out, long long n, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_arith, dim3(blocks_for(n)), dim3(BLOCK), 0, s, x, y, out, n);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -34,7 +34,8 @@ SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_con
            "grmhd_prim_adjoint", "grmhd_status", "grmhd_timing", "grmhd_free", "grmhd_strerror",
            "grmhd_batch_workspace_bytes", "grmhd_batch_init", "grmhd_batch_set_stream",
            "grmhd_batch_cons", "grmhd_batch_evolve", "grmhd_batch_prim", "grmhd_batch_tune",
-           "grmhd_batch_set_shape", "grmhd_batch_status", "grmhd_batch_free", "grmhd_rhs_noalloc")
+           "grmhd_batch_set_shape", "grmhd_batch_status", "grmhd_batch_free", "grmhd_rhs_noalloc",
+           "grmhd_device_arith")
 
 
 class Metric(C.Structure):
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH):
     L.grmhd_batch_free.argtypes = [vp]
     L.grmhd_rhs_noalloc.argtypes = [C.POINTER(Metric), C.POINTER(Grid), C.POINTER(Eos), C.POINTER(Opts), vp, vp,
                                     vp]
+    L.grmhd_device_arith.argtypes = [vp, vp, vp, C.c_longlong, vp]
     L.grmhd_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.c_int]
     L.grmhd_free.argtypes = [vp]
     L.grmhd_strerror.argtypes = [C.c_int]
@@ -454,6 +456,20 @@ def batch_for(ensemble, **over) -> BatchSolver:
               rho_atm=ensemble.rho_atm, p_atm=ensemble.p_atm)
     kw.update(over)
     return BatchSolver(**kw)
+
+
+def device_arith(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """grmhd_device_arith: (x / y, sqrt(x), 1 / sqrt(x)) as the kernels compute
+    them, for float64 1D tensors on a GPU; returns a (3, n) tensor."""
+    if x.dtype != torch.float64 or y.dtype != torch.float64 or x.shape != y.shape or x.dim() != 1:
+        raise ValueError("x and y must be float64 1D tensors of one shape")
+    x, y = x.contiguous(), y.contiguous()
+    out = torch.empty((3, x.numel()), dtype=torch.float64, device=x.device)
+    st = torch.cuda.current_stream(x.device)
+    _check(load().grmhd_device_arith(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     C.c_void_p(out.data_ptr()), x.numel(), C.c_void_p(st.cuda_stream)),
+           "grmhd_device_arith")
+    return out
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20
