@@ -67,8 +67,13 @@ def reference(orc, w, nsteps, key):
     if key not in _cache:
         pb = orc.Problem(**w.problem_kwargs())
         say("oracle: %s, %d steps on %d threads ..." % (w.name, nsteps, orc.get_threads()))
-        U, _, st = orc.step(pb, orc.prim2con(pb, w.P), w.P, w.dt, nsteps)
-        say("oracle done", st)
+        U, P = orc.prim2con(pb, w.P), w.P
+        done = 0
+        while done < nsteps:          # in chunks, reporting progress
+            k = min(10, nsteps - done)
+            U, P, st = orc.step(pb, U, P, w.dt, k)
+            done += k
+            say("oracle %s: %d of %d steps" % (key, done, nsteps), st)
         _cache[key] = U
     return _cache[key]
 
