@@ -642,15 +642,21 @@ __device__ __forceinline__ void tile_face(const T* sP, int dir, int base, int st
 }
 
 template <int KIND, int TX, int TY, int SEG, bool NT, typename T, typename TS, typename TO>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_substep(const T* __restrict__ Pc, T* __restrict__ Pn,
-                                                    const double* Un, const TS* Us, TO* Uout, Dev d, double dt,
-                                                    double a, double b, unsigned long long* __restrict__ cnt,
-                                                    unsigned char* __restrict__ fout, int ntx, int ntiles)
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_substep(
+    const T* __restrict__ Pc, T* __restrict__ Pn, const double* Un, const TS* Us, TO* Uout, Dev d, double dt,
+    double a, double b, unsigned long long* __restrict__ cnt, unsigned char* __restrict__ fout, int ntx, int ntiles)
 {
     using G = Tile<TX, TY>;
-    __shared__ T sP[9 * G::PLANE];
-    __shared__ T sFx[9 * G::NFX];
-    __shared__ T sFy[9 * G::NFY];
+    // With a float cache the staged planes and the face fluxes are double
+    // buffered (70.8 KB of LDS, still two workgroups per CU): the faces of
+    // plane k + 1 and the update of plane k then share one barrier interval.
+    // With a double cache that would take 141.7 KB, one workgroup per CU, so
+    // each plane has its staging, faces and update between two barriers.
+    constexpr bool DB = sizeof(T) < sizeof(double);
+    constexpr int NB = DB ? 2 : 1;
+    __shared__ T sP[NB][9 * G::PLANE];
+    __shared__ T sFx[NB][9 * G::NFX];
+    __shared__ T sFy[NB][9 * G::NFY];
 
     const int t = threadIdx.x;
     const int tx = t % TX, ty = t / TX;
@@ -678,27 +684,25 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // face near the domain's edge reads (ragged tiles); -1: none.
     int hslot = -1;
     long long hoff = 0;
-    {
-        int hx = tx, hy = ty;
-        bool need = false;
-        if (t < G::NH) {
-            if (t < 2 * TX) {
-                hx = t % TX;
-                hy = -2 + t / TX;
-            } else if (t < 4 * TX) {
-                hx = (t - 2 * TX) % TX;
-                hy = TY + (t - 2 * TX) / TX;
-            } else if (t < 4 * TX + 2 * TY) {
-                hx = -2 + (t - 4 * TX) % 2;
-                hy = (t - 4 * TX) / 2;
-            } else {
-                hx = TX + (t - 4 * TX - 2 * TY) % 2;
-                hy = (t - 4 * TX - 2 * TY) / 2;
-            }
-            const int gi = i0 + hx, gj = j0 + hy;
-            // rows below/above: an interior column; columns left/right: an interior row
-            need = (hy < 0 || hy >= TY) ? (ay && gi < nx && gj < ny + 2) : (ax && gj < ny && gi < nx + 2);
+    if (t < G::NH) {
+        int hx, hy;
+        if (t < 2 * TX) {
+            hx = t % TX;
+            hy = -2 + t / TX;
+        } else if (t < 4 * TX) {
+            hx = (t - 2 * TX) % TX;
+            hy = TY + (t - 2 * TX) / TX;
+        } else if (t < 4 * TX + 2 * TY) {
+            hx = -2 + (t - 4 * TX) % 2;
+            hy = (t - 4 * TX) / 2;
+        } else {
+            hx = TX + (t - 4 * TX - 2 * TY) % 2;
+            hy = (t - 4 * TX - 2 * TY) / 2;
         }
+        const int gi = i0 + hx, gj = j0 + hy;
+        // rows below/above: an interior column; columns left/right: an interior row
+        const bool need =
+            (hy < 0 || hy >= TY) ? (ay && gi < nx && gj < ny + 2) : (ax && gj < ny && gi < nx + 2);
         if (need) {
             hslot = (hy + 2) * G::W + hx + 2;
             hoff = (long long)(j0 + hy + d.g[1]) * d.px + i0 + hx + d.g[0] + (long long)d.g[2] * st;
@@ -735,50 +739,43 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
                            i + (long long)nx * (j + (long long)ny * k0), d, Fp);
     }
 
-    // with a float cache the halo cell of the plane to stage next is loaded
-    // one plane ahead (during the recovery of the plane before), so that
-    // staging waits for nothing (6 % on a mixed substep); a double cache has
-    // no registers to spare for it
-    constexpr bool pre = sizeof(T) < sizeof(double);
+    // Staging of plane k into buffer pb: the own cell (own: its value from the
+    // window) and the halo cell (hv: loaded ahead with a float cache).
     T hv[9];
-    if (pre && hslot >= 0) {
+    auto halo_load = [&](int k) {
+        if (hslot >= 0) {
 #pragma unroll
-        for (int v = 0; v < 9; ++v)
-            hv[v] = Pc[v * d.sv + hoff + (long long)k0 * st];
-    }
-    for (int k = k0; k < k1; ++k) {
-        // (1) the new cell k+2 of the window (used in (3)), the staged plane
-        T qd[9];
+            for (int v = 0; v < 9; ++v)
+                hv[v] = Pc[v * d.sv + hoff + (long long)k * st];
+        }
+    };
+    auto stage = [&](int k, int pb, const T* own, bool hv_loaded) {
+        T* P = sP[pb];
         if (act) {
 #pragma unroll
             for (int v = 0; v < 9; ++v)
-                qd[v] = Pc[v * d.sv + col + (long long)(k + 2) * st];
-#pragma unroll
-            for (int v = 0; v < 9; ++v)
-                sP[v * G::PLANE + oslot] = qb[v];
+                P[v * G::PLANE + oslot] = own[v];
         } else if (own_ghost) {
             const long long o = col + (long long)k * st;
 #pragma unroll
             for (int v = 0; v < 9; ++v)
-                sP[v * G::PLANE + oslot] = Pc[v * d.sv + o];
+                P[v * G::PLANE + oslot] = Pc[v * d.sv + o];
         }
-        if (pre && hslot >= 0) {
+        if (hslot >= 0) {
+            if (!hv_loaded)
+                halo_load(k);
 #pragma unroll
             for (int v = 0; v < 9; ++v)
-                sP[v * G::PLANE + hslot] = hv[v];
-        } else if (hslot >= 0) {
-            const long long o = hoff + (long long)k * st;
-#pragma unroll
-            for (int v = 0; v < 9; ++v)
-                sP[v * G::PLANE + hslot] = Pc[v * d.sv + o];
+                P[v * G::PLANE + hslot] = hv[v];
         }
-        __syncthreads();
+    };
 
-        // (2) the faces of the plane: every thread the x face left of its
-        // cell and the y face below it; the last wave, which stages no halo
-        // cells, also the tile's last face of each row and column.  One face
-        // solver serves both axes (a loop, not unrolled, keeps one copy of
-        // its code).
+    // The faces of plane k from staged buffer pb into face buffer fb: every
+    // thread the x face left of its cell and the y face below it; the last
+    // wave, which stages no halo cells, also the tile's last face of each
+    // row and column.  One face solver serves both axes (a loop, not
+    // unrolled, keeps one copy of its code).
+    auto faces = [&](int k, int pb, int fb) {
         const double zc = d.lo[2] + (k + 0.5) * d.dx[2];
         const int ntask = t >= G::NT - 64 ? 3 : 2;
 #pragma nounroll
@@ -799,67 +796,103 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
             const double fy = d.lo[1] + (dir == 0 ? fj + 0.5 : fj) * d.dx[1];
             const long long fglob = dir == 0 ? fi + (long long)(nx + 1) * (fj + (long long)ny * k)
                                              : fi + (long long)nx * (fj + (long long)(ny + 1) * k);
-            tile_face<KIND, G::PLANE>(sP, dir, dir == 0 ? (ys + 2) * G::W + xs : ys * G::W + xs + 2,
-                                      dir == 0 ? 1 : G::W, fx, fy, zc, fglob, d, dir == 0 ? sFx : sFy,
+            tile_face<KIND, G::PLANE>(sP[pb], dir, dir == 0 ? (ys + 2) * G::W + xs : ys * G::W + xs + 2,
+                                      dir == 0 ? 1 : G::W, fx, fy, zc, fglob, d, dir == 0 ? sFx[fb] : sFy[fb],
                                       dir == 0 ? G::NFX : G::NFY, dir == 0 ? ys * (TX + 1) + xs : ys * TX + xs);
         }
-        __syncthreads();
+    };
 
-        // (3) the cell update; the stage inputs are loaded first, so that the
-        // z face's arithmetic covers their latency
-        if (act) {
-            const long long c = i + (long long)nx * (j + (long long)ny * k);
-            double un[9], us[9];
-            constexpr bool early = sizeof(T) < sizeof(double);
-            if constexpr (early)
-                stage_load<NT>(d, Un, Us, c, un, us);
-            T q[9], qL[9], qR[9], Fc[9];
+    // The update of plane k (x and y fluxes in face buffer fb): the z face
+    // above the cell from the window (which moves up one plane), the flux
+    // differences, sources, RK combination and recovery.  With a float
+    // cache the stage inputs are loaded first, so that the z face covers
+    // their latency, and the halo cell of plane kh is loaded before the
+    // recovery; a double cache has no registers to spare for either.
+    auto update = [&](int k, int fb, int kh) {
+        constexpr bool early = sizeof(T) < sizeof(double);
+        if (!act) {
+            if (early && kh >= 0)
+                halo_load(kh);
+            return;
+        }
+        const long long c = i + (long long)nx * (j + (long long)ny * k);
+        double un[9], us[9];
+        if constexpr (early)
+            stage_load<NT>(d, Un, Us, c, un, us);
+        T qd[9];
 #pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                T sn = mc_slope(qb[v], qc[v], qd[v]);   // cell k+1
-                q[v] = qb[v];
-                qL[v] = qb[v] + half * sc[v];
-                qR[v] = qc[v] - half * sn;
-                sc[v] = sn;
-                qb[v] = qc[v];
-                qc[v] = qd[v];
-            }
-            face_flux<2, KIND>(qL, qR, x, y, zc + 0.5 * d.dx[2],
-                               i + (long long)nx * (j + (long long)ny * (k + 1)), d, Fc);
-            if constexpr (!early)
-                stage_load<NT>(d, Un, Us, c, un, us);
-            double R[9];
+        for (int v = 0; v < 9; ++v)
+            qd[v] = Pc[v * d.sv + col + (long long)(k + 2) * st];
+        T q[9], qL[9], qR[9], Fc[9];
 #pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                R[v] = -((double)Fc[v] - (double)Fp[v]) * d.idx[2];
-                Fp[v] = Fc[v];
-            }
-            const int fx = ty * (TX + 1) + tx, fy = ty * TX + tx;
-            if (ax) {
+        for (int v = 0; v < 9; ++v) {
+            T sn = mc_slope(qb[v], qc[v], qd[v]);   // cell k+1
+            q[v] = qb[v];
+            qL[v] = qb[v] + half * sc[v];
+            qR[v] = qc[v] - half * sn;
+            sc[v] = sn;
+            qb[v] = qc[v];
+            qc[v] = qd[v];
+        }
+        const double zc = d.lo[2] + (k + 0.5) * d.dx[2];
+        face_flux<2, KIND>(qL, qR, x, y, zc + 0.5 * d.dx[2], i + (long long)nx * (j + (long long)ny * (k + 1)), d,
+                           Fc);
+        if constexpr (!early)
+            stage_load<NT>(d, Un, Us, c, un, us);
+        double R[9];
 #pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    R[v] -= ((double)sFx[v * G::NFX + fx + 1] - (double)sFx[v * G::NFX + fx]) * d.idx[0];
-            }
-            if (ay) {
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    R[v] -= ((double)sFy[v * G::NFY + fy + TX] - (double)sFy[v * G::NFY + fy]) * d.idx[1];
-            }
-            Geo g;
-            add_sources<KIND>(d, x, y, zc, c, q, g, R);
-            if (pre && hslot >= 0 && k + 1 < k1) {
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    hv[v] = Pc[v * d.sv + hoff + (long long)(k + 1) * st];
-            }
-            int iters = 0;
-            const long long pc = col + (long long)k * st;
-            int flags = stage_finish<NT>(d, g, R, q, un, us, Uout, c, Pn, pc, i, j, k, dt, a, b, fout, iters);
-            tally(flags, iters, nfail, natm, npf, nfb, itmax);
-        } else if (pre && hslot >= 0 && k + 1 < k1) {
+        for (int v = 0; v < 9; ++v) {
+            R[v] = -((double)Fc[v] - (double)Fp[v]) * d.idx[2];
+            Fp[v] = Fc[v];
+        }
+        const int fx = ty * (TX + 1) + tx, fy = ty * TX + tx;
+        if (ax) {
 #pragma unroll
             for (int v = 0; v < 9; ++v)
-                hv[v] = Pc[v * d.sv + hoff + (long long)(k + 1) * st];
+                R[v] -= ((double)sFx[fb][v * G::NFX + fx + 1] - (double)sFx[fb][v * G::NFX + fx]) * d.idx[0];
+        }
+        if (ay) {
+#pragma unroll
+            for (int v = 0; v < 9; ++v)
+                R[v] -= ((double)sFy[fb][v * G::NFY + fy + TX] - (double)sFy[fb][v * G::NFY + fy]) * d.idx[1];
+        }
+        Geo g;
+        add_sources<KIND>(d, x, y, zc, c, q, g, R);
+        if (early && kh >= 0)
+            halo_load(kh);
+        int iters = 0;
+        int flags = stage_finish<NT>(d, g, R, q, un, us, Uout, c, Pn, col + (long long)k * st, i, j, k, dt, a, b,
+                                     fout, iters);
+        tally(flags, iters, nfail, natm, npf, nfb, itmax);
+    };
+
+    if constexpr (DB) {
+        // prologue: planes k0 and k0 + 1 staged, the faces of k0 solved
+        stage(k0, 0, qb, false);
+        __syncthreads();
+        faces(k0, 0, 0);
+        if (k0 + 1 < k1)
+            stage(k0 + 1, 1, qc, false);
+        __syncthreads();
+        // plane k: the faces of k + 1, the update of k, the staging of k + 2
+        // (into the buffer plane k used; its own cell is the window's qc once
+        // the update has moved the window up)
+        for (int k = k0; k < k1; ++k) {
+            const int cur = (k - k0) & 1, nxt = cur ^ 1;
+            if (k + 1 < k1)
+                faces(k + 1, nxt, nxt);
+            update(k, cur, k + 2 < k1 ? k + 2 : -1);   // also loads the halo cell of k + 2
+            if (k + 2 < k1)
+                stage(k + 2, cur, qc, true);
+            __syncthreads();
+        }
+    } else {
+        for (int k = k0; k < k1; ++k) {
+            stage(k, 0, qb, false);
+            __syncthreads();
+            faces(k, 0, 0);
+            __syncthreads();
+            update(k, 0, -1);
         }
     }
     count_sums(cnt, nfail, natm, npf, nfb, itmax);
