@@ -14,7 +14,9 @@ created with ``tape_steps >= every`` the recomputation records every step's
 stages (``grmhd_step_record``) and the reverse sweep uses them
 (``grmhd_step_adjoint_recorded``): a gradient costs one forward evolution
 (the recomputation) plus ``nsteps`` reverse sweeps, and the tape holds
-``every`` steps' stages.  Otherwise the recomputation keeps the segment's
+``every`` steps' stages.  The forward pass records the last segment's steps
+itself, so the backward pass reverses them without recomputing them (unless
+the tape was used by another call in between).  Otherwise the recomputation keeps the segment's
 states and each ``grmhd_step_adjoint`` recomputes its step's stages again.
 
 Argument marshalling only: every operation runs in the library's kernels.
@@ -30,13 +32,22 @@ class _Evolve(torch.autograd.Function):
         s = solver
         U = s.cons(P0.detach().contiguous())
         checkpoints = {0: U.clone()}
+        # with a tape, the steps of the last segment (the first one the
+        # backward pass reverses) are recorded now instead of recomputed then
+        last = ((nsteps - 1) // every) * every
+        taped = s.tape_steps >= every
+        token = object()
         for k in range(1, nsteps + 1):
-            s.step(U, dt)
+            if taped and k > last:
+                s.step_record(U, dt, k - 1 - last)
+            else:
+                s.step(U, dt)
             if k % every == 0 and k < nsteps:
                 checkpoints[k] = U.clone()
+        s.tape_owner = token if taped else None
         P = s.prim(U)
         ctx.solver, ctx.dt, ctx.nsteps, ctx.every = s, dt, nsteps, every
-        ctx.checkpoints = checkpoints
+        ctx.checkpoints, ctx.token, ctx.last = checkpoints, token, last
         ctx.save_for_backward(P0, U)
         return P
 
@@ -49,6 +60,12 @@ class _Evolve(torch.autograd.Function):
         taped = s.tape_steps >= every
         for c in reversed(starts):
             stop = min(c + every, nsteps)
+            if taped and c == ctx.last and getattr(s, "tape_owner", None) is ctx.token:
+                # recorded by the forward pass, and the tape not used since
+                for k in range(stop - 1, c - 1, -1):
+                    s.step_adjoint_recorded(k - c, Ubar)
+                continue
+            s.tape_owner = None
             # recompute the segment from its checkpoint
             U = ctx.checkpoints[c].clone()
             if c == 0:

@@ -251,15 +251,25 @@ __device__ __forceinline__ double gather_pos_v(const Dev& d, const double* __res
     const long long f_hp = (i + 2 >= 0 && i + 2 <= n) ? face(i + 2) : -1;   // face i+2
     const double* Fl = FB + v * nf;          // left-state cotangents
     const double* Fr = FB + (9 + v) * nf;    // right-state cotangents
-    const double Fl_hi = has_hi ? Fl[f_hi] : 0.0, Fr_lo = has_lo ? Fr[f_lo] : 0.0;
-    double m = Fl_hi + Fr_lo;
+    // every load issued up front (absent faces read face 0, stencil taps
+    // outside the ghosted line read its last position; neither value is used)
+    const long long g_lm = f_lm >= 0 ? f_lm : 0, g_hp = f_hp >= 0 ? f_hp : 0;
     const double* P = Pc + v * d.sv + pc;
+    auto tap = [&](int o) -> double {
+        const int p = min(max(i + o, -2), n + 1);
+        return P[(long long)(p - i) * st];
+    };
+    const double Fl_lo_v = Fl[f_lo], Fl_hi_v = Fl[f_hi], Fl_hp_v = Fl[g_hp];
+    const double Fr_lo_v = Fr[f_lo], Fr_hi_v = Fr[f_hi], Fr_lm_v = Fr[g_lm];
+    const double qm2 = tap(-2), qm1 = tap(-1), q00 = P[0], qp1 = tap(1), qp2 = tap(2);
+    const double Fl_hi = has_hi ? Fl_hi_v : 0.0, Fr_lo = has_lo ? Fr_lo_v : 0.0;
+    double m = Fl_hi + Fr_lo;
     // j = i - 1 (q_i is its qp), j in [-1, n]
     if (i - 1 >= -1 && i - 1 <= n) {
-        const double sb = 0.5 * ((has_lo ? Fl[f_lo] : 0.0) - (f_lm >= 0 ? Fr[f_lm] : 0.0));
+        const double sb = 0.5 * ((has_lo ? Fl_lo_v : 0.0) - (f_lm >= 0 ? Fr_lm_v : 0.0));
         if (sb != 0.0) {
             double dm, d0, dp;
-            mc_slope_grad(P[-2 * st], P[-st], P[0], dm, d0, dp);
+            mc_slope_grad(qm2, qm1, q00, dm, d0, dp);
             m += sb * dp;
         }
     }
@@ -268,16 +278,16 @@ __device__ __forceinline__ double gather_pos_v(const Dev& d, const double* __res
         const double sb = 0.5 * (Fl_hi - Fr_lo);
         if (sb != 0.0) {
             double dm, d0, dp;
-            mc_slope_grad(P[-st], P[0], P[st], dm, d0, dp);
+            mc_slope_grad(qm1, q00, qp1, dm, d0, dp);
             m += sb * d0;
         }
     }
     // j = i + 1 (q_i is its qm)
     if (i + 1 >= -1 && i + 1 <= n) {
-        const double sb = 0.5 * ((f_hp >= 0 ? Fl[f_hp] : 0.0) - (has_hi ? Fr[f_hi] : 0.0));
+        const double sb = 0.5 * ((f_hp >= 0 ? Fl_hp_v : 0.0) - (has_hi ? Fr_hi_v : 0.0));
         if (sb != 0.0) {
             double dm, d0, dp;
-            mc_slope_grad(P[0], P[st], P[2 * st], dm, d0, dp);
+            mc_slope_grad(q00, qp1, qp2, dm, d0, dp);
             m += sb * dm;
         }
     }

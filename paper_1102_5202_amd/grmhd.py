@@ -207,6 +207,7 @@ class Solver:
                             C.byref(self._eos), C.byref(self._opts)), "grmhd_init")
         self._ctx = ctx
         self.tape_steps = int(tape_steps) if adjoint else 0
+        self.tape_owner = None      # the differentiable evolution whose steps the tape holds
         self.set_stream(stream if stream is not None else torch.cuda.current_stream(self.device))
 
     # -- plumbing ------------------------------------------------------------
@@ -281,6 +282,7 @@ class Solver:
 
     def step_record(self, U: torch.Tensor, dt: float, slot: int) -> torch.Tensor:
         """One step of U in place, as step(), keeping its stages in tape slot `slot`."""
+        self.tape_owner = None
         _check(load().grmhd_step_record(self._ctx, C.c_void_p(self._t(U, "U")), float(dt), int(slot)),
                "grmhd_step_record")
         return U

@@ -296,3 +296,27 @@ def test_autograd_evolve_with_checkpoints(G):
         rel = float((g - g_chain).abs().sum() / g_chain.abs().sum())
         say("evolve gradient vs chain", "taped" if e >= 3 else "untaped", rel)
         assert rel <= 1e-12
+
+
+def test_autograd_evolve_tape_reused_in_between(G):
+    """The forward pass records its last segment on the tape; when another
+    evolution records over that tape before the backward pass, the backward
+    pass recomputes the segment instead: both gradients still equal the plain
+    adjoint chain."""
+    from paper_1102_5202_amd.adjoint import evolve
+    w = WL.config4(n=16, nsteps=5)
+    w.P = _vary_all(w.P)
+    s = G.solver_for(w, device=DEV, adjoint=True)
+    st = G.solver_for(w, device=DEV, adjoint=True, tape_steps=4)
+    tgt = _t(w.extra["target"])
+    L, g_chain = _loss_chain(G, w, s, _t(w.P), tgt, w.nsteps)
+    P0a = _t(w.P).requires_grad_(True)
+    Pa = evolve(st, P0a, w.dt, w.nsteps, 4)
+    P0b = (_t(w.P) * 1.001).requires_grad_(True)
+    Pb = evolve(st, P0b, w.dt, w.nsteps, 4)          # records over a's last segment
+    ((Pa[0] - tgt) ** 2).sum().backward()
+    ((Pb[0] - tgt) ** 2).sum().backward()
+    rel = float((P0a.grad - g_chain).abs().sum() / g_chain.abs().sum())
+    say("tape reused in between: gradient vs chain", rel)
+    assert rel <= 1e-12
+    assert torch.isfinite(P0b.grad).all()
