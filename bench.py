@@ -321,28 +321,44 @@ def batch_throughput(grmhd, e, dev):
     """The batched ensemble e evolved to its end in one persistent launch per
     precision, after the launch-shape tuner: zone-updates per second per
     Runge-Kutta substep (sum over problems of cells x steps x substeps, over
-    the wall time of the evolve call)."""
+    the wall time of the evolve call), and how busy the launch kept its
+    workgroup slots (summed workgroup durations over slots x span, from the
+    workgroups' own clock readings).  For comparison, FP64 once more with one
+    workgroup per problem (the tuner's best shape without the split)."""
     import torch
     work = sum(n * s for n, s in zip(e.n, e.steps)) * e.rk_order
     out = {"workload": e.name, "problems": len(e.n), "cells": e.ncell, "zone_substeps": work}
-    for prec in ("fp64", "mixed"):
+    places = {0: "one workgroup per problem, rows in HBM", 1: "one workgroup per problem, rows in LDS",
+              2: "problems split among workgroups by work"}
+
+    def run(prec, shape=None):
         s = grmhd.batch_for(e, device=dev, precision=prec)
         P0 = s.pack(e.P)
         U = s.cons(P0)
-        th, lds = s.tune(U, trial_steps=20)
+        if shape is None:
+            th, lds = s.tune(U, trial_steps=20)
+        else:
+            th, lds = shape
+            s.set_shape(th, lds)
         U = s.cons(P0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.evolve(U)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        out[prec] = {"value": work / t, "seconds": round(t, 4), "threads": th,
-                     "placement": {0: "one workgroup per problem, rows in HBM",
-                                   1: "one workgroup per problem, rows in LDS",
-                                   2: "problems split among workgroups by work"}[lds],
-                     "recovery": s.status(), "finite": bool(torch.isfinite(U).all().item())}
+        busy, slots = s.busy()
+        r = {"value": work / t, "seconds": round(t, 4), "threads": th, "placement": places[lds],
+             "busy_fraction": round(busy, 4), "wg_slots": slots,
+             "recovery": s.status(), "finite": bool(torch.isfinite(U).all().item())}
         del s, U
+        return r
+
+    for prec in ("fp64", "mixed"):
+        out[prec] = run(prec)
     out["mixed"]["speedup_vs_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)
+    one = run("fp64", (1024, 0))
+    out["fp64_one_workgroup_per_problem"] = {k: one[k] for k in ("value", "seconds", "threads", "placement",
+                                                                   "busy_fraction", "wg_slots")}
     return out
 
 

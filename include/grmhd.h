@@ -378,11 +378,12 @@ int grmhd_batch_tune(grmhd_batch *b, const double *U, int trial_steps, int *thre
  * 0 one workgroup per problem, rows in HBM; 1 one workgroup per problem,
  * rows in LDS (refused with GRMHD_ERR_ARG when the largest row does not fit
  * in 160 KiB, or when the device refused that much LDS at grmhd_batch_init);
- * 2 (threads 256) every problem split among workgroups in proportion to its
- * work (cells x steps), all of them resident at once, the parts of a problem
- * exchanging the cells beside their segments through rows in HBM after each
- * substep (refused where grmhd_batch_init could not size the split for the
- * device).  Rows in LDS are the initial choice wherever they are allowed.
+ * 2 (threads 256) the work (cells x steps) spread evenly over workgroups that
+ * are all resident at once: a problem of more work than a workgroup's share
+ * split into parts that exchange the cells beside their segments through
+ * rows in HBM after each substep, smaller problems packed whole into shared
+ * workgroups that run them one after another (refused where
+ * grmhd_batch_init could not size the split for the device).  Rows in LDS are the initial choice wherever they are allowed.
  * grmhd_batch_evolve makes no call but its launches (one; two for the split:
  * the parts' progress counters are set from the step counts first), so it
  * can be captured in a HIP graph. */
@@ -393,6 +394,17 @@ int grmhd_batch_set_shape(grmhd_batch *b, int threads, int lds);
  * all resident at once, e.g. beside other work on the GPU); the state of the
  * problems is then not valid.  The counters are returned all the same. */
 int grmhd_batch_status(grmhd_batch *b, grmhd_stats *st, int reset);
+
+/* How busy the workgroup slots were during the last grmhd_batch_evolve
+ * launch: every workgroup records its start and end on the GPU's
+ * constant-rate clock, and *busy = (sum of the workgroups' durations) /
+ * (S x the launch's span from the first start to the last end), with *slots
+ * (may be NULL) = S = the workgroups the launch could hold resident at once
+ * (its occupancy times the CUs, at most its workgroup count).  1 means every
+ * slot worked until the last workgroup ended; an uneven ensemble on one
+ * workgroup per problem shows the idle tail.  Synchronises the stream.
+ * GRMHD_ERR_STATE before the first evolve call. */
+int grmhd_batch_busy(grmhd_batch *b, double *busy, int *slots);
 
 int grmhd_batch_free(grmhd_batch *b);
 

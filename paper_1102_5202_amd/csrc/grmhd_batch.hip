@@ -21,7 +21,8 @@ using grmhd::Dev;
 namespace {
 
 constexpr size_t LDS_LIMIT = 160 * 1024;
-// Split launch: at most this many parts, each at least this many cells.
+// Split launch: at most this many workgroups (and split parts beyond one
+// per problem), each part at least this many cells.
 constexpr int SPLIT_MAX_PARTS = 4096;
 constexpr int SPLIT_MIN_CELLS = 64;
 // Placement of the primitive rows (grmhd_batch_set_shape's lds argument).
@@ -36,7 +37,7 @@ struct BatchLayout {
     long long ncell = 0, nrow = 0;   // cells in all; elements of all ghosted rows
     int nmax = 0;
     size_t off_cnt, off_probs, off_order, off_probs_t, off_prow, off_pnext, off_us, off_prow_t, off_u_t;
-    size_t off_parts, off_flags, total;
+    size_t off_parts, off_flags, off_runs, off_span, total;
 };
 
 bool desc_ok(const grmhd_batch_desc* d)
@@ -85,10 +86,17 @@ BatchLayout batch_layout(const grmhd_batch_desc* d, size_t esize)
     off = up(off + esize * L.nrow, 256);
     L.off_u_t = off;
     off = up(off + sizeof(double) * 9 * L.ncell, 256);
-    L.off_parts = off;                   // the split launch's parts and their flags
-    off = up(off + sizeof(grmhd::BatchPart) * SPLIT_MAX_PARTS, 256);
+    // the split launch: its parts (at most one per problem plus the extra
+    // parts of split problems), their flags and the workgroups' runs of parts
+    const size_t maxparts = (size_t)d->nprob + SPLIT_MAX_PARTS;
+    L.off_parts = off;
+    off = up(off + sizeof(grmhd::BatchPart) * maxparts, 256);
     L.off_flags = off;
-    off = up(off + sizeof(int) * SPLIT_MAX_PARTS, 256);
+    off = up(off + sizeof(int) * maxparts, 256);
+    L.off_runs = off;
+    off = up(off + sizeof(int2) * SPLIT_MAX_PARTS, 256);
+    L.off_span = off;                    // start and end of every workgroup of the last launch
+    off = up(off + 2 * sizeof(unsigned long long) * std::max(d->nprob, SPLIT_MAX_PARTS), 256);
     L.total = off;
     return L;
 }
@@ -116,7 +124,10 @@ struct grmhd_batch {
     size_t lds_bytes = 0;
     bool lds_ok = false;   // rows fit in LDS and their LDS size is allowed
     std::vector<grmhd::BatchPart> parts;   // the split launch (empty: not available)
+    std::vector<int2> runs;                 // its workgroups: runs of consecutive parts
     unsigned long long* cnt = nullptr;
+    // the last evolve launch: its workgroups and its shape (for the busy fraction)
+    int last_wgs = 0, last_shape = 0, last_lds = 0;
 };
 
 namespace {
@@ -141,8 +152,11 @@ int upload(grmhd_batch* b, bool reset)
                            hipMemcpyHostToDevice, b->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
         if (!b->parts.empty() &&
-            hipMemcpyAsync(at<grmhd::BatchPart>(b, b->L.off_parts), b->parts.data(),
-                           sizeof(grmhd::BatchPart) * b->parts.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+            (hipMemcpyAsync(at<grmhd::BatchPart>(b, b->L.off_parts), b->parts.data(),
+                            sizeof(grmhd::BatchPart) * b->parts.size(), hipMemcpyHostToDevice,
+                            b->stream) != hipSuccess ||
+             hipMemcpyAsync(at<int2>(b, b->L.off_runs), b->runs.data(), sizeof(int2) * b->runs.size(),
+                            hipMemcpyHostToDevice, b->stream) != hipSuccess))
             return GRMHD_ERR_HIP;
         if (grmhd::launch_zero_counters(b->cnt, b->stream) != hipSuccess)
             return GRMHD_ERR_HIP;
@@ -154,17 +168,22 @@ int upload(grmhd_batch* b, bool reset)
 template <typename T>
 int evolve_t(grmhd_batch* b, double* U, int max_steps, size_t off_probs, size_t off_prow)
 {
+    unsigned long long* span = at<unsigned long long>(b, b->L.off_span);
+    b->last_shape = b->shape;
+    b->last_lds = b->lds;
     if (b->lds == PLACE_SPLIT) {
+        b->last_wgs = (int)b->runs.size();
         const hipError_t e = grmhd::launch_batch_split<T>(
             at<BatchProb>(b, off_probs), at<grmhd::BatchPart>(b, b->L.off_parts), (int)b->parts.size(),
-            at<int>(b, b->L.off_flags), U, at<T>(b, b->L.off_us), at<T>(b, off_prow), at<T>(b, b->L.off_pnext), b->d,
-            b->rk_order, max_steps, b->cnt, b->stream);
+            at<int2>(b, b->L.off_runs), (int)b->runs.size(), at<int>(b, b->L.off_flags), U, at<T>(b, b->L.off_us),
+            at<T>(b, off_prow), at<T>(b, b->L.off_pnext), b->d, b->rk_order, max_steps, b->cnt, span, b->stream);
         return e == hipSuccess ? GRMHD_OK : GRMHD_ERR_HIP;
     }
+    b->last_wgs = b->nprob;
     const hipError_t e = grmhd::launch_batch_evolve<T>(
         b->shape, b->lds, b->lds_bytes, at<BatchProb>(b, off_probs), at<int>(b, b->L.off_order), b->nprob, U,
         at<T>(b, b->L.off_us), at<T>(b, off_prow), at<T>(b, b->L.off_pnext), b->d, b->rk_order, max_steps, b->cnt,
-        b->stream);
+        span, b->stream);
     return e == hipSuccess ? GRMHD_OK : GRMHD_ERR_HIP;
 }
 
@@ -174,54 +193,91 @@ int evolve(grmhd_batch* b, double* U, int max_steps, size_t off_probs, size_t of
                     : evolve_t<double>(b, U, max_steps, off_probs, off_prow);
 }
 
-// The split launch's parts: every problem gets parts in proportion to its
-// work (cells x steps), at least one and at most one per SPLIT_MIN_CELLS
-// cells, so that the parts' work is about even and all of them fit on the
-// GPU at once (cap: resident workgroups of the split kernel).  A problem's
-// parts are consecutive; with periodic ends its first and last part are
-// neighbours.
-std::vector<grmhd::BatchPart> split_parts(const std::vector<BatchProb>& probs, int bc, int cap)
+// The split launch's plan, for cap resident workgroups: with w the target
+// work (cells x steps) of a workgroup, every problem of more work than w is
+// split into ceil(work / w) parts (at most one per SPLIT_MIN_CELLS cells),
+// each with a workgroup of its own; the smaller problems, largest first, are
+// packed whole into shared workgroups of at most w work each (next fit), run
+// one after another.  w starts at the mean work per workgroup and grows until
+// the workgroups fit in cap.  A split problem's parts are consecutive; with
+// periodic ends its first and last part are neighbours.  Returns false when
+// no plan fits.
+bool split_plan(const std::vector<BatchProb>& probs, int bc, int cap, std::vector<grmhd::BatchPart>& parts,
+                std::vector<int2>& runs)
 {
-    std::vector<grmhd::BatchPart> parts;
+    parts.clear();
+    runs.clear();
     const int np = (int)probs.size();
     cap = std::min(cap, SPLIT_MAX_PARTS);
-    if (cap < np)
-        return parts;
+    if (cap < 1)
+        return false;
+    std::vector<double> work(np);
     double total = 0.0;
-    for (const BatchProb& p : probs)
-        total += (double)p.n * std::max(p.steps, 1);
-    double w = total / cap;
-    std::vector<int> g(np);
-    for (int tries = 0; tries < 1000; ++tries) {
-        long long sum = 0;
-        for (int b = 0; b < np; ++b) {
-            const double work = (double)probs[b].n * std::max(probs[b].steps, 1);
-            const int gmax = std::max(1, probs[b].n / SPLIT_MIN_CELLS);
-            g[b] = (int)std::min<double>(gmax, std::max(1.0, std::ceil(work / w)));
-            sum += g[b];
-        }
-        if (sum <= cap)
-            break;
-        w *= 1.05;
-    }
     for (int b = 0; b < np; ++b) {
-        const int first = (int)parts.size(), n = probs[b].n;
-        for (int q = 0; q < g[b]; ++q) {
-            grmhd::BatchPart pt{};
-            pt.b = b;
-            pt.c0 = (int)((long long)n * q / g[b]);
-            pt.c1 = (int)((long long)n * (q + 1) / g[b]);
-            const bool wrap = bc == 0 && g[b] > 1;
-            pt.left = q > 0 ? first + q - 1 : (wrap ? first + g[b] - 1 : -1);
-            pt.right = q + 1 < g[b] ? first + q + 1 : (wrap ? first : -1);
-            pt.first = first;
-            pt.count = g[b];
-            parts.push_back(pt);
-        }
+        work[b] = (double)probs[b].n * std::max(probs[b].steps, 1);
+        total += work[b];
     }
-    if ((long long)parts.size() > cap)
-        parts.clear();
-    return parts;
+    std::vector<int> bysize(np);
+    std::iota(bysize.begin(), bysize.end(), 0);
+    std::stable_sort(bysize.begin(), bysize.end(), [&](int x, int y) { return work[x] > work[y]; });
+    double w = total / cap;
+    std::vector<int> g(np, 0);   // parts of a split problem; 0: packed whole
+    bool fits = false;
+    for (int tries = 0; tries < 2000 && !fits; ++tries, w *= 1.02) {
+        long long nwg = 0;
+        double bin = -1.0;   // work in the open shared workgroup (< 0: none)
+        for (int b : bysize) {
+            if (work[b] > w) {
+                g[b] = std::min(std::max(1, probs[b].n / SPLIT_MIN_CELLS), (int)std::ceil(work[b] / w));
+                nwg += g[b];
+            } else {
+                g[b] = 0;
+                if (bin < 0.0 || bin + work[b] > w) {
+                    ++nwg;
+                    bin = 0.0;
+                }
+                bin += work[b];
+            }
+        }
+        fits = nwg <= cap;
+    }
+    if (!fits)
+        return false;
+    double bin = -1.0;
+    for (int b : bysize) {
+        const int n = probs[b].n, first = (int)parts.size();
+        if (g[b] > 0) {
+            for (int q = 0; q < g[b]; ++q) {
+                grmhd::BatchPart pt{};
+                pt.b = b;
+                pt.c0 = (int)((long long)n * q / g[b]);
+                pt.c1 = (int)((long long)n * (q + 1) / g[b]);
+                const bool wrap = bc == 0 && g[b] > 1;
+                pt.left = q > 0 ? first + q - 1 : (wrap ? first + g[b] - 1 : -1);
+                pt.right = q + 1 < g[b] ? first + q + 1 : (wrap ? first : -1);
+                pt.first = first;
+                pt.count = g[b];
+                parts.push_back(pt);
+                runs.push_back(make_int2(first + q, 1));
+            }
+            continue;
+        }
+        grmhd::BatchPart pt{};
+        pt.b = b;
+        pt.c0 = 0;
+        pt.c1 = n;
+        pt.left = pt.right = -1;
+        pt.first = first;
+        pt.count = 1;
+        parts.push_back(pt);
+        if (bin < 0.0 || bin + work[b] > w) {
+            runs.push_back(make_int2(first, 0));
+            bin = 0.0;
+        }
+        runs.back().y += 1;
+        bin += work[b];
+    }
+    return (int)runs.size() <= cap;
 }
 
 }  // namespace
@@ -330,8 +386,11 @@ int grmhd_batch_init(grmhd_batch** out, const grmhd_batch_desc* desc, const grmh
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
         const int occ = b->mixed ? grmhd::batch_split_occupancy<float>() : grmhd::batch_split_occupancy<double>();
-        if (occ > 0 && cus > 0)
-            b->parts = split_parts(b->probs, desc->bc == GRMHD_BC_PERIODIC ? 0 : 1, occ * cus);
+        if (occ > 0 && cus > 0 &&
+            !split_plan(b->probs, desc->bc == GRMHD_BC_PERIODIC ? 0 : 1, occ * cus, b->parts, b->runs)) {
+            b->parts.clear();
+            b->runs.clear();
+        }
     }
     (void)hipGetLastError();
     *out = b;
@@ -526,6 +585,42 @@ int grmhd_batch_status(grmhd_batch* b, grmhd_stats* st, int reset)
             return GRMHD_ERR_HIP;
     }
     return stalled ? GRMHD_ERR_STATE : GRMHD_OK;
+}
+
+int grmhd_batch_busy(grmhd_batch* b, double* busy, int* slots)
+{
+    if (!b || !busy)
+        return GRMHD_ERR_ARG;
+    if (b->last_wgs < 1)
+        return GRMHD_ERR_STATE;
+    int per_cu = 0;
+    if (b->last_lds == PLACE_SPLIT)
+        per_cu = b->mixed ? grmhd::batch_split_occupancy<float>() : grmhd::batch_split_occupancy<double>();
+    else
+        per_cu = b->mixed ? grmhd::batch_evolve_occupancy<float>(b->last_shape, b->last_lds, b->lds_bytes)
+                          : grmhd::batch_evolve_occupancy<double>(b->last_shape, b->last_lds, b->lds_bytes);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1)
+        return GRMHD_ERR_HIP;
+    const int nw = b->last_wgs;
+    std::vector<unsigned long long> sp(2 * (size_t)nw);
+    if (hipStreamSynchronize(b->stream) != hipSuccess ||
+        hipMemcpy(sp.data(), at<unsigned long long>(b, b->L.off_span), sizeof(unsigned long long) * sp.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return GRMHD_ERR_HIP;
+    unsigned long long t0 = ~0ull, t1 = 0;
+    double sum = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        t0 = std::min(t0, sp[2 * (size_t)w]);
+        t1 = std::max(t1, sp[2 * (size_t)w + 1]);
+        sum += (double)(sp[2 * (size_t)w + 1] - sp[2 * (size_t)w]);
+    }
+    const int S = std::min(nw, per_cu * cus);
+    if (slots)
+        *slots = S;
+    *busy = t1 > t0 ? sum / ((double)S * (double)(t1 - t0)) : 0.0;
+    return GRMHD_OK;
 }
 
 int grmhd_batch_free(grmhd_batch* b)

@@ -78,7 +78,8 @@ static constexpr int BATCH_THREADS[BATCH_SHAPES] = {256, 512, 1024};
 // A problem split among several workgroups ("parts") that run at the same
 // time: part p owns the cells [c0, c1) of problem b; left and right are the
 // parts holding the cells beside c0 and c1 (-1 at the problem's ends); the
-// problem's parts are [first, first + count).
+// problem's parts are [first, first + count).  A problem too small to split
+// is one part holding all of its cells.
 struct BatchPart {
     int b, c0, c1, left, right, first, count, pad;
 };
@@ -103,18 +104,25 @@ hipError_t allow_batch_lds(size_t bytes);
 
 // The split launch: parts[nparts] as above, flags[nparts] the substeps each
 // part has completed (kept across launches, consistent with probs[].done).
+// runs[nruns]: workgroup w runs parts runs[w].x .. runs[w].x + runs[w].y - 1
+// in turn (a split problem's parts each have a workgroup of their own; small
+// whole problems share one).  span: 2 entries per workgroup, its start and
+// end on the GPU's constant-rate clock (written by every workgroup).
 template <typename T>
-hipError_t launch_batch_split(BatchProb* probs, const BatchPart* parts, int nparts, int* flags, double* U, T* Us,
-                              T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps, unsigned long long* cnt,
-                              hipStream_t s);
+hipError_t launch_batch_split(BatchProb* probs, const BatchPart* parts, int nparts, const int2* runs, int nruns,
+                              int* flags, double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order,
+                              int max_steps, unsigned long long* cnt, unsigned long long* span, hipStream_t s);
 // Resident workgroups of the split launch per CU (0 if unknown).
 template <typename T>
 int batch_split_occupancy();
+// Resident workgroups of an evolve launch shape per CU (0 if unknown).
+template <typename T>
+int batch_evolve_occupancy(int shape, int lds, size_t lds_bytes);
 
 template <typename T>
 hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
                                double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps,
-                               unsigned long long* cnt, hipStream_t s);
+                               unsigned long long* cnt, unsigned long long* span, hipStream_t s);
 
 // Adjoint kernels (FP64; grmhd_adjoint.hip).  FB: the face-state cotangents
 // of one axis (18 rows of nf[d] values); MU: a ghosted cotangent of the

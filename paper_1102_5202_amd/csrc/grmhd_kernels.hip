@@ -1100,12 +1100,26 @@ __global__ __launch_bounds__(BLOCK) void k_batch_prim(const BatchProb* __restric
     count_sums(cnt, nf, na, np, nb, itmax);
 }
 
+// The workgroup's start (taken on entry) and end on the GPU's constant-rate
+// clock, into span[2 b], span[2 b + 1] for workgroup b, once all of its
+// threads are done: the host derives how busy the workgroup slots were.
+__device__ __forceinline__ void span_record(unsigned long long* span, unsigned long long t_start)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        span[2 * blockIdx.x] = t_start;
+        span[2 * blockIdx.x + 1] = wall_clock64();
+    }
+}
+
 template <typename T, int NT, bool LDS>
 __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ probs, const int* __restrict__ order,
                                                      double* __restrict__ U, T* __restrict__ Us,
                                                      T* __restrict__ Prow, T* __restrict__ Pnext, Dev d, int ns,
-                                                     int max_steps, unsigned long long* __restrict__ cnt)
+                                                     int max_steps, unsigned long long* __restrict__ cnt,
+                                                     unsigned long long* __restrict__ span)
 {
+    const unsigned long long t_start = wall_clock64();
     extern __shared__ unsigned char smem[];
     const int b = order[blockIdx.x];
     const BatchProb pr = probs[b];
@@ -1220,6 +1234,7 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
     if (threadIdx.x == 0)
         probs[b].done = pr.done + nsteps;
     count_sums(cnt, nfail, natm, npf, nfb, itmax);
+    span_record(span, t_start);
 }
 
 // k_batch_split: a problem's cells divided among several workgroups (parts)
@@ -1265,7 +1280,8 @@ __device__ __forceinline__ bool split_wait(int* flags, int l, int r, int target,
         *s_ok = ok;
     }
     __syncthreads();
-    return *s_ok != 0;
+    // the same for every thread: read once, as a uniform value
+    return __builtin_amdgcn_readfirstlane(*s_ok) != 0;
 }
 
 // row_store with system-scope stores (values other parts read).
@@ -1294,137 +1310,161 @@ __device__ __forceinline__ void row_store_sys(T* __restrict__ row, int pitch, in
             __hip_atomic_store(&row[v * pitch + o[e] + 2], (T)p[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_batch_split(BatchProb* __restrict__ probs, const BatchPart* __restrict__ parts,
-                                                    int* flags, double* __restrict__ U, T* __restrict__ Us,
-                                                    T* Prow, T* Pnext, Dev d, int ns, int max_steps,
-                                                    unsigned long long* __restrict__ cnt)
+// A record the whole workgroup reads at one address, moved into scalar
+// registers word by word (the records of a later part are loaded after
+// stores to the same array, so the compiler would keep them per lane).
+template <typename S>
+__device__ __forceinline__ S uniform_load(const S* p)
 {
+    static_assert(sizeof(S) % 4 == 0, "whole words");
+    S r;
+    const int* src = (const int*)p;
+    int* dst = (int*)&r;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(S) / 4); ++k)
+        dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return r;
+}
+
+// Workgroup w runs the parts runs[w].x .. runs[w].x + runs[w].y - 1 one
+// after another: a segment of a split problem (a run of one), or several
+// small problems packed whole (no neighbours, so no waits).  The register
+// budget of 3 waves per SIMD (some FP64 spills) keeps more parts resident.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_batch_split(
+    BatchProb* __restrict__ probs, const BatchPart* __restrict__ parts, const int2* __restrict__ runs, int* flags,
+    double* __restrict__ U, T* __restrict__ Us, T* Prow, T* Pnext, Dev d, int ns, int max_steps,
+    unsigned long long* __restrict__ cnt, unsigned long long* __restrict__ span)
+{
+    const unsigned long long t_start = wall_clock64();
     __shared__ int s_ok;
-    const int part = blockIdx.x;
-    const BatchPart pt = parts[part];
-    const BatchProb pr = probs[pt.b];
-    const int n = pr.n, pitch = n + 4;
-    const int nsteps = min(max_steps, pr.steps - pr.done);
-    const int base = pr.done * ns;   // substeps every part of the problem had completed
-    const int nsub = nsteps * ns;
-    const int ch = (pt.c1 - pt.c0 + NT - 1) / NT;
-    const int c0 = min(pt.c0 + (int)threadIdx.x * ch, pt.c1), c1 = min(c0 + ch, pt.c1);
-    // cells within two of either end of the segment (and those beyond it,
-    // the neighbours' and the ghost images) are written and read with
-    // system-scope accesses; the rest of the row with plain ones
-    auto edge = [&](int x) { return x < pt.c0 + 2 || x >= pt.c1 - 2; };
-    auto rd = [&](const T* r, int x) { return edge(x) ? sys_load(r + x + 2) : r[x + 2]; };
-    const bool edge_thread = c0 < c1 && (edge(c0) || edge(c1 - 1));
-    double* Ub = U + 9 * pr.off;
-    T* Usb = Us + 9 * pr.off;
-    T* cur = Prow + pr.poff;
-    T* nxt = Pnext + pr.poff;
-    const Geo geo = geo_at<FLAT>(d, 0.0, 0.0, 0.0);
-    const T half = T(0.5);
+    const int2 run = runs[blockIdx.x];
     int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
     bool stalled = false;
-    for (int i = 0; i < nsub && !stalled; ++i) {
-        if (i > 0 && !split_wait(flags, pt.left, pt.right, base + i, &s_ok)) {
-            stalled = true;
-            break;
-        }
-        const int s = i % ns;
-        const double a = ns == 3 ? (s == 0 ? 0.0 : (s == 1 ? 0.75 : 1.0 / 3.0)) : (s == 0 ? 0.0 : 0.5);
-        const double bb = ns == 3 ? (s == 0 ? 1.0 : (s == 1 ? 0.25 : 2.0 / 3.0)) : (s == 0 ? 1.0 : 0.5);
-        T Fp[9];
-        if (c0 < c1) {
-            // face c0 - 1/2 from cells c0-2 .. c0+1 (row index + 2); the first
-            // thread's two cells before c0 belong to the left neighbour
-            T qL[9], qR[9];
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                const T* r = cur + v * pitch;
-                const T q0 = rd(r, c0 - 2), q1 = rd(r, c0 - 1), q2 = rd(r, c0), q3 = rd(r, c0 + 1);
-                qL[v] = q1 + half * mc_slope(q0, q1, q2);
-                qR[v] = q2 - half * mc_slope(q1, q2, q3);
-            }
-            face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fp);
-        }
-        for (int c = c0; c < c1; ++c) {
-            T qL[9], qR[9], Fc[9], q[9];
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                const T* r = cur + v * pitch;              // cells c-1 .. c+2
-                const T q0 = rd(r, c - 1), q1 = rd(r, c), q2 = rd(r, c + 1), q3 = rd(r, c + 2);
-                q[v] = q1;
-                qL[v] = q1 + half * mc_slope(q0, q1, q2);
-                qR[v] = q2 - half * mc_slope(q1, q2, q3);
-            }
-            face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
-            double R[9];
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                R[v] = -((double)Fc[v] - (double)Fp[v]) * pr.idx;
-                Fp[v] = Fc[v];
-            }
-            R[8] -= d.kappa * (double)q[8];
-            double u[9], qg[9], p[9];
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                const double un = Ub[(long long)v * n + c];
-                const double us = s == 0 ? un : (double)Usb[(long long)v * n + c];
-                u[v] = us + a * (un - us) + bb * (pr.dt * R[v]);
-                qg[v] = (double)q[v];
-            }
-            int iters = 0;
-            const int fl = recover_cell(d, geo, u, qg, p, iters);
-            tally(fl, iters, nfail, natm, npf, nfb, itmax);
-            if (s == ns - 1) {
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    Ub[(long long)v * n + c] = u[v];
-            } else {
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    Usb[(long long)v * n + c] = (T)u[v];
-            }
-            if (edge(c))
-                row_store_sys(nxt, pitch, n, d.bc[0], c, p);
-            else
-                row_store(nxt, pitch, n, d.bc[0], c, p);
-        }
-        // publish: the values other parts read have reached memory, then the count
-        if (edge_thread)
-            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&flags[part], base + i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        T* t = cur;
-        cur = nxt;
-        nxt = t;
-    }
-    if (!stalled && (nsub & 1)) {
-        // the row ended in Pnext: once the neighbours no longer read Prow (they
-        // completed every substep), copy the own cells and their ghost images
-        if (!split_wait(flags, pt.left, pt.right, base + nsub, &s_ok))
-            stalled = true;
-        else {
-            for (int c = c0; c < c1; ++c) {
-                double p[9];
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    p[v] = (double)rd(cur + v * pitch, c);
-                row_store(Prow + pr.poff, pitch, n, d.bc[0], c, p);
-            }
-        }
-    }
-    // the problem's first part records the steps once every part has taken them
-    if (!stalled && part == pt.first) {
-        for (int q = 0; q < pt.count && !stalled; ++q)
-            if (!split_wait(flags, pt.first + q, -1, base + nsub, &s_ok))
+    for (int part = run.x; part < run.x + run.y && !stalled; ++part) {
+        const BatchPart pt = uniform_load(&parts[part]);
+        const BatchProb pr = uniform_load(&probs[pt.b]);
+        const int n = pr.n, pitch = n + 4;
+        const int nsteps = min(max_steps, pr.steps - pr.done);
+        const int base = pr.done * ns;   // substeps every part of the problem had completed
+        const int nsub = nsteps * ns;
+        const int ch = (pt.c1 - pt.c0 + NT - 1) / NT;
+        const int c0 = min(pt.c0 + (int)threadIdx.x * ch, pt.c1), c1 = min(c0 + ch, pt.c1);
+        // cells within two of either end of the segment (and those beyond it,
+        // the neighbours' and the ghost images) are written and read with
+        // system-scope accesses; the rest of the row with plain ones
+        auto edge = [&](int x) { return x < pt.c0 + 2 || x >= pt.c1 - 2; };
+        auto rd = [&](const T* r, int x) { return edge(x) ? sys_load(r + x + 2) : r[x + 2]; };
+        const bool edge_thread = c0 < c1 && (edge(c0) || edge(c1 - 1));
+        double* Ub = U + 9 * pr.off;
+        T* Usb = Us + 9 * pr.off;
+        T* cur = Prow + pr.poff;
+        T* nxt = Pnext + pr.poff;
+        const Geo geo = geo_at<FLAT>(d, 0.0, 0.0, 0.0);
+        const T half = T(0.5);
+        for (int i = 0; i < nsub && !stalled; ++i) {
+            if (i > 0 && !split_wait(flags, pt.left, pt.right, base + i, &s_ok)) {
                 stalled = true;
-        if (!stalled && threadIdx.x == 0)
-            probs[pt.b].done = pr.done + nsteps;
+                break;
+            }
+            const int s = i % ns;
+            const double a = ns == 3 ? (s == 0 ? 0.0 : (s == 1 ? 0.75 : 1.0 / 3.0)) : (s == 0 ? 0.0 : 0.5);
+            const double bb = ns == 3 ? (s == 0 ? 1.0 : (s == 1 ? 0.25 : 2.0 / 3.0)) : (s == 0 ? 1.0 : 0.5);
+            T Fp[9];
+            if (c0 < c1) {
+                // face c0 - 1/2 from cells c0-2 .. c0+1 (row index + 2); the first
+                // thread's two cells before c0 belong to the left neighbour
+                T qL[9], qR[9];
+    #pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    const T* r = cur + v * pitch;
+                    const T q0 = rd(r, c0 - 2), q1 = rd(r, c0 - 1), q2 = rd(r, c0), q3 = rd(r, c0 + 1);
+                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
+                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                }
+                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fp);
+            }
+            for (int c = c0; c < c1; ++c) {
+                T qL[9], qR[9], Fc[9], q[9];
+    #pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    const T* r = cur + v * pitch;              // cells c-1 .. c+2
+                    const T q0 = rd(r, c - 1), q1 = rd(r, c), q2 = rd(r, c + 1), q3 = rd(r, c + 2);
+                    q[v] = q1;
+                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
+                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                }
+                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
+                double R[9];
+    #pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    R[v] = -((double)Fc[v] - (double)Fp[v]) * pr.idx;
+                    Fp[v] = Fc[v];
+                }
+                R[8] -= d.kappa * (double)q[8];
+                double u[9], qg[9], p[9];
+    #pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    const double un = Ub[(long long)v * n + c];
+                    const double us = s == 0 ? un : (double)Usb[(long long)v * n + c];
+                    u[v] = us + a * (un - us) + bb * (pr.dt * R[v]);
+                    qg[v] = (double)q[v];
+                }
+                int iters = 0;
+                const int fl = recover_cell(d, geo, u, qg, p, iters);
+                tally(fl, iters, nfail, natm, npf, nfb, itmax);
+                if (s == ns - 1) {
+    #pragma unroll
+                    for (int v = 0; v < 9; ++v)
+                        Ub[(long long)v * n + c] = u[v];
+                } else {
+    #pragma unroll
+                    for (int v = 0; v < 9; ++v)
+                        Usb[(long long)v * n + c] = (T)u[v];
+                }
+                if (edge(c))
+                    row_store_sys(nxt, pitch, n, d.bc[0], c, p);
+                else
+                    row_store(nxt, pitch, n, d.bc[0], c, p);
+            }
+            // publish: the values other parts read have reached memory, then the count
+            if (edge_thread)
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&flags[part], base + i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            T* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (!stalled && (nsub & 1)) {
+            // the row ended in Pnext: once the neighbours no longer read Prow (they
+            // completed every substep), copy the own cells and their ghost images
+            if (!split_wait(flags, pt.left, pt.right, base + nsub, &s_ok))
+                stalled = true;
+            else {
+                for (int c = c0; c < c1; ++c) {
+                    double p[9];
+    #pragma unroll
+                    for (int v = 0; v < 9; ++v)
+                        p[v] = (double)rd(cur + v * pitch, c);
+                    row_store(Prow + pr.poff, pitch, n, d.bc[0], c, p);
+                }
+            }
+        }
+        // the problem's first part records the steps once every part has taken them
+        if (!stalled && part == pt.first) {
+            for (int q = 0; q < pt.count && !stalled; ++q)
+                if (!split_wait(flags, pt.first + q, -1, base + nsub, &s_ok))
+                    stalled = true;
+            if (!stalled && threadIdx.x == 0)
+                probs[pt.b].done = pr.done + nsteps;
+        }
     }
     if (stalled && threadIdx.x == 0)
         atomicAdd(&cnt[(size_t)(blockIdx.x % CNT_SLOTS) * CNT_WORDS + CNT_STALL], 1ull);
     count_sums(cnt, nfail, natm, npf, nfb, itmax);
+    span_record(span, t_start);
 }
 
 // The device arithmetic the kernels use, on arrays, for checking it against
@@ -1755,16 +1795,43 @@ hipError_t launch_batch_prim(const BatchProb* probs, int nprob, long long ncell,
 template <typename T, int NT>
 static hipError_t batch_evolve_k(int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
                                  double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int ns, int max_steps,
-                                 unsigned long long* cnt, hipStream_t s)
+                                 unsigned long long* cnt, unsigned long long* span, hipStream_t s)
 {
     if (lds) {
         // (the dynamic LDS size was allowed by allow_batch_lds at set-up)
         hipLaunchKernelGGL((k_batch_evolve<T, NT, true>), dim3(nprob), dim3(NT), lds_bytes, s, probs, order, U,
-                           Us, Prow, Pnext, d, ns, max_steps, cnt);
+                           Us, Prow, Pnext, d, ns, max_steps, cnt, span);
     } else
         hipLaunchKernelGGL((k_batch_evolve<T, NT, false>), dim3(nprob), dim3(NT), 0, s, probs, order, U, Us,
-                           Prow, Pnext, d, ns, max_steps, cnt);
+                           Prow, Pnext, d, ns, max_steps, cnt, span);
     return hipGetLastError();
+}
+
+template <typename T, int NT>
+static int evolve_occupancy_k(int lds, size_t lds_bytes)
+{
+    int nb = 0;
+    const hipError_t e =
+        lds ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_evolve<T, NT, true>, NT, lds_bytes)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_evolve<T, NT, false>, NT, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+template <typename T>
+int batch_evolve_occupancy(int shape, int lds, size_t lds_bytes)
+{
+    switch (BATCH_THREADS[shape]) {
+    case 256:
+        return evolve_occupancy_k<T, 256>(lds, lds_bytes);
+    case 512:
+        return evolve_occupancy_k<T, 512>(lds, lds_bytes);
+    default:
+        return evolve_occupancy_k<T, 1024>(lds, lds_bytes);
+    }
 }
 
 // Dynamic LDS beyond the default launch limit must be allowed per kernel, once,
@@ -1800,14 +1867,14 @@ __global__ __launch_bounds__(BLOCK) void k_split_flags(const BatchProb* __restri
 }
 
 template <typename T>
-hipError_t launch_batch_split(BatchProb* probs, const BatchPart* parts, int nparts, int* flags, double* U, T* Us,
-                              T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps, unsigned long long* cnt,
-                              hipStream_t s)
+hipError_t launch_batch_split(BatchProb* probs, const BatchPart* parts, int nparts, const int2* runs, int nruns,
+                              int* flags, double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order,
+                              int max_steps, unsigned long long* cnt, unsigned long long* span, hipStream_t s)
 {
     hipLaunchKernelGGL(k_split_flags, dim3(blocks_for(nparts)), dim3(BLOCK), 0, s, probs, parts, nparts, flags,
                        rk_order);
-    hipLaunchKernelGGL((k_batch_split<T, BATCH_SPLIT_THREADS>), dim3(nparts), dim3(BATCH_SPLIT_THREADS), 0, s, probs,
-                       parts, flags, U, Us, Prow, Pnext, d, rk_order, max_steps, cnt);
+    hipLaunchKernelGGL((k_batch_split<T, BATCH_SPLIT_THREADS>), dim3(nruns), dim3(BATCH_SPLIT_THREADS), 0, s, probs,
+                       parts, runs, flags, U, Us, Prow, Pnext, d, rk_order, max_steps, cnt, span);
     return hipGetLastError();
 }
 
@@ -1826,18 +1893,18 @@ int batch_split_occupancy()
 template <typename T>
 hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* probs, const int* order, int nprob,
                                double* U, T* Us, T* Prow, T* Pnext, const Dev& d, int rk_order, int max_steps,
-                               unsigned long long* cnt, hipStream_t s)
+                               unsigned long long* cnt, unsigned long long* span, hipStream_t s)
 {
     switch (shape) {
     case 0:
         return batch_evolve_k<T, 256>(lds, lds_bytes, probs, order, nprob, U, Us, Prow, Pnext, d, rk_order,
-                                          max_steps, cnt, s);
+                                      max_steps, cnt, span, s);
     case 1:
         return batch_evolve_k<T, 512>(lds, lds_bytes, probs, order, nprob, U, Us, Prow, Pnext, d, rk_order,
-                                         max_steps, cnt, s);
+                                      max_steps, cnt, span, s);
     default:
         return batch_evolve_k<T, 1024>(lds, lds_bytes, probs, order, nprob, U, Us, Prow, Pnext, d, rk_order,
-                                          max_steps, cnt, s);
+                                       max_steps, cnt, span, s);
     }
 }
 
@@ -1856,11 +1923,14 @@ hipError_t launch_batch_evolve(int shape, int lds, size_t lds_bytes, BatchProb* 
     template hipError_t launch_batch_prim<T>(const BatchProb*, int, long long, const double*, double*, T*,     \
                                              const Dev&, unsigned long long*, hipStream_t);                   \
     template hipError_t allow_batch_lds<T>(size_t);                                                           \
-    template hipError_t launch_batch_split<T>(BatchProb*, const BatchPart*, int, int*, double*, T*, T*, T*,     \
-                                              const Dev&, int, int, unsigned long long*, hipStream_t);         \
+    template hipError_t launch_batch_split<T>(BatchProb*, const BatchPart*, int, const int2*, int, int*, double*, \
+                                              T*, T*, T*, const Dev&, int, int, unsigned long long*,              \
+                                              unsigned long long*, hipStream_t);                                 \
     template int batch_split_occupancy<T>();                                                                  \
+    template int batch_evolve_occupancy<T>(int, int, size_t);                                                 \
     template hipError_t launch_batch_evolve<T>(int, int, size_t, BatchProb*, const int*, int, double*, T*, T*, \
-                                               T*, const Dev&, int, int, unsigned long long*, hipStream_t);
+                                               T*, const Dev&, int, int, unsigned long long*, unsigned long long*, \
+                                               hipStream_t);
 GRMHD_INSTANTIATE_BATCH(double)
 GRMHD_INSTANTIATE_BATCH(float)
 GRMHD_INSTANTIATE_UPDATE(double, double, double)

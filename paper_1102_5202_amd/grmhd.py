@@ -34,8 +34,8 @@ SYMBOLS = ("grmhd_workspace_bytes", "grmhd_init", "grmhd_set_stream", "grmhd_con
            "grmhd_prim_adjoint", "grmhd_status", "grmhd_timing", "grmhd_free", "grmhd_strerror",
            "grmhd_batch_workspace_bytes", "grmhd_batch_init", "grmhd_batch_set_stream",
            "grmhd_batch_cons", "grmhd_batch_evolve", "grmhd_batch_prim", "grmhd_batch_tune",
-           "grmhd_batch_set_shape", "grmhd_batch_status", "grmhd_batch_free", "grmhd_rhs_noalloc",
-           "grmhd_device_arith")
+           "grmhd_batch_set_shape", "grmhd_batch_status", "grmhd_batch_busy", "grmhd_batch_free",
+           "grmhd_rhs_noalloc", "grmhd_device_arith")
 
 
 class Metric(C.Structure):
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
     L.grmhd_batch_tune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.grmhd_batch_set_shape.argtypes = [vp, C.c_int, C.c_int]
     L.grmhd_batch_status.argtypes = [vp, C.POINTER(Stats), C.c_int]
+    L.grmhd_batch_busy.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.grmhd_batch_free.argtypes = [vp]
     L.grmhd_rhs_noalloc.argtypes = [C.POINTER(Metric), C.POINTER(Grid), C.POINTER(Eos), C.POINTER(Opts), vp, vp,
                                     vp]
@@ -438,6 +439,13 @@ class BatchSolver:
         _check(load().grmhd_batch_status(self._ctx, C.byref(st), int(bool(reset))), "grmhd_batch_status")
         return {"fail": st.c2p_fail, "atm": st.atm_hits, "pfloor": st.p_floor_hits,
                 "fallback_1d": st.fallback_1d, "max_newton_it": st.max_newton_it}
+
+    def busy(self) -> tuple:
+        """(busy fraction, workgroup slots) of the last evolve launch: the
+        workgroups' summed durations over slots x the launch's span."""
+        frac, slots = C.c_double(), C.c_int()
+        _check(load().grmhd_batch_busy(self._ctx, C.byref(frac), C.byref(slots)), "grmhd_batch_busy")
+        return frac.value, slots.value
 
     def close(self) -> None:
         if getattr(self, "_ctx", None):

@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 30, names
+    assert len(names) == 31, names
     assert set(names) == set(lib.SYMBOLS)
     L = lib.load()
     for n in names:
@@ -297,6 +297,10 @@ def test_batch_workspace_and_init_validation(lib):
     assert L.grmhd_batch_init(C.byref(ctx), C.byref(desc), C.byref(e), C.byref(o)) == 0
     assert L.grmhd_batch_evolve(ctx, C.c_void_p(addr), 5) == -4      # before cons
     assert L.grmhd_batch_evolve(ctx, None, 5) == -1
+    busy = C.c_double()
+    assert L.grmhd_batch_busy(ctx, C.byref(busy), None) == -4         # no evolve launch yet
+    assert L.grmhd_batch_busy(ctx, None, None) == -1
+    assert L.grmhd_batch_busy(None, C.byref(busy), None) == -1
     assert L.grmhd_batch_tune(ctx, C.c_void_p(addr), 5, None, None) == -4
     assert L.grmhd_batch_set_shape(ctx, 384, 0) == -1
     assert L.grmhd_batch_set_shape(ctx, 1024, 0) == 0

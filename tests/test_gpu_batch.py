@@ -176,3 +176,55 @@ def test_batch_one_unknown_recovery(G, orc):
         Ur, _ = _oracle_problem(orc, e, b)
         err = orc.parity_error(Us[b].numpy(), Ur)
         assert np.all(err[:8] <= 1e-10), (b, err)
+
+
+def test_batch_busy_fraction(G):
+    """The busy fraction of the last launch, from the workgroups' clock
+    readings: in (0, 1], and near 1 for an ensemble of equal problems on one
+    workgroup per problem (every slot works until the end)."""
+    e = WL.config5(nprob=12, nmin=100, nmax=101, k=4)
+    for lds in (0, 2):
+        s = G.batch_for(e, device=DEV)
+        s.set_shape(256, lds)
+        U = s.cons(s.pack(e.P))
+        s.evolve(U)
+        busy, slots = s.busy()
+        say("placement", lds, "busy", busy, "slots", slots)
+        assert 0.0 < busy <= 1.0 + 1e-12
+        assert 1 <= slots
+        if lds == 0:
+            assert slots == len(e.n) and busy > 0.5
+
+
+def test_batch_split_packs_small_problems(G, orc):
+    """Two large problems and many small ones: with the rows split among
+    workgroups the large problems are divided into parts and the small ones
+    packed whole into shared workgroups (run one after another).  The result
+    matches one workgroup per problem to rounding (relative L1 <= 1e-12: the
+    separately compiled kernels contract multiply-adds differently, and the
+    two large problems take 1500 steps of a discontinuous solution), and the
+    oracle on a large and a few small problems."""
+    small = WL.config5(nprob=120, nmin=20, nmax=40, k=5)
+    big = WL.config5(nprob=2, nmin=1500, nmax=1600, k=6)
+    # the two large problems in front of the small ones
+    e = WL.Ensemble(name="packed", P=list(big.P) + list(small.P), n=list(big.n) + list(small.n),
+                    dt=list(big.dt) + list(small.dt), steps=list(big.steps) + list(small.steps))
+    res = {}
+    for lds in (2, 0):
+        s = G.batch_for(e, device=DEV)
+        s.set_shape(256, lds)
+        U = s.cons(s.pack(e.P))
+        s.evolve(U)
+        busy, slots = s.busy()
+        st = s.status()
+        say("placement", lds, "workgroups", slots, "busy", busy, st)
+        res[lds] = U.cpu().numpy()
+    rel = np.abs(res[2] - res[0]).sum() / np.abs(res[0]).sum()
+    say("split+packed vs one workgroup per problem: rel-L1", rel)
+    assert rel <= 1e-12
+    s = G.batch_for(e, device=DEV)
+    Us = s.unpack(torch.from_numpy(res[2]))
+    for b in (0, 2, 3, len(e.n) - 1):
+        Ur, _ = _oracle_problem(orc, e, b)
+        err = orc.parity_error(Us[b].numpy(), Ur)
+        assert np.all(err[:8] <= 1e-10), (b, err)
