@@ -127,41 +127,56 @@ def test_batch_graph_replay_matches_eager(G, precision, lds):
     say(precision, "graph replays match eager; status", sg.status())
 
 
+_full = {}
+
+
+def _full_size_states(G):
+    """Config 5 at full size evolved in FP64 and mixed (tuned launch shapes),
+    once per module."""
+    if not _full:
+        e = WL.config5()
+        for prec in ("fp64", "mixed"):
+            s = G.batch_for(e, device=DEV, precision=prec)
+            U = s.cons(s.pack(e.P))
+            th, lds = s.tune(U, trial_steps=20)
+            s.evolve(U)
+            torch.cuda.synchronize()
+            say(prec, "tuned", th, lds, s.status())
+            assert bool(torch.isfinite(U).all())
+            _full[prec] = [x.numpy() for x in s.unpack(U.cpu())]
+        _full["e"] = e
+    return _full
+
+
 def test_batch_full_size_sampled(G, orc):
     """The ensemble at full size (256 problems, 200..4000 cells, each to
-    t = 0.4): the three smallest problems against the oracle, every state
-    finite, mixed against FP64 per problem."""
-    e = WL.config5()
-    res = {}
-    for prec in ("fp64", "mixed"):
-        s = G.batch_for(e, device=DEV, precision=prec)
-        U = s.cons(s.pack(e.P))
-        th, lds = s.tune(U, trial_steps=20)
-        s.evolve(U)
-        torch.cuda.synchronize()
-        say(prec, "tuned", th, lds, s.status())
-        assert bool(torch.isfinite(U).all())
-        res[prec] = [x.numpy() for x in s.unpack(U.cpu())]
+    t = 0.4): every state finite, the three smallest problems against the
+    oracle at the FP64 bar."""
+    res = _full_size_states(G)
+    e = res["e"]
     for b in np.argsort(e.n)[:3]:
         Ur, _ = _oracle_problem(orc, e, int(b))
         err = orc.parity_error(res["fp64"][b], Ur)
-        say("problem", b, "n", e.n[b], "rel-L1", err[:8].max())
-        assert np.all(err[:8] <= 1e-10)
-    errs = []
-    for b in range(len(e.n)):
-        err = orc.parity_error(res["mixed"][b], res["fp64"][b])
-        errs.append(err[:8])
-    errs = np.array(errs)
+        say("problem", b, "n", e.n[b], "rel-L1", err.max())
+        assert np.all(err <= 1e-10)
+
+
+@pytest.mark.xfail(strict=True, reason="discontinuous 1D solutions: FP32 face arithmetic moves sub-cell "
+                                       "features, so the longer problems end 1e-5 .. 1e-3 from FP64")
+def test_batch_full_size_mixed_within_1e5(G, orc):
+    """Mixed against FP64 (itself matched to the oracle) on every problem of
+    the full ensemble, all nine variables, at the 1e-5 bar.  It fails on the
+    longer problems; the distribution is reported."""
+    res = _full_size_states(G)
+    e = res["e"]
+    errs = np.array([orc.parity_error(res["mixed"][b], res["fp64"][b]) for b in range(len(e.n))])
     worst = errs.max(axis=1)
     order = np.argsort(worst)[::-1]
-    say("mixed vs fp64 per-problem rel-L1: median %.2e, 90%% %.2e, worst %.2e"
-        % (np.median(worst), np.percentile(worst, 90), worst.max()))
+    say("mixed vs fp64 per-problem rel-L1 (all variables): median %.2e, 90%% %.2e, worst %.2e, above 1e-5: %d"
+        % (np.median(worst), np.percentile(worst, 90), worst.max(), int((worst > 1e-5).sum())))
     for b in order[:6]:
         say("  problem", b, "n", e.n[b], "by variable", np.array2string(errs[b], precision=2))
-    # discontinuous solutions: FP32 rounding moves sub-cell features, so the
-    # distance grows with the number of cells and steps; the median problem
-    # holds the 1e-5 bar
-    assert np.median(worst) <= 1e-5 and np.percentile(worst, 90) <= 1e-4
+    assert np.all(worst <= 1e-5)
 
 
 def test_batch_one_unknown_recovery(G, orc):
