@@ -272,6 +272,17 @@ __device__ __forceinline__ T mc_slope(T qm, T q0, T qp)
     return (dl * dr > T(0)) ? copysign(s, dc) : T(0);
 }
 
+// Half the MC slope, the offset of the face values from the cell value:
+// minmod(dq-, (dq- + dq+)/4, dq+), the same number as 0.5 * mc_slope (the
+// factors of two are exact) in fewer operations.
+template <typename T>
+__device__ __forceinline__ T mc_hslope(T qm, T q0, T qp)
+{
+    const T dl = q0 - qm, dr = qp - q0, dq = qp - qm;
+    const T h = fmin(fmin(fabs(dl), fabs(dr)), T(0.25) * fabs(dq));
+    return (dl * dr > T(0)) ? copysign(h, dq) : T(0);
+}
+
 // PPM edge values (Colella & Woodward's piecewise parabolic method, the
 // alternative reconstruction of section 3.2) of the middle cell of a0..a4:
 // interface values from the four nearest cells with MC-limited slopes, then

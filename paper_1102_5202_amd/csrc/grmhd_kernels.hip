@@ -134,14 +134,13 @@ __global__ __launch_bounds__(BLOCK) void k_flux_x(const T* __restrict__ Pc, T* _
     int k = (int)(t / d.n[1]);
     // cell i-2 in ghosted coordinates
     long long base = ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + i + d.g[0] - 2;
-    const T half = T(0.5);
     T qL[9], qR[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
         const T* p = Pc + v * d.sv + base;
         T q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
-        qL[v] = q1 + half * mc_slope(q0, q1, q2);
-        qR[v] = q2 - half * mc_slope(q1, q2, q3);
+        qL[v] = q1 + mc_hslope(q0, q1, q2);
+        qR[v] = q2 - mc_hslope(q1, q2, q3);
     }
     face_store<0, KIND, NT>(qL, qR, d.lo[0] + i * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
                         d.lo[2] + (k + 0.5) * d.dx[2], d, F, d.nf[0], f);
@@ -177,8 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, 
     const long long fstr = D == 1 ? (long long)d.n[0] : (long long)d.n[0] * d.n[1];
     long long fidx = D == 1 ? i + (long long)d.n[0] * ((long long)f0 + (long long)(d.n[1] + 1) * a)
                             : i + (long long)d.n[0] * (a + (long long)d.n[1] * f0);
-    const T half = T(0.5);
-    T qb[9], qc[9], sc[9];      // cells f-1 and f, MC slope of cell f-1
+    T qb[9], qc[9], sc[9];      // cells f-1 and f, half MC slope of cell f-1
     {
         T qa[9];
 #pragma unroll
@@ -190,7 +188,7 @@ __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, 
         }
 #pragma unroll
         for (int v = 0; v < 9; ++v)
-            sc[v] = mc_slope(qa[v], qb[v], qc[v]);
+            sc[v] = mc_hslope(qa[v], qb[v], qc[v]);
     }
     double xyz[3];
     xyz[0] = d.lo[0] + (i + 0.5) * d.dx[0];
@@ -202,9 +200,9 @@ __global__ __launch_bounds__(BLOCK) void k_flux_march(const T* __restrict__ Pc, 
 #pragma unroll
         for (int v = 0; v < 9; ++v) {
             T qd = Pc[v * d.sv + pf];
-            T sn = mc_slope(qb[v], qc[v], qd);   // slope of cell f
-            qL[v] = qb[v] + half * sc[v];        // cell f-1, right face
-            qR[v] = qc[v] - half * sn;           // cell f, left face
+            T sn = mc_hslope(qb[v], qc[v], qd);   // half slope of cell f
+            qL[v] = qb[v] + sc[v];                // cell f-1, right face
+            qR[v] = qc[v] - sn;                   // cell f, left face
             sc[v] = sn;
             qb[v] = qc[v];
             qc[v] = qd;
@@ -608,7 +606,6 @@ template <int KIND, int PLANE, typename T>
 __device__ __forceinline__ void tile_face(const T* sP, int dir, int base, int stride, double fx, double fy,
                                           double fz, long long fglob, const Dev& d, T* sF, int nslot, int slot)
 {
-    const T half = T(0.5);
     int vo[9];   // variable v of the cycled frame is variable vo[v] of the grid
     vo[0] = 0;
     vo[1] = 1;
@@ -624,8 +621,8 @@ __device__ __forceinline__ void tile_face(const T* sP, int dir, int base, int st
     for (int v = 0; v < 9; ++v) {
         const T* p = sP + vo[v] * PLANE + base;
         const T q0 = p[0], q1 = p[stride], q2 = p[2 * stride], q3 = p[3 * stride];
-        qL[v] = q1 + half * mc_slope(q0, q1, q2);
-        qR[v] = q2 - half * mc_slope(q1, q2, q3);
+        qL[v] = q1 + mc_hslope(q0, q1, q2);
+        qR[v] = q2 - mc_hslope(q1, q2, q3);
     }
     Geo g;
     if (KIND == STORED) {
@@ -676,7 +673,6 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
     const long long col = (long long)(j + d.g[1]) * d.px + i + d.g[0] + (long long)d.g[2] * st;
     const double x = d.lo[0] + (i + 0.5) * d.dx[0];
     const double y = d.lo[1] + (j + 0.5) * d.dx[1];
-    const T half = T(0.5);
     int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
 
     // The cell this thread stages from HBM each plane: a halo position
@@ -711,7 +707,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
     const bool own_ghost = !act && ((ax && i < nx + 2 && j < ny) || (ay && i < nx && j < ny + 2));
     const int oslot = (ty + 2) * G::W + tx + 2;
 
-    // z window of the thread's column: qb = q_k, qc = q_(k+1), sc = slope of
+    // z window of the thread's column: qb = q_k, qc = q_(k+1), sc = half slope of
     // cell k, Fp = the flux through the face below cell k
     T qb[9], qc[9], sc[9], Fp[9];
     if (act) {
@@ -727,10 +723,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
 #pragma unroll
         for (int v = 0; v < 9; ++v) {
             T qd = Pc[v * d.sv + base + 3 * st];
-            T s0 = mc_slope(qa[v], qb[v], qc[v]);   // cell k0-1
-            T s1 = mc_slope(qb[v], qc[v], qd);      // cell k0
-            qL[v] = qb[v] + half * s0;
-            qR[v] = qc[v] - half * s1;
+            T s0 = mc_hslope(qa[v], qb[v], qc[v]);   // cell k0-1
+            T s1 = mc_hslope(qb[v], qc[v], qd);      // cell k0
+            qL[v] = qb[v] + s0;
+            qR[v] = qc[v] - s1;
             sc[v] = s1;
             qb[v] = qc[v];
             qc[v] = qd;
@@ -826,10 +822,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 2)))
         T q[9], qL[9], qR[9], Fc[9];
 #pragma unroll
         for (int v = 0; v < 9; ++v) {
-            T sn = mc_slope(qb[v], qc[v], qd[v]);   // cell k+1
+            T sn = mc_hslope(qb[v], qc[v], qd[v]);   // cell k+1
             q[v] = qb[v];
-            qL[v] = qb[v] + half * sc[v];
-            qR[v] = qc[v] - half * sn;
+            qL[v] = qb[v] + sc[v];
+            qR[v] = qc[v] - sn;
             sc[v] = sn;
             qb[v] = qc[v];
             qc[v] = qd[v];
@@ -1139,7 +1135,6 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
     double* Ub = U + 9 * pr.off;
     T* Usb = Us + 9 * pr.off;
     const Geo geo = geo_at<FLAT>(d, 0.0, 0.0, 0.0);
-    const T half = T(0.5);
     int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
     for (int step = 0; step < nsteps; ++step) {
         for (int s = 0; s < ns; ++s) {
@@ -1153,8 +1148,8 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
                 for (int v = 0; v < 9; ++v) {
                     const T* r = cur + v * pitch + c0;
                     const T q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3];
-                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
-                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                    qL[v] = q1 + mc_hslope(q0, q1, q2);
+                    qR[v] = q2 - mc_hslope(q1, q2, q3);
                 }
                 face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fp);
             }
@@ -1165,8 +1160,8 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
                     const T* r = cur + v * pitch + c + 1;      // cells c-1 .. c+2
                     const T q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3];
                     q[v] = q1;
-                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
-                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                    qL[v] = q1 + mc_hslope(q0, q1, q2);
+                    qR[v] = q2 - mc_hslope(q1, q2, q3);
                 }
                 face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
                 double R[9];
@@ -1361,7 +1356,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         T* cur = Prow + pr.poff;
         T* nxt = Pnext + pr.poff;
         const Geo geo = geo_at<FLAT>(d, 0.0, 0.0, 0.0);
-        const T half = T(0.5);
         for (int i = 0; i < nsub && !stalled; ++i) {
             if (i > 0 && !split_wait(flags, pt.left, pt.right, base + i, &s_ok)) {
                 stalled = true;
@@ -1379,8 +1373,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
                 for (int v = 0; v < 9; ++v) {
                     const T* r = cur + v * pitch;
                     const T q0 = rd(r, c0 - 2), q1 = rd(r, c0 - 1), q2 = rd(r, c0), q3 = rd(r, c0 + 1);
-                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
-                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                    qL[v] = q1 + mc_hslope(q0, q1, q2);
+                    qR[v] = q2 - mc_hslope(q1, q2, q3);
                 }
                 face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fp);
             }
@@ -1391,8 +1385,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void
                     const T* r = cur + v * pitch;              // cells c-1 .. c+2
                     const T q0 = rd(r, c - 1), q1 = rd(r, c), q2 = rd(r, c + 1), q3 = rd(r, c + 2);
                     q[v] = q1;
-                    qL[v] = q1 + half * mc_slope(q0, q1, q2);
-                    qR[v] = q2 - half * mc_slope(q1, q2, q3);
+                    qL[v] = q1 + mc_hslope(q0, q1, q2);
+                    qR[v] = q2 - mc_hslope(q1, q2, q3);
                 }
                 face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
                 double R[9];
