@@ -1324,9 +1324,18 @@ __device__ __forceinline__ S uniform_load(const S* p)
 // Workgroup w runs the parts runs[w].x .. runs[w].x + runs[w].y - 1 one
 // after another: a segment of a split problem (a run of one), or several
 // small problems packed whole (no neighbours, so no waits).  The register
-// budget of 3 waves per SIMD (some FP64 spills) keeps more parts resident.
+// budget of 3 waves per SIMD with a double cache, 4 with a float cache (some
+// spills either way: measured faster than fewer, larger-register waves)
+// keeps more parts resident.
+template <typename T>
+constexpr int split_waves()
+{
+    return sizeof(T) == sizeof(double) ? 3 : 4;
+}
+
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_batch_split(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(split_waves<T>(), split_waves<T>())))
+void k_batch_split(
     BatchProb* __restrict__ probs, const BatchPart* __restrict__ parts, const int2* __restrict__ runs, int* flags,
     double* __restrict__ U, T* __restrict__ Us, T* Prow, T* Pnext, Dev d, int ns, int max_steps,
     unsigned long long* __restrict__ cnt, unsigned long long* __restrict__ span)
