@@ -257,19 +257,22 @@ def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
     and grmhd_step_adjoint_recorded, the reverse sweep of a recorded step.
     Also the wall time of a whole gradient (forward evolution with checkpoints
     every `every` steps, then the checkpointed reverse sweep, with the tape of
-    recorded steps and without it) over that of the forward evolution alone."""
+    recorded steps and without it) over that of the forward evolution alone,
+    and with a tape as long as the run (every step recorded by the forward
+    pass, nothing recomputed: memory for compute)."""
     import numpy as np
     import torch
     from paper_1102_5202_amd.adjoint import evolve
     s = grmhd.solver_for(w, device=dev, adjoint=True)
     st = grmhd.solver_for(w, device=dev, adjoint=True, tape_steps=every)
+    sf = grmhd.solver_for(w, device=dev, adjoint=True, tape_steps=steps)
     P0 = torch.from_numpy(w.P).to(dev)
     tgt = (torch.from_numpy(np.ascontiguousarray(w.extra["target"])).to(dev) if "target" in w.extra
            else P0[0] * 1.01)
 
-    def gradient(solver):
+    def gradient(solver, seg=every):
         Pq = P0.clone().requires_grad_(True)
-        Pn = evolve(solver, Pq, w.dt, steps, every)
+        Pn = evolve(solver, Pq, w.dt, steps, seg)
         ((Pn[0] - tgt) ** 2).sum().backward()
         return Pq.grad
 
@@ -297,6 +300,7 @@ def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
     st.step_adjoint_recorded(0, Ub)
     g = gradient(s)                     # warm-up of every path
     gt = gradient(st)
+    gf = gradient(sf, steps)
     n = max(4, min(steps, 20))
     t_fwd = timed(lambda: s.step(U, w.dt), n)
     t_adj = timed(lambda: s.step_adjoint(U, Ub, w.dt), n)
@@ -305,6 +309,7 @@ def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
     t_evo = timed(forward_evolution, 2)
     t_grad = timed(lambda: gradient(s), 2)
     t_gradt = timed(lambda: gradient(st), 2)
+    t_gradf = timed(lambda: gradient(sf, steps), 2)
     return {"workload": w.name, "steps": steps, "checkpoint_every": every,
             "forward_step_ms": round(1e3 * t_fwd, 4), "adjoint_step_ms": round(1e3 * t_adj, 4),
             "adjoint_over_forward": round(t_adj / t_fwd, 3),
@@ -314,7 +319,11 @@ def adjoint_cost(grmhd, w, dev, steps: int, every: int = 10):
             "forward_evolution_ms": round(1e3 * t_evo, 3),
             "gradient_over_forward": round(t_gradt / t_evo, 3),
             "gradient_untaped_over_forward": round(t_grad / t_evo, 3),
-            "finite": bool(torch.isfinite(g).all().item() and torch.isfinite(gt).all().item())}
+            "gradient_full_tape_ms": round(1e3 * t_gradf, 3),
+            "gradient_full_tape_over_forward": round(t_gradf / t_evo, 3),
+            "full_tape_bytes": int(sf.workspace.numel() - s.workspace.numel()),
+            "finite": bool(torch.isfinite(g).all().item() and torch.isfinite(gt).all().item()
+                           and torch.isfinite(gf).all().item())}
 
 
 def batch_throughput(grmhd, e, dev):
