@@ -1342,6 +1342,8 @@ void k_batch_split(
 {
     const unsigned long long t_start = wall_clock64();
     __shared__ int s_ok;
+    // face fluxes of a chunk of cells, double buffered: sF[b][v][f]
+    __shared__ T sF[2][9 * NT];
     const int2 run = runs[blockIdx.x];
     int nfail = 0, natm = 0, npf = 0, nfb = 0, itmax = 0;
     bool stalled = false;
@@ -1352,14 +1354,12 @@ void k_batch_split(
         const int nsteps = min(max_steps, pr.steps - pr.done);
         const int base = pr.done * ns;   // substeps every part of the problem had completed
         const int nsub = nsteps * ns;
-        const int ch = (pt.c1 - pt.c0 + NT - 1) / NT;
-        const int c0 = min(pt.c0 + (int)threadIdx.x * ch, pt.c1), c1 = min(c0 + ch, pt.c1);
         // cells within two of either end of the segment (and those beyond it,
         // the neighbours' and the ghost images) are written and read with
         // system-scope accesses; the rest of the row with plain ones
         auto edge = [&](int x) { return x < pt.c0 + 2 || x >= pt.c1 - 2; };
         auto rd = [&](const T* r, int x) { return edge(x) ? sys_load(r + x + 2) : r[x + 2]; };
-        const bool edge_thread = c0 < c1 && (edge(c0) || edge(c1 - 1));
+        const int t = threadIdx.x;
         double* Ub = U + 9 * pr.off;
         T* Usb = Us + 9 * pr.off;
         T* cur = Prow + pr.poff;
@@ -1373,65 +1373,70 @@ void k_batch_split(
             const int s = i % ns;
             const double a = ns == 3 ? (s == 0 ? 0.0 : (s == 1 ? 0.75 : 1.0 / 3.0)) : (s == 0 ? 0.0 : 0.5);
             const double bb = ns == 3 ? (s == 0 ? 1.0 : (s == 1 ? 0.25 : 2.0 / 3.0)) : (s == 0 ? 1.0 : 0.5);
-            T Fp[9];
-            if (c0 < c1) {
-                // face c0 - 1/2 from cells c0-2 .. c0+1 (row index + 2); the first
-                // thread's two cells before c0 belong to the left neighbour
-                T qL[9], qR[9];
+            // the segment in chunks of NT - 1 cells, consecutive cells on
+            // consecutive threads (coalesced rows): thread t solves the face
+            // left of cell base + t (NT faces per chunk, the last one the
+            // right face of the chunk's last cell), then updates that cell
+            bool wrote_edge = false;
+            int chunk = 0;
+            for (int cb = pt.c0; cb < pt.c1; cb += NT - 1, ++chunk) {
+                const int cend = min(cb + NT - 1, pt.c1);   // cells [cb, cend), faces [cb, cend]
+                const int c = cb + t;
+                T* F = sF[chunk & 1];
+                T q[9];
+                if (c <= cend) {
+                    // face c - 1/2 from cells c-2 .. c+1 (row index + 2)
+                    T qL[9], qR[9], Fc[9];
     #pragma unroll
-                for (int v = 0; v < 9; ++v) {
-                    const T* r = cur + v * pitch;
-                    const T q0 = rd(r, c0 - 2), q1 = rd(r, c0 - 1), q2 = rd(r, c0), q3 = rd(r, c0 + 1);
-                    qL[v] = q1 + mc_hslope(q0, q1, q2);
-                    qR[v] = q2 - mc_hslope(q1, q2, q3);
-                }
-                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fp);
-            }
-            for (int c = c0; c < c1; ++c) {
-                T qL[9], qR[9], Fc[9], q[9];
-    #pragma unroll
-                for (int v = 0; v < 9; ++v) {
-                    const T* r = cur + v * pitch;              // cells c-1 .. c+2
-                    const T q0 = rd(r, c - 1), q1 = rd(r, c), q2 = rd(r, c + 1), q3 = rd(r, c + 2);
-                    q[v] = q1;
-                    qL[v] = q1 + mc_hslope(q0, q1, q2);
-                    qR[v] = q2 - mc_hslope(q1, q2, q3);
-                }
-                face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
-                double R[9];
-    #pragma unroll
-                for (int v = 0; v < 9; ++v) {
-                    R[v] = -((double)Fc[v] - (double)Fp[v]) * pr.idx;
-                    Fp[v] = Fc[v];
-                }
-                R[8] -= d.kappa * (double)q[8];
-                double u[9], qg[9], p[9];
-    #pragma unroll
-                for (int v = 0; v < 9; ++v) {
-                    const double un = Ub[(long long)v * n + c];
-                    const double us = s == 0 ? un : (double)Usb[(long long)v * n + c];
-                    u[v] = us + a * (un - us) + bb * (pr.dt * R[v]);
-                    qg[v] = (double)q[v];
-                }
-                int iters = 0;
-                const int fl = recover_cell(d, geo, u, qg, p, iters);
-                tally(fl, iters, nfail, natm, npf, nfb, itmax);
-                if (s == ns - 1) {
+                    for (int v = 0; v < 9; ++v) {
+                        const T* r = cur + v * pitch;
+                        const T q0 = rd(r, c - 2), q1 = rd(r, c - 1), q2 = rd(r, c), q3 = rd(r, c + 1);
+                        q[v] = q2;
+                        qL[v] = q1 + mc_hslope(q0, q1, q2);
+                        qR[v] = q2 - mc_hslope(q1, q2, q3);
+                    }
+                    face_flux<0, FLAT>(qL, qR, 0.0, 0.0, 0.0, 0, d, Fc);
     #pragma unroll
                     for (int v = 0; v < 9; ++v)
-                        Ub[(long long)v * n + c] = u[v];
-                } else {
+                        F[v * NT + t] = Fc[v];
+                }
+                __syncthreads();
+                if (c < cend) {
+                    double R[9];
     #pragma unroll
                     for (int v = 0; v < 9; ++v)
-                        Usb[(long long)v * n + c] = (T)u[v];
+                        R[v] = -((double)F[v * NT + t + 1] - (double)F[v * NT + t]) * pr.idx;
+                    R[8] -= d.kappa * (double)q[8];
+                    double u[9], qg[9], p[9];
+    #pragma unroll
+                    for (int v = 0; v < 9; ++v) {
+                        const double un = Ub[(long long)v * n + c];
+                        const double us = s == 0 ? un : (double)Usb[(long long)v * n + c];
+                        u[v] = us + a * (un - us) + bb * (pr.dt * R[v]);
+                        qg[v] = (double)q[v];
+                    }
+                    int iters = 0;
+                    const int fl = recover_cell(d, geo, u, qg, p, iters);
+                    tally(fl, iters, nfail, natm, npf, nfb, itmax);
+                    if (s == ns - 1) {
+    #pragma unroll
+                        for (int v = 0; v < 9; ++v)
+                            Ub[(long long)v * n + c] = u[v];
+                    } else {
+    #pragma unroll
+                        for (int v = 0; v < 9; ++v)
+                            Usb[(long long)v * n + c] = (T)u[v];
+                    }
+                    if (edge(c)) {
+                        row_store_sys(nxt, pitch, n, d.bc[0], c, p);
+                        wrote_edge = true;
+                    } else {
+                        row_store(nxt, pitch, n, d.bc[0], c, p);
+                    }
                 }
-                if (edge(c))
-                    row_store_sys(nxt, pitch, n, d.bc[0], c, p);
-                else
-                    row_store(nxt, pitch, n, d.bc[0], c, p);
             }
             // publish: the values other parts read have reached memory, then the count
-            if (edge_thread)
+            if (wrote_edge)
                 __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             __syncthreads();
             if (threadIdx.x == 0)
@@ -1446,7 +1451,7 @@ void k_batch_split(
             if (!split_wait(flags, pt.left, pt.right, base + nsub, &s_ok))
                 stalled = true;
             else {
-                for (int c = c0; c < c1; ++c) {
+                for (int c = pt.c0 + t; c < pt.c1; c += NT) {
                     double p[9];
     #pragma unroll
                     for (int v = 0; v < 9; ++v)
