@@ -1233,9 +1233,11 @@ __global__ __launch_bounds__(NT) void k_batch_evolve(BatchProb* __restrict__ pro
 }
 
 // k_batch_split: a problem's cells divided among several workgroups (parts)
-// that run at the same time, each part marching its segment as
-// k_batch_evolve does with the rows in HBM.  The two cells beside a
-// segment's ends come from the neighbouring parts through the rows.  Parts
+// that run at the same time, the rows in HBM.  A part walks its segment in
+// chunks of NT - 1 cells, one cell per thread (consecutive cells on
+// consecutive threads, so that row accesses are coalesced), the chunk's face
+// fluxes exchanged through LDS.  The two cells beside a segment's ends come
+// from the neighbouring parts through the rows.  Parts
 // may sit on different XCDs, whose L2 caches are not kept coherent for this
 // memory, so the values that cross parts (each segment's two end cells at
 // either end and their ghost images) are stored and loaded with system-scope
