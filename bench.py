@@ -412,14 +412,19 @@ def cpu_baseline(w, small):
 
 def batch_accuracy(grmhd, e, dev, nsteps: int = None):
     """Relative L1 distance of the mixed-precision ensemble from the FP64 one
-    after every problem ran to its end, per problem (the largest over all 9
-    conserved variables, vector components normalised as in accuracy()):
-    median, 90th percentile and maximum over the problems."""
+    after every problem ran to its end (both with the split placement where
+    the device allows it), per problem (the largest over all 9 conserved
+    variables, vector components normalised as in accuracy()): median, 90th
+    percentile and maximum over the problems."""
     import numpy as np
     import torch
     res = {}
     for prec in ("fp64", "mixed"):
         s = grmhd.batch_for(e, device=dev, precision=prec)
+        try:
+            s.set_shape(256, 2)       # the placement the throughput leg measures
+        except RuntimeError:
+            pass
         U = s.cons(s.pack(e.P))
         s.evolve(U)
         torch.cuda.synchronize()
