@@ -39,11 +39,18 @@ def _oracle_problem(orc, e, b):
     return U.reshape(9, -1), P.reshape(9, -1)
 
 
-@pytest.mark.parametrize("bc", [WL.OUTFLOW, WL.PERIODIC])
-def test_batch_matches_oracle(G, orc, bc):
+@pytest.mark.parametrize("bc,split", [(WL.OUTFLOW, False), (WL.PERIODIC, False), (WL.OUTFLOW, True),
+                                      (WL.PERIODIC, True)])
+def test_batch_matches_oracle(G, orc, bc, split):
+    """Every problem against the oracle run alone; with split, the work
+    spread over co-resident workgroups (the longer problems divided into
+    parts whose end cells cross between workgroups, periodic ends joining a
+    problem's first and last part)."""
     e = WL.config5(nprob=12, nmin=20, nmax=150, k=1)
     e.bc = bc
     s = G.batch_for(e, device=DEV)
+    if split:
+        s.set_shape(256, 2)
     P0 = s.pack(e.P)
     U = s.cons(P0)
     s.evolve(U)
