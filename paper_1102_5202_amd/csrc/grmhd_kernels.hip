@@ -577,8 +577,8 @@ __global__ __launch_bounds__(BLOCK) void k_update(const T* __restrict__ Fx, cons
 //   (2) solves the tile's x faces (TX + 1 per row) and y faces (TY + 1 per
 //       column) from LDS into LDS, one face of each axis per thread plus the
 //       tile's last row and column of faces;
-//   (3) per cell, as k_update_zmarch: the z face above the cell from the
-//       thread's register window (one new cell and one slope per plane), the
+//   (3) per cell: the z face above the cell from the thread's register
+//       window (one new cell and one half slope per plane), the
 //       flux differences of the three axes, the sources, the Runge-Kutta
 //       combination and the recovery, the new primitives (with their ghost
 //       images) going to another cache.
