@@ -250,3 +250,24 @@ def test_batch_split_packs_small_problems(G, orc):
         Ur, _ = _oracle_problem(orc, e, b)
         err = orc.parity_error(Us[b].numpy(), Ur)
         assert np.all(err[:8] <= 1e-10), (b, err)
+
+
+def test_batch_split_multichunk_matches_oracle(G, orc):
+    """The full ensemble with the split placement: a problem packed whole of
+    about 1,000 cells and one split into parts of several hundred cells both
+    walk their cells in several chunks of 255 per substep; each matches the
+    oracle run alone at the FP64 bar."""
+    e = WL.config5()
+    s = G.batch_for(e, device=DEV)
+    s.set_shape(256, 2)
+    U = s.cons(s.pack(e.P))
+    s.evolve(U)
+    st = s.status()
+    Us = s.unpack(U.cpu())
+    n = np.array(e.n)
+    for target in (1000, 1500):
+        b = int(np.argmin(np.abs(n - target)))
+        Ur, _ = _oracle_problem(orc, e, b)
+        err = orc.parity_error(Us[b].numpy(), Ur)
+        say("split, problem", b, "n", e.n[b], "rel-L1", err.max(), st)
+        assert np.all(err <= 1e-10), (b, err)
