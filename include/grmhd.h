@@ -157,7 +157,8 @@ typedef struct {
     int reconstruction;    /* grmhd_reconstruction: MC (2 ghost layers) or PPM (3) */
     int divergence;        /* grmhd_divergence: hyperbolic cleaning or flux-CT */
     int timing;            /* nonzero: time every kernel launch with HIP events */
-    int adjoint;           /* nonzero: reserve the workspace of the adjoint calls (FP64 only) */
+    int adjoint;           /* nonzero: reserve the workspace of the adjoint calls (FP64 only,
+                              at most 2^30 cells) */
     int tape_steps;        /* with adjoint: slots of recorded steps (grmhd_step_record), 0..4096 */
     void *workspace;       /* device memory, >= grmhd_workspace_bytes(), 256-byte aligned */
     size_t workspace_bytes;

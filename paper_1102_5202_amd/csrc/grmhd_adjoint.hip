@@ -39,6 +39,17 @@ __device__ __forceinline__ long long ghosted(const Dev& d, int i, int j, int k)
     return ((long long)(k + d.g[2]) * d.py + (j + d.g[1])) * d.px + (i + d.g[0]);
 }
 
+// Interior cell c (x fastest) -> (i, j, k).  The adjoint contexts hold at
+// most 2^30 cells, so 32-bit arithmetic suffices.
+__device__ __forceinline__ void cell_ijk(const Dev& d, long long c, int& i, int& j, int& k)
+{
+    const unsigned cu = (unsigned)c, n0 = d.n[0], n1 = d.n[1];
+    const unsigned t = cu / n0, kk = t / n1;
+    i = (int)(cu - t * n0);
+    j = (int)(t - kk * n1);
+    k = (int)kk;
+}
+
 __device__ __forceinline__ double3 centre(const Dev& d, int i, int j, int k)
 {
     return make_double3(d.lo[0] + (i + 0.5) * d.dx[0], d.lo[1] + (j + 0.5) * d.dx[1],
@@ -151,11 +162,10 @@ __device__ __forceinline__ void adj_face(long long f, const double* __restrict__
         return;
     int m[3] = {d.n[0], d.n[1], d.n[2]};
     m[D] += 1;
-    int fi[3];
-    fi[0] = (int)(f % m[0]);
-    const long long t = f / m[0];
-    fi[1] = (int)(t % m[1]);
-    fi[2] = (int)(t / m[1]);
+    // f < nf < 2^32 (the launch checks it): 32-bit index arithmetic
+    const unsigned fu = (unsigned)f, m0 = m[0], m1 = m[1];
+    const unsigned t = fu / m0, k = t / m1;
+    const int fi[3] = {(int)(fu - t * m0), (int)(t - k * m1), (int)k};
     const int fD = fi[D];
     double Fb[9];
 #pragma unroll
@@ -237,18 +247,19 @@ __device__ __forceinline__ double gather_pos_v(const Dev& d, const double* __res
     const long long nf = d.nf[D];
     int fm[3] = {d.n[0], d.n[1], d.n[2]};
     fm[D] += 1;
-    auto face = [&](int ff) -> long long {
-        int fi[3] = {ci[0], ci[1], ci[2]};
-        fi[D] = ff;
-        return fi[0] + (long long)fm[0] * (fi[1] + (long long)fm[1] * fi[2]);
-    };
+    // face i along D (i may lie outside 0..n: only used where it exists);
+    // neighbouring faces along D are sf apart
+    const long long sf = D == 0 ? 1 : (D == 1 ? (long long)fm[0] : (long long)fm[0] * fm[1]);
+    int fi0[3] = {ci[0], ci[1], ci[2]};
+    fi0[D] = 0;
+    const long long fb = fi0[0] + (long long)fm[0] * (fi0[1] + (long long)fm[1] * fi0[2]) + (long long)i * sf;
     const long long st = D == 0 ? 1 : (D == 1 ? (long long)d.px : (long long)d.px * d.py);
     const long long pc = ghosted(d, ci[0], ci[1], ci[2]);
     const bool has_lo = i >= 0 && i <= n;            // face i exists
     const bool has_hi = i + 1 >= 0 && i + 1 <= n;    // face i+1 exists
-    const long long f_lo = has_lo ? face(i) : 0, f_hi = has_hi ? face(i + 1) : 0;
-    const long long f_lm = (i - 1 >= 0 && i - 1 <= n) ? face(i - 1) : -1;   // face i-1
-    const long long f_hp = (i + 2 >= 0 && i + 2 <= n) ? face(i + 2) : -1;   // face i+2
+    const long long f_lo = has_lo ? fb : 0, f_hi = has_hi ? fb + sf : 0;
+    const long long f_lm = (i - 1 >= 0 && i - 1 <= n) ? fb - sf : -1;   // face i-1
+    const long long f_hp = (i + 2 >= 0 && i + 2 <= n) ? fb + 2 * sf : -1;   // face i+2
     const double* Fl = FB + v * nf;          // left-state cotangents
     const double* Fr = FB + (9 + v) * nf;    // right-state cotangents
     // every load issued up front (absent faces read face 0, stencil taps
@@ -423,10 +434,8 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_rec(double* __restrict__ Ub, con
     const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
     if (c >= d.N)
         return;
-    const int i = (int)(c % d.n[0]);
-    const long long t = c / d.n[0];
-    const int j = (int)(t % d.n[1]);
-    const int k = (int)(t / d.n[1]);
+    int i, j, k;
+    cell_ijk(d, c, i, j, k);
     const long long pc = ghosted(d, i, j, k);
     double q[9], ub[9], ut[9];
     const double pb[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -446,6 +455,12 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_rec(double* __restrict__ Ub, con
 
 // Lines along axis D (cells of the other two axes) and the line of a cell.
 template <int D>
+__device__ __forceinline__ long long lines_of(const Dev& d)
+{
+    return D == 0 ? (long long)d.n[1] * d.n[2] : (D == 1 ? (long long)d.n[0] * d.n[2] : (long long)d.n[0] * d.n[1]);
+}
+
+template <int D>
 __device__ __forceinline__ long long line_of(const Dev& d, const int* ci)
 {
     return D == 0 ? ci[1] + (long long)d.n[1] * ci[2]
@@ -459,16 +474,17 @@ __device__ __forceinline__ long long line_of(const Dev& d, const int* ci)
 template <int D>
 __device__ __forceinline__ void gather_ghost(const Dev& d, const double* __restrict__ Pc,
                                              const double* __restrict__ FB, double* __restrict__ G,
-                                             long long t, long long lines, int v)
+                                             unsigned t, unsigned lines, int v)
 {
     const int slot = (int)(t / lines);
-    const long long line = t - slot * lines;
+    const unsigned line = t - slot * lines;
     int ci[3];
     const int a = D == 0 ? 1 : 0, b = D == 2 ? 1 : 2;   // the two other axes
-    ci[a] = (int)(line % d.n[a]);
-    ci[b] = (int)(line / d.n[a]);
+    const unsigned na = d.n[a], lb = line / na;
+    ci[a] = (int)(line - lb * na);
+    ci[b] = (int)lb;
     ci[D] = slot < 2 ? slot - 2 : d.n[D] + slot - 2;
-    G[(v * 4 + slot) * lines + line] = gather_pos_v<D>(d, Pc, FB, ci, v);
+    G[(long long)(v * 4 + slot) * lines + line] = gather_pos_v<D>(d, Pc, FB, ci, v);
 }
 
 // One thread per position and primitive variable v (v slowest, positions
@@ -485,16 +501,16 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
                                                         const double* __restrict__ FB2,
                                                         double* __restrict__ MU, double* __restrict__ G0,
                                                         double* __restrict__ G1, double* __restrict__ G2, Dev d,
-                                                        long long npos)
+                                                        unsigned npos)
 {
-    const long long g = (long long)blockIdx.x * ABLOCK + threadIdx.x;
-    if (g >= 9 * npos)
+    unsigned t = blockIdx.x * ABLOCK + threadIdx.x;
+    if (t >= npos)
         return;
-    const int v = (int)(g / npos);
-    long long t = g - v * npos;
-    if (t < d.N) {
-        const long long r = t / d.n[0];
-        const int ci[3] = {(int)(t % d.n[0]), (int)(r % d.n[1]), (int)(r / d.n[1])};
+    const int v = blockIdx.y;
+    if (t < (unsigned)d.N) {
+        const unsigned n0 = d.n[0], n1 = d.n[1];
+        const unsigned r = t / n0, k = r / n1;
+        const int ci[3] = {(int)(t - r * n0), (int)(r - k * n1), (int)k};
         double m = 0.0;
         if (d.act[0])
             m += gather_pos_v<0>(d, Pc, FB0, ci, v);
@@ -505,9 +521,9 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
         MU[v * d.N + t] = m;
         return;
     }
-    t -= d.N;
+    t -= (unsigned)d.N;
     if (d.act[0]) {
-        const long long lines = d.N / d.n[0];
+        const unsigned lines = (unsigned)lines_of<0>(d);
         if (t < 4 * lines) {
             gather_ghost<0>(d, Pc, FB0, G0, t, lines, v);
             return;
@@ -515,7 +531,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
         t -= 4 * lines;
     }
     if (d.act[1]) {
-        const long long lines = d.N / d.n[1];
+        const unsigned lines = (unsigned)lines_of<1>(d);
         if (t < 4 * lines) {
             gather_ghost<1>(d, Pc, FB1, G1, t, lines, v);
             return;
@@ -523,7 +539,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_gather(const double* __restrict_
         t -= 4 * lines;
     }
     if (d.act[2]) {
-        const long long lines = d.N / d.n[2];
+        const unsigned lines = (unsigned)lines_of<2>(d);
         if (t < 4 * lines)
             gather_ghost<2>(d, Pc, FB2, G2, t, lines, v);
     }
@@ -536,7 +552,7 @@ template <int D>
 __device__ __forceinline__ void fold_ghosts(const Dev& d, const double* __restrict__ G, const int* ci, double* pb)
 {
     const int i = ci[D], n = d.n[D];
-    const long long lines = d.N / n, line = line_of<D>(d, ci);
+    const long long lines = lines_of<D>(d), line = line_of<D>(d, ci);
     int sl[2], ns = 0;
     if (d.bc[D] == 0) {   // periodic: position n+i, or i-n
         if (i < 2)
@@ -577,10 +593,8 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_cell(const double* __restrict__ 
     const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
     if (c >= d.N)
         return;
-    const int i = (int)(c % d.n[0]);
-    const long long t = c / d.n[0];
-    const int j = (int)(t % d.n[1]);
-    const int k = (int)(t / d.n[1]);
+    int i, j, k;
+    cell_ijk(d, c, i, j, k);
     const long long pc = ghosted(d, i, j, k);
     const bool any = d.act[0] || d.act[1] || d.act[2];
     double pb[9], q[9], rb[9];
@@ -637,10 +651,8 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_final(const double* __restrict__
     const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
     if (c >= d.N)
         return;
-    const int i = (int)(c % d.n[0]);
-    const long long t = c / d.n[0];
-    const int j = (int)(t % d.n[1]);
-    const int k = (int)(t / d.n[1]);
+    int i, j, k;
+    cell_ijk(d, c, i, j, k);
     const long long pc = ghosted(d, i, j, k);
     double q[9], pb[9], ut[9];
 #pragma unroll
@@ -673,10 +685,8 @@ __global__ __launch_bounds__(ABLOCK) void k_adj_cons(const double* __restrict__ 
     const long long c = (long long)blockIdx.x * ABLOCK + threadIdx.x;
     if (c >= d.N)
         return;
-    const int i = (int)(c % d.n[0]);
-    const long long t = c / d.n[0];
-    const int j = (int)(t % d.n[1]);
-    const int k = (int)(t / d.n[1]);
+    int i, j, k;
+    cell_ijk(d, c, i, j, k);
     double q[9], ub[9];
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
@@ -720,8 +730,10 @@ hipError_t launch_adj_gather(const double* Pc, const double* const* FB, double* 
     for (int a = 0; a < 3; ++a)
         if (d.act[a])
             npos += 4 * (d.N / d.n[a]);
-    hipLaunchKernelGGL(k_adj_gather, dim3(ablocks(9 * npos)), dim3(ABLOCK), 0, s, Pc, FB[0], FB[1], FB[2], MU, G[0],
-                       G[1], G[2], d, npos);
+    if (npos > 0xffffffffLL - ABLOCK)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_gather, dim3(ablocks(npos), 9), dim3(ABLOCK), 0, s, Pc, FB[0], FB[1], FB[2], MU, G[0],
+                       G[1], G[2], d, (unsigned)npos);
     return hipGetLastError();
 }
 
@@ -742,8 +754,11 @@ hipError_t launch_adj_face(int kind, const double* Pc, const double* Rb, double*
                            hipStream_t s)
 {
     unsigned nb[3];
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
+        if (d.nf[a] > 0xffffffffLL - ABLOCK)
+            return hipErrorInvalidValue;
         nb[a] = d.act[a] ? ablocks(d.nf[a]) : 0;
+    }
     const unsigned total = nb[0] + nb[1] + nb[2];
     if (total == 0)
         return hipSuccess;

@@ -175,7 +175,8 @@ int ghost_width(const grmhd_opts* o)
 }
 
 // Options that fit the grid: PPM needs 3 cells on every active axis (the
-// periodic images of the ghost layers) and has no adjoint.
+// periodic images of the ghost layers) and has no adjoint; an adjoint context
+// holds at most 2^30 cells.
 bool opts_fit(const grmhd_grid* g, const grmhd_opts* o)
 {
     if (!o)
@@ -185,6 +186,9 @@ bool opts_fit(const grmhd_grid* g, const grmhd_opts* o)
     if (o->divergence != GRMHD_DIV_CLEANING && o->divergence != GRMHD_DIV_FLUXCT)
         return false;
     if (o->divergence == GRMHD_DIV_FLUXCT && o->adjoint)
+        return false;
+    // the adjoint kernels index cells, faces and ghost positions in 32 bits
+    if (o->adjoint && (long long)g->n[0] * g->n[1] * g->n[2] > (1LL << 30))
         return false;
     if (o->reconstruction == GRMHD_RECON_PPM) {
         if (o->adjoint)

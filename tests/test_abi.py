@@ -138,6 +138,27 @@ def test_adjoint_workspace(lib):
     assert L.grmhd_free(ctx) == 0
 
 
+def test_adjoint_cell_limit(lib):
+    """The adjoint kernels index cells, faces and ghost positions in 32 bits:
+    an adjoint context holds at most 2^30 cells (a forward one more)."""
+    L = lib.load()
+    m = lib.Metric(lib.FLAT, 0, 0.0, 1.0)
+    e = lib.Eos(0, 5.0 / 3.0, 0.0)
+    for n, fits in (((1024, 1024, 1024), True), ((1024, 1024, 1025), False)):
+        g = lib.make_grid(n, (0, 0, 0), (1, 1, 1), (0, 0, 0))
+        o = lib.Opts()
+        fwd = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        o.adjoint = 1
+        adj = L.grmhd_workspace_bytes(C.byref(g), C.byref(o))
+        assert fwd > 0
+        assert (adj > fwd) if fits else (adj == 0)
+        o = lib.Opts(3, 0, 1.0, 1.0, 1e-12, 1e-12, 1e-12, 50, 0, 0, 0, 0, 1, 0, None, 0)   # FP64, adjoint
+        ctx = C.c_void_p()
+        # past the limit the grid is refused before the (missing) workspace is looked at
+        rc = L.grmhd_init(C.byref(ctx), C.byref(m), C.byref(g), C.byref(e), C.byref(o))
+        assert rc == (-2 if fits else -1)
+
+
 def test_tape_workspace_and_validation(lib):
     """Tape slots of recorded steps: (rk+1) ghosted FP64 caches and rk flag
     bytes per cell per slot; slot and state checks happen on the host."""
