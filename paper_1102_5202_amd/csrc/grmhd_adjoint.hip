@@ -487,8 +487,9 @@ __device__ __forceinline__ void gather_ghost(const Dev& d, const double* __restr
     G[(long long)(v * 4 + slot) * lines + line] = gather_pos_v<D>(d, Pc, FB, ci, v);
 }
 
-// One thread per position and primitive variable v (v slowest, positions
-// fastest, so a wave reads consecutive cells of one variable): positions
+// One thread per position and primitive variable v (v the grid's y index,
+// positions along x, so a wave reads consecutive cells of one variable; the
+// positions, fewer than 2^32, are counted in 32 bits): positions
 // [0, N) are the interior cells, whose cotangent from the face-state
 // cotangents of every active axis (FB0/1/2, 18 rows of nf values each)
 // pulled back through the MC reconstruction goes to MU (dense [9][N]); then,
