@@ -194,7 +194,8 @@ typedef enum {
 typedef struct grmhd_ctx grmhd_ctx;
 
 /* Bytes of device workspace a context needs for this grid and these options.
- * Returns 0 for an invalid grid. */
+ * Returns 0 for an invalid grid or options that do not fit it (PPM on an
+ * axis of fewer than 3 cells, an adjoint context of more than 2^30 cells). */
 size_t grmhd_workspace_bytes(const grmhd_grid *grid, const grmhd_opts *opts);
 
 /* Create a context (host-only; no device work, no allocation of device
