@@ -194,8 +194,8 @@ __device__ __forceinline__ void adj_face(long long f, const double* __restrict__
     for (int v = 0; v < 9; ++v) {
         const double* p = Pc + v * d.sv + base;
         const double q0 = p[0], q1 = p[st], q2 = p[2 * st], q3 = p[3 * st];
-        qL[v] = q1 + 0.5 * mc_slope(q0, q1, q2);
-        qR[v] = q2 - 0.5 * mc_slope(q1, q2, q3);
+        qL[v] = q1 + mc_hslope(q0, q1, q2);   // half the MC slope, as the forward kernels take it
+        qR[v] = q2 - mc_hslope(q1, q2, q3);
     }
     double pos[3];
 #pragma unroll
