@@ -167,23 +167,24 @@ __device__ __forceinline__ void adj_face(long long f, const double* __restrict__
     const unsigned t = fu / m0, k = t / m1;
     const int fi[3] = {(int)(fu - t * m0), (int)(t - k * m1), (int)k};
     const int fD = fi[D];
+    // The RHS cotangents of the two cells beside the face are loaded whether
+    // or not the cells exist (indices clamped into the domain), so that these
+    // loads are in flight together with the stencil's; a cell outside the
+    // domain then contributes zero.
+    const bool hi_in = fD < d.n[D], lo_in = fD > 0;
+    int ch[3] = {fi[0], fi[1], fi[2]}, cl[3] = {fi[0], fi[1], fi[2]};
+    ch[D] = hi_in ? fD : fD - 1;
+    cl[D] = lo_in ? fD - 1 : fD;
+    const long long chi = ch[0] + (long long)d.n[0] * (ch[1] + (long long)d.n[1] * ch[2]);
+    const long long clo = cl[0] + (long long)d.n[0] * (cl[1] + (long long)d.n[1] * cl[2]);
     double Fb[9];
 #pragma unroll
-    for (int v = 0; v < 9; ++v)
-        Fb[v] = 0.0;
-    if (fD < d.n[D]) {
-        const long long c = fi[0] + (long long)d.n[0] * (fi[1] + (long long)d.n[1] * fi[2]);
-#pragma unroll
-        for (int v = 0; v < 9; ++v)
-            Fb[v] += Rb[v * d.N + c] * d.idx[D];
-    }
-    if (fD > 0) {
-        int ci[3] = {fi[0], fi[1], fi[2]};
-        ci[D] -= 1;
-        const long long c = ci[0] + (long long)d.n[0] * (ci[1] + (long long)d.n[1] * ci[2]);
-#pragma unroll
-        for (int v = 0; v < 9; ++v)
-            Fb[v] -= Rb[v * d.N + c] * d.idx[D];
+    for (int v = 0; v < 9; ++v) {
+        const double rh = Rb[v * d.N + chi], rl = Rb[v * d.N + clo];
+        double f = 0.0;
+        f += (hi_in ? rh : 0.0) * d.idx[D];
+        f -= (lo_in ? rl : 0.0) * d.idx[D];
+        Fb[v] = f;
     }
     int bi[3] = {fi[0], fi[1], fi[2]};
     bi[D] -= 2;
@@ -213,11 +214,13 @@ __device__ __forceinline__ void adj_face(long long f, const double* __restrict__
 // The faces of every active axis in one launch: workgroups [0, nb0) take x
 // faces, the next nb1 y faces, the rest z faces (one launch instead of three
 // leaves one partly filled last wave of workgroups instead of three).
+//
+// Two waves per SIMD are asked for: the curved-metric instance, with every
+// load of a face issued up front, would otherwise take 262 registers.
 template <int KIND>
-__global__ __launch_bounds__(ABLOCK) void k_adj_face(const double* __restrict__ Pc,
-                                                      const double* __restrict__ Rb,
-                                                      double* __restrict__ FB0, double* __restrict__ FB1,
-                                                      double* __restrict__ FB2, Dev d, unsigned nb0, unsigned nb1)
+__global__ __launch_bounds__(ABLOCK) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_adj_face(const double* __restrict__ Pc, const double* __restrict__ Rb, double* __restrict__ FB0,
+                double* __restrict__ FB1, double* __restrict__ FB2, Dev d, unsigned nb0, unsigned nb1)
 {
     unsigned b = blockIdx.x;
     if (b < nb0) {
